@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against closed forms, library routines, invariants
+and brute force.  None of these calls the HIP library."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.ndimage
+
+import ksinputs as ki
+from oracle import cg as ocg
+from oracle import cnn as ocnn
+from oracle import hamiltonian as oh
+from oracle import linalg as ola
+from oracle import lobpcg as olob
+from oracle import precond as opc
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def tiny_cfg(n=10, L=7.0, lmax=1, positions=((0.1, 0.2, 0.3), (0.6, 0.55, 0.45)), nb=6, **kw):
+    return ki.custom_config("tiny", L, n, positions, nb, lmax=lmax, rc=0.61, **kw)
+
+
+def dense_h_from_generator(cell):
+    """Dense H built independently of the oracle: numpy.fft for T, the
+    generator's own potential and projector tables."""
+    n, L = cell.n, cell.L
+    Ng = n ** 3
+    Tk = oh.kinetic_diag(n, L)  # closed form |G|^2/2 (also pinned below)
+    eye = np.eye(Ng)
+    T = np.array([np.fft.ifftn(np.fft.fftn(eye[i].reshape(n, n, n)) * Tk).ravel() for i in range(Ng)]).T
+    H = T + np.diag(cell.V)
+    for a in range(cell.natoms):
+        s0, s1 = cell.atom_supp_ptr[a], cell.atom_supp_ptr[a + 1]
+        idx = cell.supp_idx[s0:s1]
+        ns = s1 - s0
+        for j in range(cell.atom_proj_ptr[a], cell.atom_proj_ptr[a + 1]):
+            jj = j - cell.atom_proj_ptr[a]
+            b = np.zeros(Ng)
+            b[idx] = cell.beta[cell.beta_ptr[a] + jj * ns: cell.beta_ptr[a] + (jj + 1) * ns]
+            H += cell.D[j] * np.outer(b, b)
+    return 0.5 * (H + H.conj().T)
+
+
+# ---------------------------------------------------------------- P3, P2, P1
+
+
+@pytest.mark.parametrize("n", [5, 8, 12, 16])
+def test_naive_dft_matches_numpy_fft(n):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((2, n, n, n)) + 1j * rng.standard_normal((2, n, n, n))
+    f = oh.dft3(a, n)
+    ref = np.fft.fftn(a, axes=(1, 2, 3))
+    assert np.abs(f - ref).max() <= 1e-13 * np.abs(ref).max()
+    b = oh.dft3(f, n, inverse=True)
+    assert np.abs(b - a).max() <= 1e-13 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("n,L", [(8, 6.74), (9, 5.0), (16, 6.74)])
+def test_plane_wave_is_kinetic_eigenvector(n, L):
+    x = np.arange(n) * L / n
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    for m in [(0, 0, 0), (1, 0, 0), (1, -2, 3), (n // 2, 1, -1), (-(n // 2), 0, 2)]:
+        g = [2 * math.pi / L * mi for mi in m]
+        pw = np.exp(1j * (g[0] * X + g[1] * Y + g[2] * Z)).ravel()[None]
+        mw = [((mi + n // 2) % n) - n // 2 if n % 2 == 0 else ((mi + (n - 1) // 2) % n) - (n - 1) // 2 for mi in m]
+        expect = 0.5 * sum((2 * math.pi / L * mi) ** 2 for mi in mw)
+        tpw = oh.apply_t(pw, n, L)
+        assert np.abs(tpw - expect * pw).max() <= 1e-11 * max(1.0, expect)
+
+
+def test_free_electron_spectrum_closed_form():
+    # V = 0, no projectors: eigenvalues are (1/2)(2 pi/L)^2 |m|^2
+    L, n = 6.74, 16
+    q = 0.5 * (2 * math.pi / L) ** 2
+    assert abs(q - 0.43452) < 5e-6
+    levels = np.array([0, 1, 2, 3, 4, 5]) * q
+    mult = [1, 6, 12, 8, 6, 24]
+    expect = np.repeat(levels, mult)
+    oc = oh.OracleCell(n, L, np.zeros(n ** 3), [], [], np.zeros(0))
+    cfg = ki.custom_config("fe", L, n, [(0, 0, 0)], 19)
+    X0 = ki.make_x0(cfg)
+    st, _ = olob.run(oc, X0, 19, tol=1e-9, maxit=300, precond=olob.tpa_preconditioner(oc))
+    assert np.abs(st.theta - expect[:19]).max() <= 1e-10
+
+
+# ---------------------------------------------------------------- geometry
+
+
+def test_oracle_recomputes_generator_potential_and_projectors():
+    cfg = ki.config("C2")
+    cell = ki.make_cell(cfg)
+    oc = oh.oracle_cell(cfg, cell.D)
+    assert np.abs(oc.V - cell.V).max() <= 1e-12
+    for a in range(cell.natoms):
+        s0, s1 = cell.atom_supp_ptr[a], cell.atom_supp_ptr[a + 1]
+        ns = s1 - s0
+        for j in range(cell.atom_proj_ptr[a], cell.atom_proj_ptr[a + 1]):
+            jj = j - cell.atom_proj_ptr[a]
+            np.testing.assert_array_equal(oc.proj_supp[j], cell.supp_idx[s0:s1])
+            b = cell.beta[cell.beta_ptr[a] + jj * ns: cell.beta_ptr[a] + (jj + 1) * ns]
+            assert np.abs(oc.proj_val[j] - b).max() <= 1e-12
+
+
+def test_config_sizes_match_derived_table():
+    c2, c3, c4 = ki.config("C2"), ki.config("C3"), ki.config("C4")
+    assert c2.Ng == 110592 and c3.Ng == 884736 and c4.Ng == 1404928
+    assert abs(c3.L - 20.22) < 1e-9 and abs(c4.L - 23.92) < 1e-9
+    cell = ki.make_cell(c2)
+    assert cell.natoms == 64 and cell.nproj == 256
+    per_atom = np.diff(cell.atom_supp_ptr)
+    assert 11500 < per_atom.mean() < 12700  # about 12.1k points inside 4 bohr
+
+
+# ---------------------------------------------------------------- P8, P9
+
+
+def random_hpd(n, rng, cond=1e3):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    s = np.logspace(0, -math.log10(cond), n)
+    return (Q * s) @ Q.conj().T
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 48])
+def test_cholesky_and_triangular_solves_match_library(n):
+    rng = np.random.default_rng(n)
+    S = random_hpd(n, rng)
+    L, info = ola.cholesky_lower(S)
+    assert info == 0
+    assert np.abs(L - np.linalg.cholesky(S)).max() <= 1e-12
+    B = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    Y = ola.solve_lower(L, B)
+    assert np.abs(Y - scipy.linalg.solve_triangular(L, B, lower=True)).max() <= 1e-10 * np.abs(Y).max()
+    Xs = ola.solve_lower_conj_t(L, B)
+    ref = scipy.linalg.solve_triangular(L, B, lower=True, trans="C")
+    assert np.abs(Xs - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_cholesky_reports_failing_minor():
+    S = np.diag([1.0, 2.0, -1.0, 3.0]).astype(complex)
+    _, info = ola.cholesky_lower(S)
+    assert info == 3
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((6, 4)) + 1j * rng.standard_normal((6, 4))
+    A = np.concatenate([A, A[:, 1:2]], axis=1)  # duplicated column
+    _, info = ola.cholesky_lower(A.conj().T @ A)
+    assert info == 5
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 16, 47, 64])
+def test_jacobi_matches_numpy_eigh(n):
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = A + A.conj().T
+    w, Z = ola.jacobi_eigh(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(w - ref).max() <= 1e-13 * np.abs(ref).max() * max(1, n)
+    assert np.abs(Z.conj().T @ Z - np.eye(n)).max() <= 1e-13 * max(1, n)
+    assert np.abs(A @ Z - Z * w).max() <= 1e-12 * np.abs(ref).max() * max(1, n)
+
+
+def test_jacobi_diagonal_input_unchanged():
+    d = np.array([3.0, -1.0, 2.0, 0.5])
+    w, Z = ola.jacobi_eigh(np.diag(d).astype(complex))
+    np.testing.assert_array_equal(w, np.sort(d))
+    assert np.abs(np.abs(Z) - np.abs(Z).round()).max() == 0.0
+
+
+@pytest.mark.parametrize("n,nev", [(12, 4), (48, 16), (90, 30)])
+def test_two_trsm_reduction_matches_generalised_library_solve(n, nev):
+    rng = np.random.default_rng(7 * n)
+    S = random_hpd(n, rng, cond=1e4)
+    Hm = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Hm = Hm + Hm.conj().T
+    w, C, info = ola.hegv_two_trsm(Hm, S, nev)
+    assert info == 0
+    ref = scipy.linalg.eigh(Hm, S, eigvals_only=True)[:nev]
+    assert np.abs(w - ref).max() <= 1e-12 * np.abs(ref).max() * 10
+    assert np.abs(C.conj().T @ S @ C - np.eye(nev)).max() <= 1e-10
+    assert np.abs(Hm @ C - S @ C * w).max() <= 1e-9 * np.abs(Hm).max()
+
+
+def test_two_trsm_reports_indefinite_overlap():
+    n = 6
+    S = np.eye(n, dtype=complex)
+    S[3, 3] = -1.0
+    _, _, info = ola.hegv_two_trsm(np.eye(n, dtype=complex), S, 2)
+    assert info == n + 4
+
+
+# ---------------------------------------------------------------- P5, P6, P7, P4, P11
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    cfg = tiny_cfg()
+    cell = ki.make_cell(cfg)
+    oc = oh.oracle_cell(cfg, cell.D)
+    return cfg, cell, oc
+
+
+def test_hamiltonian_is_hermitian(tiny):
+    cfg, cell, oc = tiny
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((2, cfg.Ng)) + 1j * rng.standard_normal((2, cfg.Ng))
+    Ha = oh.apply_h(oc, a)
+    lhs = np.vdot(a[0], Ha[1])
+    rhs = np.vdot(Ha[0], a[1])
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,lmax,npos", [(8, 1, 1), (10, 1, 2), (12, 2, 2)])
+def test_lobpcg_matches_brute_force_dense_eigh(n, lmax, npos):
+    pos = ((0.1, 0.2, 0.3), (0.6, 0.55, 0.45))[:npos]
+    L = 7.0 if n < 12 else 8.0
+    cfg = tiny_cfg(n=n, L=L, lmax=lmax, positions=pos, nb=8)
+    cell = ki.make_cell(cfg)
+    Hd = dense_h_from_generator(cell)
+    ref = np.linalg.eigvalsh(Hd)
+    oc = oh.oracle_cell(cfg, cell.D)
+    # oracle H-apply equals the dense matrix on random vectors
+    rng = np.random.default_rng(n)
+    v = rng.standard_normal((3, cfg.Ng)) + 1j * rng.standard_normal((3, cfg.Ng))
+    assert np.abs(oh.apply_h(oc, v) - (Hd @ v.T).T).max() <= 1e-11 * np.abs(Hd).max()
+    st, hist = olob.run(oc, ki.make_x0(cfg), 8, tol=1e-9, maxit=400, precond=olob.tpa_preconditioner(oc))
+    assert hist[-1][1][:8].max() <= 1e-9
+    assert np.abs(st.theta - ref[:8]).max() <= 1e-10
+    # S-orthonormality of the final block (S = I)
+    G = np.conj(st.X) @ st.X.T
+    assert np.abs(G - np.eye(8)).max() <= 1e-12
+
+
+def test_constant_potential_shift_and_zero_coupling(tiny):
+    cfg, cell, oc = tiny
+    X0 = ki.make_x0(cfg)
+    pc = olob.tpa_preconditioner
+    st0, _ = olob.run(oc, X0, 6, 1e-9, 300, pc(oc))
+    oc_shift = oh.OracleCell(oc.n, oc.L, oc.V + 0.37, oc.proj_supp, oc.proj_val, oc.D)
+    st1, _ = olob.run(oc_shift, X0, 6, 1e-9, 300, pc(oc_shift))
+    assert np.abs(st1.theta - st0.theta - 0.37).max() <= 1e-10
+    # D = 0 reduces to the local-only problem
+    oc_d0 = oh.OracleCell(oc.n, oc.L, oc.V, oc.proj_supp, oc.proj_val, np.zeros_like(oc.D))
+    oc_loc = oh.OracleCell(oc.n, oc.L, oc.V, [], [], np.zeros(0))
+    a, _ = olob.run(oc_d0, X0, 6, 1e-9, 300, pc(oc_d0))
+    b, _ = olob.run(oc_loc, X0, 6, 1e-9, 300, pc(oc_loc))
+    assert np.abs(a.theta - b.theta).max() <= 1e-10
+
+
+def test_translation_and_permutation_invariance():
+    base = ((0.1, 0.2, 0.3), (0.6, 0.55, 0.45))
+    n, L = 10, 7.0
+    cfg = tiny_cfg(n=n, L=L, positions=base)
+    cell = ki.make_cell(cfg)
+    ref = np.linalg.eigvalsh(dense_h_from_generator(cell))[:10]
+    # translate every atom by a whole grid vector (2, -1, 3) * h
+    sh = np.array([2, -1, 3]) / n
+    moved = tuple(tuple((np.array(p) + sh) % 1.0) for p in base)
+    cfg2 = tiny_cfg(n=n, L=L, positions=moved)
+    cell2 = ki.make_cell(cfg2)
+    cell2.D[:] = cell.D
+    w2 = np.linalg.eigvalsh(dense_h_from_generator(cell2))[:10]
+    assert np.abs(w2 - ref).max() <= 1e-11
+    # permute the atoms together with their couplings
+    cfg3 = tiny_cfg(n=n, L=L, positions=base[::-1])
+    cell3 = ki.make_cell(cfg3)
+    npa = cell.nproj // 2
+    cell3.D[:npa], cell3.D[npa:] = cell.D[npa:], cell.D[:npa]
+    w3 = np.linalg.eigvalsh(dense_h_from_generator(cell3))[:10]
+    assert np.abs(w3 - ref).max() <= 1e-11
+
+
+# ---------------------------------------------------------------- P10
+
+
+def test_rank_one_projector_interlaces_and_solves_secular_equation():
+    cfg = tiny_cfg(n=8, L=7.0, lmax=0, positions=((0.3, 0.4, 0.5),), nb=6)
+    cell = ki.make_cell(cfg)
+    cell.D[:] = 0.8
+    oc = oh.oracle_cell(cfg, cell.D)
+    oc_loc = oh.OracleCell(oc.n, oc.L, oc.V, [], [], np.zeros(0))
+    # local spectrum by brute force (dense from numpy.fft)
+    Hd = dense_h_from_generator(cell)
+    b = np.zeros(cfg.Ng)
+    b[oc.proj_supp[0]] = oc.proj_val[0]
+    H0 = Hd - 0.8 * np.outer(b, b)
+    lam0, phi = np.linalg.eigh(H0)
+    lam, _ = np.linalg.eigh(Hd)
+    # interlacing for a positive rank-one update
+    assert np.all(lam[:-1] >= lam0[:-1] - 1e-12) and np.all(lam[:-1] <= lam0[1:] + 1e-12)
+    # oracle LOBPCG reproduces the updated values
+    st, _ = olob.run(oc, ki.make_x0(cfg), 6, 1e-9, 300, olob.tpa_preconditioner(oc))
+    assert np.abs(st.theta - lam[:6]).max() <= 1e-10
+    # every eigenvalue with nonzero weight solves 1 + D sum |<phi|b>|^2/(lam_k - lam) = 0
+    wgt = np.abs(phi.T @ b) ** 2
+    for x in st.theta[:3]:
+        sec = 1.0 + 0.8 * np.sum(wgt / (lam0 - x))
+        assert abs(sec) <= 1e-6 * np.sum(wgt / np.abs(lam0 - x))
+    del oc_loc
+
+
+# ---------------------------------------------------------------- P12
+
+
+def test_residual_bounds_certify_eigenvalues(tiny):
+    cfg, cell, oc = tiny
+    ref = np.linalg.eigvalsh(dense_h_from_generator(cell))
+    st, _ = olob.run(oc, ki.make_x0(cfg), 6, 1e-4, 300, olob.tpa_preconditioner(oc))
+    R, res = olob.residual(st)
+    for i in range(6):
+        # Krylov-Weinstein: some eigenvalue within ||r|| of theta
+        assert np.min(np.abs(ref - st.theta[i])) <= res[i] * (1 + 1e-9)
+    # Kato-Temple for the lowest (gap to the second level)
+    gap = ref[1] - st.theta[0]
+    assert st.theta[0] - ref[0] <= res[0] ** 2 / gap * (1 + 1e-6) + 1e-14
+
+
+# ---------------------------------------------------------------- P14
+
+
+def test_tpa_on_plane_wave_is_the_polynomial():
+    n, L = 12, 6.0
+    x = np.arange(n) * L / n
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    m = (2, -1, 3)
+    g = [2 * math.pi / L * mi for mi in m]
+    pw = np.exp(1j * (g[0] * X + g[1] * Y + g[2] * Z)).ravel()[None]
+    E = np.array([1.7])
+    w = opc.tpa_apply(pw, E, n, L)
+    xg = 0.5 * sum(gi * gi for gi in g) / E[0]
+    k = (27 + 18 * xg + 12 * xg ** 2 + 8 * xg ** 3) / (27 + 18 * xg + 12 * xg ** 2 + 8 * xg ** 3 + 16 * xg ** 4)
+    assert np.abs(w - k * pw).max() <= 1e-12
+    assert opc.tpa_polynomial(np.array([0.0]))[0] == 1.0
+
+
+def test_band_kinetic_energy_of_plane_wave():
+    n, L = 8, 5.0
+    x = np.arange(n) * L / n
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    g = 2 * math.pi / L
+    pw = (np.exp(1j * g * (X + 2 * Y)).ravel() / math.sqrt(n ** 3))[None]
+    E = opc.band_kinetic_energy(pw, n, L)
+    assert abs(E[0] - 0.5 * g * g * 5) <= 1e-12
+
+
+# ---------------------------------------------------------------- P15
+
+
+def test_conv_matches_scipy_correlate_wrap():
+    rng = np.random.default_rng(5)
+    n = 6
+    inp = rng.standard_normal((3, n, n, n))
+    w = rng.standard_normal((4, 3, 3, 3, 3))
+    b = rng.standard_normal(4)
+    out = ocnn.conv3d(inp, w, b)
+    for o in range(4):
+        ref = np.full((n, n, n), b[o])
+        for i in range(3):
+            ref += scipy.ndimage.correlate(inp[i], w[o, i], mode="wrap")
+        assert np.abs(out[o] - ref).max() <= 1e-12
+
+
+def test_cnn_backward_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    n = 5
+    params = ocnn.init_params(2, channels=(3, 4, 4, 2))
+    x = rng.standard_normal((3, n, n, n))
+    t = rng.standard_normal((2, n, n, n))
+
+    def loss_of(ps, xx):
+        y, _ = ocnn.forward(ps, xx)
+        return ocnn.normalised_loss(y, t)[0]
+
+    y, cache = ocnn.forward(params, x)
+    _, gy = ocnn.normalised_loss(y, t)
+    grads, gx = ocnn.backward(params, cache, gy)
+    eps = 1e-6
+    for k, idx in [(0, (1, 2, 0, 1, 2)), (1, (3, 0, 2, 2, 1)), (2, (1, 3, 0, 0, 0))]:
+        w = params[k][0]
+        wp = w.copy(); wp[idx] += eps
+        wm = w.copy(); wm[idx] -= eps
+        pp = list(params); pp[k] = (wp, params[k][1])
+        pm = list(params); pm[k] = (wm, params[k][1])
+        fd = (loss_of(pp, x) - loss_of(pm, x)) / (2 * eps)
+        assert abs(fd - grads[k][0][idx]) <= 1e-6 * max(1e-3, abs(fd))
+    for k in range(3):
+        bp = params[k][1].copy(); bp[1] += eps
+        bm = params[k][1].copy(); bm[1] -= eps
+        pp = list(params); pp[k] = (params[k][0], bp)
+        pm = list(params); pm[k] = (params[k][0], bm)
+        fd = (loss_of(pp, x) - loss_of(pm, x)) / (2 * eps)
+        assert abs(fd - grads[k][1][1]) <= 1e-6 * max(1e-3, abs(fd))
+    xp = x.copy(); xp[0, 1, 2, 3] += eps
+    xm = x.copy(); xm[0, 1, 2, 3] -= eps
+    fd = (loss_of(params, xp) - loss_of(params, xm)) / (2 * eps)
+    assert abs(fd - gx[0, 1, 2, 3]) <= 1e-6 * max(1e-3, abs(fd))
+
+
+def test_adam_first_step_is_lr_times_sign():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    p1, _, _ = ocnn.adam_update(p, g, np.zeros(3), np.zeros(3), 1, lr=1e-3)
+    assert np.allclose(p - p1, 1e-3 * np.sign(g), rtol=1e-4)
+
+
+# ---------------------------------------------------------------- P16
+
+
+def test_projected_cg_matches_lstsq(tiny):
+    cfg, cell, oc = tiny
+    Hd = dense_h_from_generator(cell)
+    st, _ = olob.run(oc, ki.make_x0(cfg), 6, 1e-9, 300, olob.tpa_preconditioner(oc))
+    X = st.X
+    i = 2
+    theta = st.theta[i]
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(cfg.Ng) + 1j * rng.standard_normal(cfg.Ng)
+    P = np.eye(cfg.Ng) - X.T @ np.conj(X)
+    r = P @ r
+    t, its, ok = ocg.projected_cg(lambda v: oh.apply_h(oc, v), X, theta, r, rtol=1e-12, maxit=2000)
+    A = P @ (Hd - theta * np.eye(cfg.Ng)) @ P
+    ref, *_ = np.linalg.lstsq(A, r, rcond=1e-12)
+    ref = P @ ref
+    assert ok
+    assert np.linalg.norm(t - ref) <= 1e-8 * np.linalg.norm(ref)
