@@ -1,0 +1,204 @@
+"""Benchmark: LOBPCG iterations/s of the HIP path on one MI355X.
+
+Workload (default): the 64-atom diamond-like cell -- 2x2x2 conventional
+diamond supercell, L = 13.48 bohr, 48^3 grid, 160 bands (128 tracked),
+Gaussian local potential and s+p Gaussian Kleinman-Bylander projectors,
+complex128 throughout, Teter-Payne-Allan preconditioner.  Inputs are seeded
+and synthetic.  A step is one full LOBPCG iteration: residual and
+preconditioner, block orthonormalisation, H-apply (batched 3D FFT, local and
+nonlocal terms), Gram GEMMs, Cholesky + two triangular solves + Hermitian
+eigensolve + back-transform, rotation GEMMs.
+
+Prints ONE JSON line.  Extra legs: time to 1e-6 Ha (fresh solve from the
+initial block against the stored oracle eigenvalues) and the CPU oracle
+timed on the host for one LOBPCG iteration of the same cell.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to 1e-6 Ha eigenpairs & LOBPCG iter/s: FP64 vs mixed+learned precond"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tta", action="store_true")
+    return ap.parse_args()
+
+
+def family_work(cfg, steps_info):
+    """Algorithmic flops / bytes per step for each kernel family (FP64 C2)."""
+    Ng, nb = cfg.Ng, cfg.nb
+    m = 3 * nb
+    es = 16
+    blk = Ng * nb * es
+    return {
+        # Hermitian triangles: W and P self-Grams (S only), basis Gram (S and H)
+        "gram_flops": 8 * Ng * nb * (nb + 1) / 2 * 2 + 2 * 8 * Ng * m * (m + 1) / 2,
+        # W and P/AP Cholesky-QR rotations, X/P from V and AX/AP from AV
+        "rotate_flops": 8 * Ng * nb * nb * 3 + 2 * 8 * Ng * m * nb,
+        # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-apply of W (R+W)
+        "pass_a_bytes": blk * (2 + 3 + 2),
+        # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W)
+        "pass_b_bytes": blk * (1 + 2 + 2),
+        # pass C: TPA (R+W), H (tmp R + psi R + W)
+        "pass_c_bytes": blk * (2 + 3),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import ksinputs as ki
+    from paper_2512_04447_amd import binding as b
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = ki.config(args.config)
+    cell = ki.make_cell(cfg)
+    X0 = ki.make_x0(cfg)
+    log(f"[bench] {cfg.name}: n={cfg.n} nb={cfg.nb} atoms={cell.natoms} nproj={cell.nproj}")
+    plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell), cfg.nb, b.KS_FP64)
+    v = torch.from_numpy(cell.V).cuda()
+    x0 = torch.from_numpy(X0).cuda()
+    lob = b.Lobpcg(plan, v, x0)
+    lob.init()
+    tol = cfg.res_tol
+    for _ in range(args.warmup):
+        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
+    torch.cuda.synchronize()
+    fams = [b.KF_GRAM, b.KF_ROTATE, b.KF_PASS_A, b.KF_PASS_B, b.KF_PASS_C, b.KF_NL_PROJECT, b.KF_HEGV, b.KF_ZGEMM]
+    names = ["gram", "rotate", "pass_a", "pass_b", "pass_c", "nl_project", "hegv", "zgemm"]
+    # timed region without event instrumentation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    log(f"[bench] {args.steps} steps in {wall:.3f}s")
+    # same number of steps again with HIP events around each kernel family
+    for f in fams:
+        b.kernel_timer(True, f)
+    for _ in range(args.steps):
+        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
+    torch.cuda.synchronize()
+    fam_ms = {}
+    for f, nm in zip(fams, names):
+        ms, n = b.kernel_timer_read(f)
+        b.kernel_timer(False, f)
+        fam_ms[nm] = (ms / args.steps, n / args.steps)
+    log("[bench] per-step ms by family: " + ", ".join(f"{k}={v[0]:.3f} ({v[1]:.0f} launches)" for k, v in fam_ms.items()))
+    work = family_work(cfg, None)
+    rates = {
+        "gram": ("mfma", work["gram_flops"] / 1e12 / (fam_ms["gram"][0] / 1e3), FP64_PEAK_TFS, "TFLOP/s",
+                 work["gram_flops"] / max(fam_ms["gram"][1], 1)),
+        "rotate": ("mfma", work["rotate_flops"] / 1e12 / (fam_ms["rotate"][0] / 1e3), FP64_PEAK_TFS, "TFLOP/s",
+                   work["rotate_flops"] / max(fam_ms["rotate"][1], 1)),
+        "pass_a": ("hbm", work["pass_a_bytes"] / 1e9 / (fam_ms["pass_a"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
+                   work["pass_a_bytes"] / max(fam_ms["pass_a"][1], 1)),
+        "pass_b": ("hbm", work["pass_b_bytes"] / 1e9 / (fam_ms["pass_b"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
+                   work["pass_b_bytes"] / max(fam_ms["pass_b"][1], 1)),
+        "pass_c": ("hbm", work["pass_c_bytes"] / 1e9 / (fam_ms["pass_c"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
+                   work["pass_c_bytes"] / max(fam_ms["pass_c"][1], 1)),
+    }
+    dom = max(rates, key=lambda k: fam_ms[k][0])
+    bound, ach, peak, unit, per_launch = rates[dom]
+    roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                "frac": round(ach / peak, 4), "traffic": None,
+                "algorithmic_per_launch": per_launch,
+                "avg_launch_ms": fam_ms[dom][0] / max(fam_ms[dom][1], 1)}
+    others = {k: {"achieved": round(r[1], 3), "unit": r[3], "frac": round(r[1] / r[2], 4),
+                  "ms_per_step": round(fam_ms[k][0], 4)} for k, r in rates.items()}
+    others["hegv"] = {"ms_per_step": round(fam_ms["hegv"][0], 4)}
+    others["nl_project"] = {"ms_per_step": round(fam_ms["nl_project"][0], 4)}
+
+    # time to 1e-6 Ha against the stored oracle eigenvalues
+    tta = None
+    ref_path = os.path.join(ROOT, "tests", "golden", "c2_eigenvalues.txt")
+    if not args.no_tta and cfg.name == "C2" and os.path.exists(ref_path):
+        ref = np.loadtxt(ref_path, comments="#", usecols=1)[: cfg.ntrack]
+        lob2 = b.Lobpcg(plan, v, x0)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        lob2.init()
+        it = 0
+        while it < 200:
+            lob2.step(b.KS_PRECOND_TPA, 0.1 * tol)
+            it += 1
+            th = lob2.theta[: cfg.ntrack].cpu().numpy()
+            if np.abs(th - ref).max() <= 1e-6:
+                break
+        torch.cuda.synchronize()
+        tta = {"seconds": round(time.perf_counter() - s0, 4), "iterations": it,
+               "max_abs_err_Ha": float(np.abs(th - ref).max())}
+        log(f"[bench] time to 1e-6 Ha: {tta}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import hamiltonian as oh
+        from oracle import lobpcg as olob
+
+        cores = len(os.sched_getaffinity(0))
+        oc = oh.oracle_cell(cfg, cell.D)
+        st = olob.initial_state(oc, X0)
+        pc = olob.tpa_preconditioner(oc)
+        c0 = time.perf_counter()
+        olob.step(oc, st, pc, 0.1 * tol)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(1.0 / dt, 5), "unit": "LOBPCG iter/s", "cores": cores, "kind": "oracle",
+               "sample": f"one oracle LOBPCG iteration on the same cell after its initialisation ({dt:.1f} s)"}
+        log(f"[bench] cpu oracle: {dt:.2f}s per iteration on {cores} cores")
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / wall, 4),
+        "unit": "LOBPCG iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "diamond-like 2x2x2 supercell, 64 atoms, L=13.48 bohr, 48^3 grid, 160 bands, "
+                               "s+p KB projectors, complex128, TPA preconditioner",
+                   "Ng": cfg.Ng, "bands": cfg.nb, "precision": "fp64"},
+        "roofline": roofline,
+        "kernels": others,
+        "time_to_1e-6_Ha": tta,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

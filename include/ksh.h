@@ -1,0 +1,223 @@
+/*
+ * ksh.h - C ABI of an MI355X-native LOBPCG eigensolver for real-space
+ * Kohn-Sham DFT (the SCF hot path of arXiv 2512.04447).
+ *
+ * The paper names four per-SCF-iteration tasks (the task-list paragraph):
+ * (1) FFTs that apply the Laplacian to every orbital in one batched call,
+ * (2) the dense products that form the LOBPCG subspace matrices H and S,
+ * (3) the generalised Hermitian eigensolve H X = lambda S X, reduced by a
+ *     Cholesky factor S = L L^H to K Z = lambda Z, K = L^-1 H L^-H (Eq. 1),
+ *     with K formed by two triangular solves (paragraph after Eq. 1), and
+ * (4) the separable nonlocal pseudopotential operator.
+ * Everything behind this header is hand-written HIP for gfx950.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: Hartree atomic units (Ha, bohr).
+ * Grid: orthorhombic, n[0] x n[1] x n[2] points; point (i,j,k) sits at
+ *   (i L0/n0, j L1/n1, k L2/n2); its linear index is (i*n1 + j)*n2 + k.
+ *   Ng = n0*n1*n2.  Each n must factor into 2, 3, 5 and 7.
+ * Transforms: forward sum_r exp(-i G.r) f(r), inverse exp(+i G.r)/Ng,
+ *   G = 2 pi m / L per axis with m wrapped into [-n/2, n/2); T(G) = |G|^2/2.
+ * Blocks: an orbital block of nb columns is column-major, column (band) j
+ *   starting at base + j*ld elements, ld >= Ng, interleaved complex:
+ *   double2 (complex128) for KS_FP64 plans, float2 (complex64) for the
+ *   mixed-precision plans.
+ * Pointers: unless stated otherwise, data pointers are DEVICE pointers owned
+ *   by the caller; the library never frees them.  Plan-owned tables live in
+ *   device memory allocated by ks_plan_create and freed by ks_plan_destroy.
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *   stream ordered; a call returns once its work is enqueued, except where
+ *   noted (lobpcg_init and lobpcg_step read 4 bytes back per subspace solve).
+ * Errors: every function returns 0 on success; -i when argument i (1-based)
+ *   is invalid (checked on the host before any launch); KS_E_HIP - code for
+ *   a HIP runtime error; KS_E_WORKSPACE when work_bytes is too small;
+ *   KS_E_NUMERIC when a numerical breakdown stops the computation.  The
+ *   message of the last error on the calling thread is ks_last_error().
+ * Concurrency: one plan is used by one stream at a time.
+ */
+#ifndef KSH_H
+#define KSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KS_E_HIP (-1000)
+#define KS_E_WORKSPACE (-2001)
+#define KS_E_NUMERIC (-2002)
+#define KS_E_UNSUPPORTED (-2003)
+
+/* Arithmetic of a plan.
+ * KS_FP64: blocks complex128; FFT, H-apply, Gram, rotation and subspace
+ *   solve all in FP64.
+ * KS_MIXED_FP32: blocks complex64; FFT and H-apply in FP32; Gram products in
+ *   FP32 with FP32 accumulation inside each K chunk and FP64 summation of
+ *   the chunks; Cholesky, triangular solves, eigensolve and the X
+ *   re-orthonormalisation factor in FP64; rotation in FP32.
+ * KS_MIXED_BF16X3: as KS_MIXED_FP32 but the H Gram uses three bf16 products
+ *   (hi*hi + hi*lo + lo*hi) per real product; S stays FP32. */
+typedef enum { KS_FP64 = 0, KS_MIXED_FP32 = 1, KS_MIXED_BF16X3 = 2 } ks_precision;
+
+typedef struct {
+  int32_t n[3];
+  double L[3];
+} ks_grid;
+
+/* Separable (Kleinman-Bylander) projector set, task (4) of the task list.
+ * HOST pointers, read once by ks_plan_create.
+ * Atom a owns support points supp_idx[atom_supp_ptr[a] .. atom_supp_ptr[a+1])
+ * (grid linear indices) and projectors atom_proj_ptr[a] .. atom_proj_ptr[a+1].
+ * The values of its projector j (0-based within the atom) at its support
+ * points are beta[beta_ptr[a] + j*|S_a| + s].  D[p] is the coupling of
+ * projector p (Ha).  The operator is sum_p b_p D_p b_p^T (real b_p). */
+typedef struct {
+  int32_t n_atoms;
+  int32_t n_proj;
+  int64_t n_supp;
+  const int32_t* atom_supp_ptr; /* n_atoms + 1 */
+  const int32_t* supp_idx;      /* n_supp */
+  const int32_t* atom_proj_ptr; /* n_atoms + 1 */
+  const int64_t* beta_ptr;      /* n_atoms + 1 */
+  const double* beta;           /* beta_ptr[n_atoms] */
+  const double* D;              /* n_proj */
+} ks_projset;
+
+typedef struct ks_plan ks_plan;
+
+/* LOBPCG iteration state (Knyazev's [X, W, P] Rayleigh-Ritz; the paper's
+ * eigensolver).  All block pointers are device blocks of plan->nb_max or
+ * fewer columns with the common leading dimension ld.  X, AX (= H X), P, AP,
+ * W, AW hold the iterate; Xn, AXn, Pn, APn and T1 are scratch blocks of the
+ * same shape.  lobpcg_step swaps the pointer pairs (X,Xn), (AX,AXn),
+ * (P,Pn), (AP,APn) and (W,Xn) as it goes: read them back after each call.
+ * theta[nb] (Ritz values) and res[nb] (residual 2-norms of the block the
+ * step started from) are device arrays of doubles. */
+typedef struct {
+  int32_t nb;
+  int32_t has_p;   /* 0 before the first step; set by lobpcg_step */
+  int64_t ld;
+  void* X;
+  void* AX;
+  void* W;
+  void* AW;
+  void* P;
+  void* AP;
+  void* Xn;
+  void* AXn;
+  void* Pn;
+  void* APn;
+  void* T1;
+  double* theta;
+  double* res;
+  int32_t iter;       /* iterations done */
+  int32_t last_info;  /* info of the last subspace solve (0 = ok) */
+  int32_t dropped_p;  /* times P was dropped after a failed Cholesky */
+  int32_t pad_;
+} ks_lobpcg_state;
+
+/* Preconditioner kinds. */
+#define KS_PRECOND_NONE 0
+#define KS_PRECOND_TPA 1
+
+typedef struct {
+  int32_t precond;  /* KS_PRECOND_* */
+  int32_t pad_;
+  /* Soft locking: a band with residual norm <= lock_tol contributes an
+   * exactly-zero column to W and P (its X column stays). */
+  double lock_tol;
+} ks_lobpcg_opts;
+
+/* Which operation a workspace query is for. */
+#define KS_OP_APPLY_H 1
+#define KS_OP_PRECOND 2
+#define KS_OP_LOBPCG 3
+
+/* Build a plan: radix schedules and twiddle tables for the three axes, the
+ * projector tables in device memory (values in the plan's precision) plus
+ * their inverse by grid point (for the deterministic scatter), and launch
+ * configurations.  `proj` may be NULL or have n_proj == 0 (no nonlocal
+ * term).  nb_max bounds the block width of later calls.  Allocates device
+ * memory; synchronises `stream` once at the end. */
+int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj,
+                   int32_t nb_max, int32_t precision, void* stream);
+int ks_plan_destroy(ks_plan* plan);
+
+/* Bytes of caller workspace that `op` needs for blocks of nb columns. */
+int ks_workspace_size(const ks_plan* plan, int32_t op, int32_t nb, size_t* bytes);
+
+/* Kohn-Sham H-apply (tasks (1) and (4) of the task list plus the local
+ * potential):  hpsi = T psi + V_loc .* psi + sum_p b_p D_p (b_p^T psi).
+ * v_loc: Ng reals (double for KS_FP64, float otherwise).  psi and hpsi must
+ * not overlap.  T is applied by a batched 3D FFT over all nb columns. */
+int ks_apply_h(const ks_plan* plan, const void* v_loc, const void* psi, int64_t ld_psi,
+               void* hpsi, int64_t ld_hpsi, int32_t nb, void* work, size_t work_bytes,
+               void* stream);
+
+/* Residual and preconditioner: R = AX - X diag(theta); res[i] = ||r_i||_2;
+ * W = K(R) where K is the identity (KS_PRECOND_NONE) or the Teter-Payne-
+ * Allan kinetic preconditioner (KS_PRECOND_TPA: w_i = IFFT(K(x) FFT(r_i)),
+ * x = T(G)/E_i, E_i = <x_i|T|x_i>, K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2
+ * +8x^3+16x^4)).  Columns with res[i] <= lock_tol are written as zeros.
+ * All blocks share ld. */
+int ks_precond_apply(const ks_plan* plan, int32_t kind, const void* X, const void* AX,
+                     const double* theta, int64_t ld, int32_t nb, double lock_tol,
+                     void* W, double* res, void* work, size_t work_bytes, void* stream);
+
+/* Generalised Hermitian eigensolve by the paper's reduction (Eq. 1 and the
+ * paragraph after it), FP64 complex, column-major:
+ *   L = chol(S) (lower);  Y = L^-1 H;  K = L^-1 Y^H (= L^-1 H L^-H);
+ *   K <- (K + K^H)/2;  K = Q T Q^H (Householder);  lowest nev eigenpairs of
+ *   the real tridiagonal T by bisection and inverse iteration;  Z = Q Z_T;
+ *   C = L^-H Z.
+ * On return w[0..nev) ascending, C (n x nev, ldc) with C^H S C = I, S holds
+ * L in its lower triangle and H is overwritten.  info_dev (device int32):
+ * 0 ok; n + k if the leading minor k of S is not positive definite (pivot
+ * <= 1e-14 * max diag(S)), then w and C are not written.  n <= 8192. */
+int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds,
+                      double* w, void* C, int32_t ldc, void* work, size_t work_bytes,
+                      int32_t* info_dev, void* stream);
+int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes);
+
+/* LOBPCG start: X <- X L^-H with L = chol(X^H X) (Cholesky-QR of the initial
+ * block in st->X), AX = H X, Rayleigh-Ritz on span(X): X <- X Z, AX <- AX Z,
+ * theta = Ritz values ascending.  Sets st->has_p = 0, st->iter = 0. */
+int lobpcg_init(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st, void* work,
+                size_t work_bytes, void* stream);
+
+/* One LOBPCG iteration:
+ *   R = AX - X Theta, res;  W = K(R) with soft-locked columns zeroed;
+ *   W <- W D L^-H (unit columns, then Cholesky-QR within the block);
+ *   AW = H W;  P, AP masked by the lock mask and orthonormalised the same way;
+ *   S = V^H V, H = V^H AV for V = [X W P] (Hermitised; zero columns decoupled);
+ *   hegv_reduce_solve -> Theta, C (on a failed Cholesky P is dropped and the
+ *   solve repeated);  X <- V C, AX <- AV C, P <- V_{[W P]} C_{[W P]}, AP likewise.
+ * On the mixed plans X is then re-orthonormalised (FP64 Cholesky-QR of X
+ * with the matching update of AX).  Reads the 4-byte info of each subspace
+ * solve back to the host. */
+int lobpcg_step(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st,
+                const ks_lobpcg_opts* opts, void* work, size_t work_bytes, void* stream);
+
+/* Kernel timing for measurement (not needed to solve anything).
+ * ks_kernel_timer(1, id) starts recording a HIP event pair around every
+ * later launch of kernel family `id` on the stream it is launched on;
+ * ks_kernel_timer(0, id) stops recording.  ks_kernel_timer_read waits for
+ * the recorded events, returns the summed kernel time (ms) and launch count
+ * since the last start, and releases the events.  Families:
+ * 0 Gram GEMM, 1 rotation GEMM, 2 FFT pass A, 3 FFT pass B, 4 FFT pass C,
+ * 5 nonlocal projection, 6 subspace solve (hegv as a whole), 7 small GEMM.
+ * Host-side state shared by all threads; not for concurrent use. */
+#define KS_KERNEL_FAMILIES 8
+int ks_kernel_timer(int32_t enable, int32_t family);
+int ks_kernel_timer_read(int32_t family, double* total_ms, int64_t* launches);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* ks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KSH_H */

@@ -183,12 +183,34 @@ def from_arrays(n: int, L: float, V: np.ndarray, supp: list, vals: list, D) -> O
     return OracleCell(n, L, np.asarray(V, np.float64), list(supp), list(vals), np.asarray(D, np.float64))
 
 
+def _atom_groups(cell: OracleCell):
+    """Consecutive projectors that share one support list (one atom)."""
+    groups = []
+    p = 0
+    while p < len(cell.proj_supp):
+        q = p + 1
+        while q < len(cell.proj_supp) and (
+            cell.proj_supp[q] is cell.proj_supp[p]
+            or (len(cell.proj_supp[q]) == len(cell.proj_supp[p])
+                and np.array_equal(cell.proj_supp[q], cell.proj_supp[p]))):
+            q += 1
+        groups.append((p, q))
+        p = q
+    return groups
+
+
 def apply_nl(cell: OracleCell, psi: np.ndarray) -> np.ndarray:
-    """sum over projectors p of b_p D_p (b_p^T psi)."""
+    """sum over projectors p of b_p D_p (b_p^T psi).
+
+    Projectors of one atom share a support, so their terms are formed
+    together: c = psi_S B^T, then psi_S += (c * D) B with B the rows b_p.
+    """
     out = np.zeros_like(psi)
-    for idx, b, d in zip(cell.proj_supp, cell.proj_val, cell.D):
-        c = psi[:, idx] @ b  # (nb,)
-        out[:, idx] += d * np.outer(c, b)
+    for p, q in _atom_groups(cell):
+        idx = cell.proj_supp[p]
+        B = np.array(cell.proj_val[p:q])  # (np_a, |S|)
+        c = psi[:, idx] @ B.T  # (nb, np_a)
+        out[:, idx] += (c * cell.D[p:q]) @ B
     return out
 
 

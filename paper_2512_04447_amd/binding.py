@@ -1,0 +1,346 @@
+"""ctypes binding of libksh.so: argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch
+device tensors and numpy host arrays into the pointers and structs declared
+in include/ksh.h.  Importing works without a GPU; ``load()`` raises if the
+shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libksh.so")
+
+KS_FP64, KS_MIXED_FP32, KS_MIXED_BF16X3 = 0, 1, 2
+KS_PRECOND_NONE, KS_PRECOND_TPA = 0, 1
+KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG = 1, 2, 3
+KS_E_HIP, KS_E_WORKSPACE, KS_E_NUMERIC, KS_E_UNSUPPORTED = -1000, -2001, -2002, -2003
+
+EXPORTS = (
+    "ks_plan_create",
+    "ks_plan_destroy",
+    "ks_workspace_size",
+    "ks_apply_h",
+    "ks_precond_apply",
+    "hegv_reduce_solve",
+    "hegv_workspace_size",
+    "lobpcg_init",
+    "lobpcg_step",
+    "ks_kernel_timer",
+    "ks_kernel_timer_read",
+    "ks_last_error",
+)
+
+# kernel families of ks_kernel_timer
+KF_GRAM, KF_ROTATE, KF_PASS_A, KF_PASS_B, KF_PASS_C, KF_NL_PROJECT, KF_HEGV, KF_ZGEMM = range(8)
+
+
+class KsGrid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3)]
+
+
+class KsProjset(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32),
+        ("n_proj", C.c_int32),
+        ("n_supp", C.c_int64),
+        ("atom_supp_ptr", C.POINTER(C.c_int32)),
+        ("supp_idx", C.POINTER(C.c_int32)),
+        ("atom_proj_ptr", C.POINTER(C.c_int32)),
+        ("beta_ptr", C.POINTER(C.c_int64)),
+        ("beta", C.POINTER(C.c_double)),
+        ("D", C.POINTER(C.c_double)),
+    ]
+
+
+class KsLobpcgState(C.Structure):
+    _fields_ = [
+        ("nb", C.c_int32),
+        ("has_p", C.c_int32),
+        ("ld", C.c_int64),
+        ("X", C.c_void_p),
+        ("AX", C.c_void_p),
+        ("W", C.c_void_p),
+        ("AW", C.c_void_p),
+        ("P", C.c_void_p),
+        ("AP", C.c_void_p),
+        ("Xn", C.c_void_p),
+        ("AXn", C.c_void_p),
+        ("Pn", C.c_void_p),
+        ("APn", C.c_void_p),
+        ("T1", C.c_void_p),
+        ("theta", C.c_void_p),
+        ("res", C.c_void_p),
+        ("iter", C.c_int32),
+        ("last_info", C.c_int32),
+        ("dropped_p", C.c_int32),
+        ("pad_", C.c_int32),
+    ]
+
+
+class KsLobpcgOpts(C.Structure):
+    _fields_ = [("precond", C.c_int32), ("pad_", C.c_int32), ("lock_tol", C.c_double)]
+
+
+class KsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libksh.so and declare its signatures; raises when not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise KsError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.ks_plan_create.argtypes = [C.POINTER(vp), C.POINTER(KsGrid), C.POINTER(KsProjset), i32, i32, vp]
+    lib.ks_plan_destroy.argtypes = [vp]
+    lib.ks_workspace_size.argtypes = [vp, i32, i32, C.POINTER(sz)]
+    lib.ks_apply_h.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, sz, vp]
+    lib.ks_precond_apply.argtypes = [vp, i32, vp, vp, vp, i64, i32, C.c_double, vp, vp, vp, sz, vp]
+    lib.hegv_reduce_solve.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp, vp]
+    lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
+    lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
+    lib.lobpcg_step.argtypes = [vp, vp, C.POINTER(KsLobpcgState), C.POINTER(KsLobpcgOpts), vp, sz, vp]
+    lib.ks_kernel_timer.argtypes = [i32, i32]
+    lib.ks_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.ks_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name != "ks_last_error":
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = load().ks_last_error().decode()
+        raise KsError(f"{what} failed with {rc}: {msg}")
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _work(nbytes: int, device):
+    import torch
+
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class ProjectorArrays:
+    """Host copies of the projector set (numpy), kept alive for the call."""
+
+    atom_supp_ptr: np.ndarray
+    supp_idx: np.ndarray
+    atom_proj_ptr: np.ndarray
+    beta_ptr: np.ndarray
+    beta: np.ndarray
+    D: np.ndarray
+
+    @classmethod
+    def from_cell(cls, cell):
+        return cls(
+            np.ascontiguousarray(cell.atom_supp_ptr, np.int32),
+            np.ascontiguousarray(cell.supp_idx, np.int32),
+            np.ascontiguousarray(cell.atom_proj_ptr, np.int32),
+            np.ascontiguousarray(cell.beta_ptr, np.int64),
+            np.ascontiguousarray(cell.beta, np.float64),
+            np.ascontiguousarray(cell.D, np.float64),
+        )
+
+    def struct(self) -> KsProjset:
+        ps = KsProjset()
+        ps.n_atoms = len(self.atom_supp_ptr) - 1
+        ps.n_proj = len(self.D)
+        ps.n_supp = len(self.supp_idx)
+        ps.atom_supp_ptr = self.atom_supp_ptr.ctypes.data_as(C.POINTER(C.c_int32))
+        ps.supp_idx = self.supp_idx.ctypes.data_as(C.POINTER(C.c_int32))
+        ps.atom_proj_ptr = self.atom_proj_ptr.ctypes.data_as(C.POINTER(C.c_int32))
+        ps.beta_ptr = self.beta_ptr.ctypes.data_as(C.POINTER(C.c_int64))
+        ps.beta = self.beta.ctypes.data_as(C.POINTER(C.c_double))
+        ps.D = self.D.ctypes.data_as(C.POINTER(C.c_double))
+        return ps
+
+
+class Plan:
+    """Owns a ks_plan*."""
+
+    def __init__(self, n, L, proj: ProjectorArrays | None, nb_max: int, precision: int = KS_FP64, stream=None):
+        lib = load()
+        g = KsGrid()
+        for a in range(3):
+            g.n[a] = int(n[a] if hasattr(n, "__len__") else n)
+            g.L[a] = float(L[a] if hasattr(L, "__len__") else L)
+        self.n = tuple(int(g.n[a]) for a in range(3))
+        self.Ng = self.n[0] * self.n[1] * self.n[2]
+        self.nb_max = int(nb_max)
+        self.precision = int(precision)
+        self._proj = proj
+        ps = proj.struct() if proj is not None and len(proj.D) > 0 else None
+        h = C.c_void_p()
+        rc = lib.ks_plan_create(C.byref(h), C.byref(g), C.byref(ps) if ps is not None else None, self.nb_max,
+                                self.precision, C.c_void_p(_stream(stream)))
+        check(rc, "ks_plan_create")
+        self.handle = h
+
+    @property
+    def complex_dtype(self):
+        import torch
+
+        return torch.complex128 if self.precision == KS_FP64 else torch.complex64
+
+    @property
+    def real_dtype(self):
+        import torch
+
+        return torch.float64 if self.precision == KS_FP64 else torch.float32
+
+    def workspace_size(self, op: int, nb: int) -> int:
+        n = C.c_size_t()
+        check(load().ks_workspace_size(self.handle, op, nb, C.byref(n)), "ks_workspace_size")
+        return int(n.value)
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            load().ks_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ks_apply_h(plan: Plan, v, psi, hpsi, nb: int | None = None, work=None, stream=None):
+    """hpsi = H psi for torch blocks of shape (nb, >=Ng) on the device."""
+    nb = psi.shape[0] if nb is None else nb
+    need = plan.workspace_size(KS_OP_APPLY_H, nb)
+    if work is None:
+        work = _work(need, psi.device)
+    rc = load().ks_apply_h(plan.handle, _ptr(v), _ptr(psi), psi.stride(0), _ptr(hpsi), hpsi.stride(0), nb,
+                           _ptr(work), work.numel(), C.c_void_p(_stream(stream)))
+    check(rc, "ks_apply_h")
+    return hpsi
+
+
+def ks_precond_apply(plan: Plan, kind: int, X, AX, theta, W, res, lock_tol: float = 0.0, work=None, stream=None):
+    nb = X.shape[0]
+    need = plan.workspace_size(KS_OP_PRECOND, nb)
+    if work is None:
+        work = _work(need, X.device)
+    rc = load().ks_precond_apply(plan.handle, kind, _ptr(X), _ptr(AX), _ptr(theta), X.stride(0), nb, float(lock_tol),
+                                 _ptr(W), _ptr(res), _ptr(work), work.numel(), C.c_void_p(_stream(stream)))
+    check(rc, "ks_precond_apply")
+    return W
+
+
+def kernel_timer(enable: bool, family: int) -> None:
+    check(load().ks_kernel_timer(1 if enable else 0, family), "ks_kernel_timer")
+
+
+def kernel_timer_read(family: int):
+    """(total milliseconds, launches) recorded since the timer was enabled."""
+    ms = C.c_double()
+    n = C.c_int64()
+    check(load().ks_kernel_timer_read(family, C.byref(ms), C.byref(n)), "ks_kernel_timer_read")
+    return float(ms.value), int(n.value)
+
+
+def hegv_workspace_size(n: int, nev: int) -> int:
+    b = C.c_size_t()
+    check(load().hegv_workspace_size(n, nev, C.byref(b)), "hegv_workspace_size")
+    return int(b.value)
+
+
+def hegv_reduce_solve(H, S, nev: int, w, Cmat, info, work=None, stream=None):
+    """H, S: (n, n) complex128 column-major device matrices, i.e. torch
+    tensors whose transpose is contiguous (pass A.T.contiguous().T)."""
+    n = H.shape[0]
+    if work is None:
+        work = _work(hegv_workspace_size(n, nev), H.device)
+    rc = load().hegv_reduce_solve(n, nev, _ptr(H), H.stride(1), _ptr(S), S.stride(1), _ptr(w), _ptr(Cmat),
+                                  Cmat.stride(1), _ptr(work), work.numel(), _ptr(info), C.c_void_p(_stream(stream)))
+    check(rc, "hegv_reduce_solve")
+
+
+class Lobpcg:
+    """Device buffers of one LOBPCG run and the calls that advance it."""
+
+    BLOCKS = ("X", "AX", "W", "AW", "P", "AP", "Xn", "AXn", "Pn", "APn", "T1")
+
+    def __init__(self, plan: Plan, v, X0, stream=None):
+        import torch
+
+        self.plan = plan
+        self.v = v
+        nb = X0.shape[0]
+        dev = X0.device
+        self.buf = {}
+        for name in self.BLOCKS:
+            self.buf[name] = torch.empty((nb, plan.Ng), dtype=plan.complex_dtype, device=dev)
+        self.buf["X"].copy_(X0)
+        self.theta = torch.zeros(nb, dtype=torch.float64, device=dev)
+        self.res = torch.zeros(nb, dtype=torch.float64, device=dev)
+        self.work = _work(plan.workspace_size(KS_OP_LOBPCG, nb), dev)
+        self._by_ptr = {_ptr(t): t for t in self.buf.values()}
+        st = KsLobpcgState()
+        st.nb = nb
+        st.ld = plan.Ng
+        for name in self.BLOCKS:
+            setattr(st, name, _ptr(self.buf[name]))
+        st.theta = _ptr(self.theta)
+        st.res = _ptr(self.res)
+        self.st = st
+        self.stream = stream
+
+    def block(self, name: str):
+        return self._by_ptr[int(getattr(self.st, name))]
+
+    def init(self):
+        rc = load().lobpcg_init(self.plan.handle, _ptr(self.v), C.byref(self.st), _ptr(self.work), self.work.numel(),
+                                C.c_void_p(_stream(self.stream)))
+        check(rc, "lobpcg_init")
+
+    def step(self, precond: int = KS_PRECOND_TPA, lock_tol: float = 0.0):
+        o = KsLobpcgOpts()
+        o.precond = precond
+        o.lock_tol = float(lock_tol)
+        rc = load().lobpcg_step(self.plan.handle, _ptr(self.v), C.byref(self.st), C.byref(o), _ptr(self.work),
+                                self.work.numel(), C.c_void_p(_stream(self.stream)))
+        check(rc, "lobpcg_step")
+
+    @property
+    def X(self):
+        return self.block("X")
+
+    @property
+    def AX(self):
+        return self.block("AX")
+
+    @property
+    def P(self):
+        return self.block("P") if self.st.has_p else None
+
+    @property
+    def AP(self):
+        return self.block("AP") if self.st.has_p else None

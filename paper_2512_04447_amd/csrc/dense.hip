@@ -1,0 +1,667 @@
+// Dense FP64 generalised Hermitian eigensolve for the LOBPCG subspace
+// problem H X = lambda S X (the paragraph before Eq. 1), by the paper's
+// reduction: S = L L^H, K = L^-1 H L^-H (Eq. 1) formed with two triangular
+// solves instead of a HEGST-type reduction (the paragraph after Eq. 1), a
+// Hermitian eigensolve of K, and X = L^-H Z.
+//
+// The paper calls vendor (P)ZHEEVD; here the Hermitian eigensolve is
+// Householder tridiagonalisation (one column per step), bisection with
+// Sturm counts for the lowest nev eigenvalues, inverse iteration with
+// modified Gram-Schmidt inside clusters of close eigenvalues, and the
+// back-transformation by the stored reflectors.
+#include <cfloat>
+
+#include "gemm.hpp"
+
+namespace ks {
+
+constexpr int NB = 32;          // panel width of the blocked factorisation
+constexpr double CHOL_TOL = 1e-14;
+
+static inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+// ---------------------------------------------------------------- potrf
+__global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, double* dmax, int32_t* info) {
+  __shared__ double red[4];
+  double m = -DBL_MAX;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, S[i + (int64_t)i * lds].x);
+  // block max by a fixed tree
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) r = fmax(r, red[w]);
+    *dmax = r;
+    *info = 0;
+  }
+}
+
+// Unblocked Cholesky of the diagonal block at k0 (kb <= NB columns) in LDS,
+// then the inverse of that block (for the panel and the triangular solves).
+__global__ void __launch_bounds__(256)
+k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restrict__ dmax,
+        int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv) {
+  __shared__ double2 a[NB][NB + 1];
+  __shared__ int failed;
+  if (*info != 0) return;
+  const double tol = CHOL_TOL * (*dmax);
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    a[i][j] = (i < kb && j < kb) ? S[(k0 + i) + (int64_t)(k0 + j) * lds] : make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x == 0) failed = 0;
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double d = a[j][j].x;
+    if (!(d > tol)) {
+      if (threadIdx.x == 0) { failed = 1; *info = info_offset + k0 + j + 1; }
+      return;  // uniform: every thread read the same d
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    if (threadIdx.x == 0) a[j][j] = make_double2(ljj, 0.0);
+    for (int i = j + 1 + threadIdx.x; i < kb; i += blockDim.x) {
+      a[i][j].x /= ljj;
+      a[i][j].y /= ljj;
+    }
+    __syncthreads();
+    // trailing update of the block: a[i][p] -= a[i][j] conj(a[p][j]), j < p <= i
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+      const int i = e % kb, p = e / kb;
+      if (p > j && i >= p) {
+        const double2 x = a[i][j], y = a[p][j];
+        a[i][p].x -= x.x * y.x + x.y * y.y;
+        a[i][p].y -= x.y * y.x - x.x * y.y;
+      }
+    }
+    __syncthreads();
+  }
+  // write L_kk (lower part) back
+  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+    const int i = e % kb, j = e / kb;
+    if (i >= j) S[(k0 + i) + (int64_t)(k0 + j) * lds] = a[i][j];
+  }
+  // inverse: column c of X = L^-1 solves L x = e_c by forward substitution
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    double2 x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) x[i] = make_double2(0.0, 0.0);
+    if (c < kb) {
+      for (int i = c; i < kb; ++i) {
+        double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        for (int p = c; p < i; ++p) {
+          const double2 l = a[i][p];
+          s.x -= l.x * x[p].x - l.y * x[p].y;
+          s.y -= l.x * x[p].y + l.y * x[p].x;
+        }
+        const double inv = 1.0 / a[i][i].x;
+        x[i] = make_double2(s.x * inv, s.y * inv);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) linv[i + (int64_t)c * NB] = x[i];
+  }
+}
+
+__global__ void k_copy(const double2* __restrict__ src, int ld_src, double2* __restrict__ dst, int ld_dst, int rows,
+                       int cols) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows);
+    const int64_t j = e / rows;
+    dst[i + j * ld_dst] = src[i + j * ld_src];
+  }
+}
+
+static int copy_block(const double2* src, int ld_src, double2* dst, int ld_dst, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return 0;
+  const int64_t total = (int64_t)rows * cols;
+  const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 2048);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, src, ld_src, dst, ld_dst, rows, cols);
+  KS_LAUNCH_CHECK("copy");
+  return 0;
+}
+
+struct PotrfWs {
+  double* dmax;
+  double2* linv;  // nblk x NB x NB
+  double2* panel; // n x NB
+};
+
+static PotrfWs potrf_ws(void* work, int n) {
+  char* p = static_cast<char*>(work);
+  PotrfWs w;
+  w.dmax = reinterpret_cast<double*>(p);
+  p += 256;
+  w.linv = reinterpret_cast<double2*>(p);
+  p += al((size_t)ceil_div(n, NB) * NB * NB * sizeof(double2));
+  w.panel = reinterpret_cast<double2*>(p);
+  return w;
+}
+
+size_t potrf_work(int n) {
+  return 256 + al((size_t)ceil_div(n, NB) * NB * NB * sizeof(double2)) + al((size_t)n * NB * sizeof(double2));
+}
+
+static int potrf_impl(int n, double2* S, int lds, void* work, int32_t* info, int info_offset, hipStream_t s) {
+  PotrfWs w = potrf_ws(work, n);
+  hipLaunchKernelGGL(k_potrf_init, dim3(1), dim3(256), 0, s, S, lds, n, w.dmax, info);
+  KS_LAUNCH_CHECK("potrf_init");
+  int rc;
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int kb = std::min(NB, n - k0);
+    double2* linv = w.linv + (size_t)(k0 / NB) * NB * NB;
+    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, s, S, lds, k0, kb, w.dmax, info, info_offset, linv);
+    KS_LAUNCH_CHECK("potf2");
+    const int rest = n - k0 - kb;
+    if (rest <= 0) break;
+    double2* A21 = S + (k0 + kb) + (int64_t)k0 * lds;
+    // panel: A21 <- A21 L_kk^-H
+    if ((rc = zgemm('N', 'C', rest, kb, kb, 1.0, A21, lds, linv, NB, 0.0, w.panel, n, s))) return rc;
+    if ((rc = copy_block(w.panel, n, A21, lds, rest, kb, s))) return rc;
+    // trailing: A22 <- A22 - A21 A21^H (full square)
+    double2* A22 = S + (k0 + kb) + (int64_t)(k0 + kb) * lds;
+    if ((rc = zgemm('N', 'C', rest, rest, kb, -1.0, w.panel, n, w.panel, n, 1.0, A22, lds, s))) return rc;
+  }
+  return 0;
+}
+
+int potrf(int n, double2* S, int lds, void* work, int32_t* info, hipStream_t s) {
+  return potrf_impl(n, S, lds, work, info, 0, s);
+}
+
+// B <- op(L)^-1 B using the inverted diagonal blocks from potrf.
+// tmp: NB x ncol.
+int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ldb, void* potrf_workspace, void* tmp,
+         const int32_t* info, hipStream_t s) {
+  (void)info;
+  if (n <= 0 || ncol <= 0) return 0;
+  PotrfWs w = potrf_ws(potrf_workspace, n);
+  double2* T = static_cast<double2*>(tmp);
+  int rc;
+  const int nblk = (int)ceil_div(n, NB);
+  if (op == 'N') {
+    for (int kbk = 0; kbk < nblk; ++kbk) {
+      const int k0 = kbk * NB, kb = std::min(NB, n - k0);
+      const double2* linv = w.linv + (size_t)kbk * NB * NB;
+      if ((rc = zgemm('N', 'N', kb, ncol, kb, 1.0, linv, NB, B + k0, ldb, 0.0, T, NB, s))) return rc;
+      if ((rc = copy_block(T, NB, B + k0, ldb, kb, ncol, s))) return rc;
+      const int rest = n - k0 - kb;
+      if (rest > 0)
+        if ((rc = zgemm('N', 'N', rest, ncol, kb, -1.0, L + (k0 + kb) + (int64_t)k0 * ldl, ldl, T, NB, 1.0,
+                        B + k0 + kb, ldb, s)))
+          return rc;
+    }
+  } else {
+    for (int kbk = nblk - 1; kbk >= 0; --kbk) {
+      const int k0 = kbk * NB, kb = std::min(NB, n - k0);
+      const double2* linv = w.linv + (size_t)kbk * NB * NB;
+      if ((rc = zgemm('C', 'N', kb, ncol, kb, 1.0, linv, NB, B + k0, ldb, 0.0, T, NB, s))) return rc;
+      if ((rc = copy_block(T, NB, B + k0, ldb, kb, ncol, s))) return rc;
+      if (k0 > 0)
+        if ((rc = zgemm('C', 'N', k0, ncol, kb, -1.0, L + k0, ldl, T, NB, 1.0, B, ldb, s))) return rc;
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- small ops
+// dst = src^H (n x n)
+__global__ void k_conj_transpose(const double2* __restrict__ src, int lds_, double2* __restrict__ dst, int ldd,
+                                 int n) {
+  __shared__ double2 t[32][33];
+  const int bi = blockIdx.x * 32, bj = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + tx, j = bj + r;
+    if (i < n && j < n) t[r][tx] = src[i + (int64_t)j * lds_];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bj + tx, j = bi + r;  // dst(i, j) = conj(src(j, i))
+    if (i < n && j < n) {
+      double2 v = t[tx][r];
+      dst[i + (int64_t)j * ldd] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
+// K <- (K + K^H)/2
+__global__ void k_hermitise(double2* __restrict__ K, int ldk, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i > j) continue;
+    double2 a = K[i + (int64_t)j * ldk];
+    double2 b = K[j + (int64_t)i * ldk];
+    double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    if (i == j) m.y = 0.0;
+    K[i + (int64_t)j * ldk] = m;
+    K[j + (int64_t)i * ldk] = make_double2(m.x, -m.y);
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonalisation
+// Step k: Householder vector of K[k+1:n, k].  With x = (alpha, x2),
+// beta = -sign(Re alpha) sqrt(|alpha|^2 + |x2|^2), tau = (beta - alpha)/beta,
+// v = (1, x2/(alpha - beta)), so that (I - tau v v^H)^H x = beta e_1.
+// v overwrites K[k+1:n, k]; d[k] = Re K[k][k], e[k] = beta.
+__global__ void __launch_bounds__(256)
+k_house(double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ tau, double* __restrict__ d,
+        double* __restrict__ e) {
+  __shared__ double red[4];
+  double2* x = K + (k + 1) + (int64_t)k * ldk;
+  const int len = n - k - 1;
+  double s = 0.0;
+  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) s += x[i].x * x[i].x + x[i].y * x[i].y;
+  s = block_sum(s, red);
+  const double2 alpha = x[0];
+  double2 t;
+  double beta;
+  double2 scale;
+  if (s == 0.0 && alpha.y == 0.0) {
+    t = make_double2(0.0, 0.0);
+    beta = alpha.x;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    // 1/(alpha - beta)
+    const double ar = alpha.x - beta, ai = alpha.y;
+    const double den = ar * ar + ai * ai;
+    scale = make_double2(ar / den, -ai / den);
+  }
+  __syncthreads();
+  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) {
+    const double2 v = x[i];
+    x[i] = make_double2(v.x * scale.x - v.y * scale.y, v.x * scale.y + v.y * scale.x);
+  }
+  if (threadIdx.x == 0) {
+    x[0] = make_double2(1.0, 0.0);
+    tau[k] = t;
+    d[k] = K[k + (int64_t)k * ldk].x;
+    e[k] = beta;
+  }
+}
+
+// y = A22 v, A22 = K[k+1:, k+1:], v = K[k+1:, k].  16 rows per block,
+// 16 column groups per row, summed in a fixed order.
+__global__ void __launch_bounds__(256)
+k_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ y) {
+  __shared__ double2 part[16][17];
+  const int len = n - k - 1;
+  const double2* v = K + (k + 1) + (int64_t)k * ldk;
+  const double2* A = K + (k + 1) + (int64_t)(k + 1) * ldk;
+  const int ri = threadIdx.x & 15, jg = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + ri;
+  double2 acc = make_double2(0.0, 0.0);
+  if (i < len) {
+    for (int j = jg; j < len; j += 16) {
+      const double2 a = A[i + (int64_t)j * ldk];
+      const double2 b = v[j];
+      acc.x += a.x * b.x - a.y * b.y;
+      acc.y += a.x * b.y + a.y * b.x;
+    }
+  }
+  part[ri][jg] = acc;
+  __syncthreads();
+  if (jg == 0 && i < len) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int g = 0; g < 16; ++g) {
+      s.x += part[ri][g].x;
+      s.y += part[ri][g].y;
+    }
+    y[i] = s;
+  }
+}
+
+// A22 <- A22 - w v^H - v w^H with w = tau y - (1/2)|tau|^2 Re(v^H y) v.
+// Every block recomputes v^H y in the same order (identical result).
+__global__ void __launch_bounds__(256)
+k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict__ y,
+       const double2* __restrict__ tau) {
+  __shared__ double red[4];
+  __shared__ double2 wi_s[32], vi_s[32], wj_s[32], vj_s[32];
+  const int len = n - k - 1;
+  const double2* v = K + (k + 1) + (int64_t)k * ldk;
+  double2* A = K + (k + 1) + (int64_t)(k + 1) * ldk;
+  const double2 t = tau[k];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) s += v[i].x * y[i].x + v[i].y * y[i].y;  // Re(conj(v) y)
+  s = block_sum(s, red);
+  const double c = -0.5 * (t.x * t.x + t.y * t.y) * s;
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  if (threadIdx.x < 32) {
+    const int i = i0 + threadIdx.x;
+    if (i < len) {
+      const double2 vi = v[i], yi = y[i];
+      vi_s[threadIdx.x] = vi;
+      wi_s[threadIdx.x] = make_double2(t.x * yi.x - t.y * yi.y + c * vi.x, t.x * yi.y + t.y * yi.x + c * vi.y);
+    }
+  } else if (threadIdx.x < 64) {
+    const int j = j0 + threadIdx.x - 32;
+    if (j < len) {
+      const double2 vj = v[j], yj = y[j];
+      vj_s[threadIdx.x - 32] = vj;
+      wj_s[threadIdx.x - 32] = make_double2(t.x * yj.x - t.y * yj.y + c * vj.x, t.x * yj.y + t.y * yj.x + c * vj.y);
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int ii = e & 31, jj = e >> 5;
+    const int i = i0 + ii, j = j0 + jj;
+    if (i < len && j < len) {
+      const double2 wi = wi_s[ii], vi = vi_s[ii], wj = wj_s[jj], vj = vj_s[jj];
+      // w_i conj(v_j) + v_i conj(w_j)
+      const double re = wi.x * vj.x + wi.y * vj.y + vi.x * wj.x + vi.y * wj.y;
+      const double im = wi.y * vj.x - wi.x * vj.y + vi.y * wj.x - vi.x * wj.y;
+      double2* a = A + i + (int64_t)j * ldk;
+      a->x -= re;
+      a->y -= im;
+    }
+  }
+}
+
+__global__ void k_tridiag_tail(const double2* __restrict__ K, int ldk, int n, double* __restrict__ d,
+                               double* __restrict__ e, double2* __restrict__ tau) {
+  if (threadIdx.x == 0) {
+    d[n - 1] = K[(n - 1) + (int64_t)(n - 1) * ldk].x;
+    e[n - 1] = 0.0;
+    tau[n - 1] = make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- bisection
+__device__ inline double pivmin_of(const double* e, int n) {
+  double m = 1.0;
+  for (int i = 0; i + 1 < n; ++i) m = fmax(m, e[i] * e[i]);
+  return DBL_MIN * m;
+}
+
+// number of eigenvalues of the tridiagonal (d, e) below x (Sturm count)
+__device__ inline int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void k_bisect(const double* __restrict__ d, const double* __restrict__ e, int n, int nev,
+                         double* __restrict__ w, double* __restrict__ tnorm_out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nev) return;
+  double gl = DBL_MAX, gu = -DBL_MAX;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double pivmin = pivmin_of(e, n);
+  gl -= 2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
+  gu += 2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
+  double lo = gl, hi = gu;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= fmax(4.0 * DBL_EPSILON * tnorm, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) + pivmin) break;
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(d, e, n, mid, pivmin) <= idx) lo = mid; else hi = mid;
+  }
+  w[idx] = 0.5 * (lo + hi);
+  if (idx == 0) *tnorm_out = tnorm;
+}
+
+// Clusters of eigenvalues closer than 1e-3 ||T|| (consecutive in w): start
+// indices cl[0..ncl), cl[ncl] = nev; *ncl_out = ncl.
+__global__ void k_clusters(const double* __restrict__ w, int nev, const double* __restrict__ tnorm,
+                           int32_t* __restrict__ cl, int32_t* __restrict__ ncl_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double ortol = 1e-3 * (*tnorm);
+  int ncl = 0;
+  for (int i = 0; i < nev; ++i) {
+    if (i == 0 || w[i] - w[i - 1] > ortol) cl[ncl++] = i;
+  }
+  cl[ncl] = nev;
+  *ncl_out = ncl;
+}
+
+// Inverse iteration for the eigenvalues of one cluster (one block per
+// cluster; blocks past the cluster count exit).  Solves (T - lambda I) x = b
+// by Gaussian elimination with partial pivoting on the tridiagonal matrix
+// (thread 0), re-orthogonalises against the earlier vectors of the cluster
+// (modified Gram-Schmidt, all threads) and normalises; three sweeps.
+__global__ void __launch_bounds__(256)
+k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, int n, const double* __restrict__ w,
+                    const double* __restrict__ tnorm_p, const int32_t* __restrict__ cl,
+                    const int32_t* __restrict__ ncl, double* __restrict__ Z, int ldz, double* __restrict__ scratch) {
+  __shared__ double red[4];
+  __shared__ double lam_prev;
+  const int c = blockIdx.x;
+  if (c >= *ncl) return;
+  const int j0 = cl[c], j1 = cl[c + 1];
+  double* u0 = scratch + (size_t)c * 5 * n;
+  double* u1 = u0 + n;
+  double* u2 = u1 + n;
+  double* lm = u2 + n;
+  int* piv = reinterpret_cast<int*>(lm + n);
+  const double tnorm = *tnorm_p;
+  const double eps = DBL_EPSILON;
+  const double pertol = 10.0 * eps * fmax(tnorm, DBL_MIN);
+  for (int j = j0; j < j1; ++j) {
+    double lam = w[j];
+    if (threadIdx.x == 0) {
+      if (j > j0 && lam - lam_prev < pertol) lam = lam_prev + pertol;
+      lam_prev = lam;
+    }
+    __syncthreads();
+    lam = lam_prev;
+    double* x = Z + (int64_t)j * ldz;
+    // LU factorisation of T - lam I with partial pivoting (thread 0)
+    if (threadIdx.x == 0) {
+      const double small = eps * fmax(tnorm, DBL_MIN);
+      for (int i = 0; i < n; ++i) {
+        u0[i] = d[i] - lam;
+        u1[i] = (i + 1 < n) ? e[i] : 0.0;
+        u2[i] = 0.0;
+      }
+      for (int i = 0; i + 1 < n; ++i) {
+        const double b = e[i];
+        if (fabs(u0[i]) >= fabs(b)) {
+          const double piv0 = (u0[i] == 0.0) ? small : u0[i];
+          u0[i] = piv0;
+          const double l = b / piv0;
+          lm[i] = l;
+          piv[i] = 0;
+          u0[i + 1] -= l * u1[i];
+        } else {
+          const double l = u0[i] / b;
+          lm[i] = l;
+          piv[i] = 1;
+          const double a1 = u0[i + 1], c1 = u1[i + 1];
+          const double old_u1 = u1[i];
+          u0[i] = b;
+          u1[i] = a1;
+          u2[i] = c1;
+          u0[i + 1] = old_u1 - l * a1;
+          u1[i + 1] = -l * c1;
+        }
+      }
+      if (u0[n - 1] == 0.0) u0[n - 1] = small;
+      // deterministic start vector
+      for (int i = 0; i < n; ++i) {
+        unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)(j * 40503u + 12345u);
+        h ^= h >> 13; h *= 0x5bd1e995u; h ^= h >> 15;
+        x[i] = 0.5 + (double)(h & 0xffff) / 65536.0;
+      }
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 3; ++sweep) {
+      if (threadIdx.x == 0) {
+        for (int i = 0; i + 1 < n; ++i) {
+          if (piv[i] == 0) {
+            x[i + 1] -= lm[i] * x[i];
+          } else {
+            const double t0 = x[i], t1 = x[i + 1];
+            x[i] = t1;
+            x[i + 1] = t0 - lm[i] * t1;
+          }
+        }
+        x[n - 1] = x[n - 1] / u0[n - 1];
+        if (n > 1) x[n - 2] = (x[n - 2] - u1[n - 2] * x[n - 1]) / u0[n - 2];
+        for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / u0[i];
+      }
+      __syncthreads();
+      // scale to avoid growth, then MGS against earlier vectors of the cluster
+      double mx = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(x[i]));
+      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = mx;
+      __syncthreads();
+      mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      __syncthreads();
+      const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= sc;
+      __syncthreads();
+      for (int p = j0; p < j; ++p) {
+        const double* zp = Z + (int64_t)p * ldz;
+        double dot = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) dot += zp[i] * x[i];
+        dot = block_sum(dot, red);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] -= dot * zp[i];
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) nn += x[i] * x[i];
+      nn = block_sum(nn, red);
+      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= inv;
+      __syncthreads();
+    }
+  }
+}
+
+// C[:, j] = Q Z_T[:, j], Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H.
+__global__ void __launch_bounds__(256)
+k_backtransform(const double2* __restrict__ K, int ldk, int n, const double2* __restrict__ tau,
+                const double* __restrict__ Z, int ldz, double2* __restrict__ C, int ldc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* z = reinterpret_cast<double2*>(smem_raw);
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) z[i] = make_double2(Z[i + (int64_t)j * ldz], 0.0);
+  __syncthreads();
+  for (int k = n - 2; k >= 0; --k) {
+    const double2 t = tau[k];
+    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
+    const double2* v = K + (k + 1) + (int64_t)k * ldk;
+    const int len = n - k - 1;
+    double sr = 0.0, si = 0.0;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double2 a = v[i], b = z[k + 1 + i];
+      sr += a.x * b.x + a.y * b.y;  // conj(v) z
+      si += a.x * b.y - a.y * b.x;
+    }
+    sr = block_sum(sr, red);
+    si = block_sum(si, red);
+    // f = tau * (v^H z)
+    const double fr = t.x * sr - t.y * si, fi = t.x * si + t.y * sr;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double2 a = v[i];
+      double2 b = z[k + 1 + i];
+      b.x -= fr * a.x - fi * a.y;
+      b.y -= fr * a.y + fi * a.x;
+      z[k + 1 + i] = b;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) C[i + (int64_t)j * ldc] = z[i];
+}
+
+// ---------------------------------------------------------------- hegv
+struct HegvWs {
+  void* potrf;
+  double2* K;
+  double2* y;
+  double2* tau;
+  double* d;
+  double* e;
+  double* tnorm;
+  int32_t* cl;
+  int32_t* ncl;
+  double* Z;
+  double* scratch;
+  double2* tmp;
+};
+
+static HegvWs hegv_ws(void* work, int n, int nev) {
+  char* p = static_cast<char*>(work);
+  HegvWs w;
+  w.potrf = p; p += al(potrf_work(n));
+  w.K = reinterpret_cast<double2*>(p); p += al((size_t)n * n * sizeof(double2));
+  w.y = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
+  w.tau = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
+  w.d = reinterpret_cast<double*>(p); p += al((size_t)n * 8);
+  w.e = reinterpret_cast<double*>(p); p += al((size_t)n * 8);
+  w.tnorm = reinterpret_cast<double*>(p); p += 256;
+  w.cl = reinterpret_cast<int32_t*>(p); p += al((size_t)(nev + 1) * 4);
+  w.ncl = reinterpret_cast<int32_t*>(p); p += 256;
+  w.Z = reinterpret_cast<double*>(p); p += al((size_t)n * nev * 8);
+  w.scratch = reinterpret_cast<double*>(p); p += al((size_t)nev * 5 * n * 8);
+  w.tmp = reinterpret_cast<double2*>(p); p += al((size_t)NB * n * sizeof(double2));
+  return w;
+}
+
+size_t hegv_work(int n, int nev) {
+  return al(potrf_work(n)) + al((size_t)n * n * 16) + 2 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
+         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)nev * 5 * n * 8) +
+         al((size_t)NB * n * 16);
+}
+
+int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, double2* C, int ldc, void* work,
+         int32_t* info, hipStream_t s) {
+  HegvWs ws = hegv_ws(work, n, nev);
+  TimerScope ts(KF_HEGV, s);
+  int rc;
+  if ((rc = potrf_impl(n, S, lds_, ws.potrf, info, n, s))) return rc;
+  // Y = L^-1 H (in H)
+  if ((rc = trsm('N', n, n, S, lds_, H, ldh, ws.potrf, ws.tmp, info, s))) return rc;
+  // K = L^-1 Y^H
+  dim3 tg((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32));
+  hipLaunchKernelGGL(k_conj_transpose, tg, dim3(256), 0, s, H, ldh, ws.K, n, n);
+  KS_LAUNCH_CHECK("conj_transpose");
+  if ((rc = trsm('N', n, n, S, lds_, ws.K, n, ws.potrf, ws.tmp, info, s))) return rc;
+  hipLaunchKernelGGL(k_hermitise, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)), dim3(256),
+                     0, s, ws.K, n, n);
+  KS_LAUNCH_CHECK("hermitise");
+  // Householder tridiagonalisation, one column per step
+  for (int k = 0; k + 1 < n; ++k) {
+    const int len = n - k - 1;
+    hipLaunchKernelGGL(k_house, dim3(1), dim3(256), 0, s, ws.K, n, n, k, ws.tau, ws.d, ws.e);
+    hipLaunchKernelGGL(k_hemv, dim3((unsigned)ceil_div(len, 16)), dim3(256), 0, s, ws.K, n, n, k, ws.y);
+    hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
+                       ws.K, n, n, k, ws.y, ws.tau);
+  }
+  KS_LAUNCH_CHECK("tridiagonalisation");
+  hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
+  hipLaunchKernelGGL(k_bisect, dim3((unsigned)ceil_div(nev, 64)), dim3(64), 0, s, ws.d, ws.e, n, nev, w, ws.tnorm);
+  hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, w, nev, ws.tnorm, ws.cl, ws.ncl);
+  hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), 0, s, ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl,
+                     ws.Z, n, ws.scratch);
+  KS_LAUNCH_CHECK("bisection / inverse iteration");
+  hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(256), (size_t)n * sizeof(double2), s, ws.K, n, n, ws.tau,
+                     ws.Z, n, C, ldc);
+  KS_LAUNCH_CHECK("backtransform");
+  // C = L^-H Z
+  return trsm('C', n, nev, S, lds_, C, ldc, ws.potrf, ws.tmp, info, s);
+}
+
+}  // namespace ks

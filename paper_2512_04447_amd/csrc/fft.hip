@@ -1,0 +1,621 @@
+// Batched 3D FFT Hamiltonian application and Teter-Payne-Allan
+// preconditioner for gfx950.
+//
+// The paper applies the kinetic term through FFTs over all orbitals at once
+// (task (1) of the SCF task list; the FFT figure shows batching is what makes
+// GPUs win).  Here a 3D transform of one band is split into three passes
+// over HBM, each staging tiles in LDS:
+//   pass A: per (band, x-plane): z- then y-transforms of the n1 x n2 plane;
+//   pass B: per (band, y, z-chunk): x-transform of an x-pencil tile, a
+//           spectral multiply, then the inverse x-transform;
+//   pass C: per (band, x-plane): inverse y- and z-transforms, 1/Ng, and an
+//           epilogue (local potential and nonlocal scatter for H, lock mask
+//           for the preconditioner).
+// Each 1D transform is a mixed-radix (2, 3, 4, 5, 7) Stockham autosort FFT
+// done in place in LDS: a stage reads its butterfly inputs into registers,
+// barriers, then writes the outputs to their autosorted positions.  The
+// inverse transform is conj(FFT(conj(.))).
+#include <cmath>
+
+#include "ks_plan.hpp"
+
+namespace ks {
+
+// ---------------------------------------------------------------- radices
+template <typename T2> __device__ inline T2 mul_minus_i(T2 a) { return cmake<T2>(a.y, -a.x); }
+
+template <int R, typename T2> struct Dft;
+
+template <typename T2> struct Dft<2, T2> {
+  __device__ static void run(T2* a) {
+    T2 t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  }
+};
+
+template <typename T2> struct Dft<3, T2> {
+  __device__ static void run(T2* a) {
+    using T = decltype(a[0].x);
+    const T s1 = T(-0.86602540378443864676);  // sin(-2 pi / 3)
+    T2 t1 = cadd(a[1], a[2]);
+    T2 t2 = csub(a[1], a[2]);
+    T2 y0 = cadd(a[0], t1);
+    T2 m1 = csub(a[0], cscale(t1, T(0.5)));
+    T2 m2 = cmake<T2>(-s1 * t2.y, s1 * t2.x);  // i * s1 * t2
+    a[0] = y0;
+    a[1] = cadd(m1, m2);
+    a[2] = csub(m1, m2);
+  }
+};
+
+template <typename T2> struct Dft<4, T2> {
+  __device__ static void run(T2* a) {
+    T2 t0 = cadd(a[0], a[2]);
+    T2 t1 = csub(a[0], a[2]);
+    T2 t2 = cadd(a[1], a[3]);
+    T2 t3 = mul_minus_i(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+// Odd radix by symmetric pairs: with s_q = a_q + a_{R-q}, d_q = a_q - a_{R-q},
+// y_k = a_0 + sum_q s_q cos(2 pi q k/R) - i sum_q d_q sin(2 pi q k/R) and
+// y_{R-k} the same with +i.
+template <int R> struct OddRoots;
+template <> struct OddRoots<5> {
+  static constexpr double c[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410,
+                                  -0.80901699437494742410, 0.30901699437494742410};
+  static constexpr double s[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917,
+                                  -0.58778525229247312917, -0.95105651629515357212};
+};
+template <> struct OddRoots<7> {
+  static constexpr double c[7] = {1.0, 0.62348980185873353053, -0.22252093395631440429,
+                                  -0.90096886790241912624, -0.90096886790241912624,
+                                  -0.22252093395631440429, 0.62348980185873353053};
+  static constexpr double s[7] = {0.0, 0.78183148246802980871, 0.97492791218182360702,
+                                  0.43388373911755812048, -0.43388373911755812048,
+                                  -0.97492791218182360702, -0.78183148246802980871};
+};
+
+template <int R, typename T2> struct DftOdd {
+  __device__ static void run(T2* a) {
+    using T = decltype(a[0].x);
+    constexpr int H = (R - 1) / 2;
+    T2 sq[H], dq[H];
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      sq[q - 1] = cadd(a[q], a[R - q]);
+      dq[q - 1] = csub(a[q], a[R - q]);
+    }
+    T2 y0 = a[0];
+#pragma unroll
+    for (int q = 0; q < H; ++q) y0 = cadd(y0, sq[q]);
+    T2 out[R];
+    out[0] = y0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      T2 A = a[0];
+      T2 B = cmake<T2>(T(0), T(0));
+#pragma unroll
+      for (int q = 1; q <= H; ++q) {
+        const int idx = (q * k) % R;
+        const T c = T(OddRoots<R>::c[idx]);
+        const T s = T(OddRoots<R>::s[idx]);
+        A = cadd(A, cscale(sq[q - 1], c));
+        B = cadd(B, cscale(dq[q - 1], s));
+      }
+      // y_k = A - i B, y_{R-k} = A + i B
+      out[k] = cmake<T2>(A.x + B.y, A.y - B.x);
+      out[R - k] = cmake<T2>(A.x - B.y, A.y + B.x);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = out[k];
+  }
+};
+template <typename T2> struct Dft<5, T2> : DftOdd<5, T2> {};
+template <typename T2> struct Dft<7, T2> : DftOdd<7, T2> {};
+
+// ---------------------------------------------------------------- Stockham
+// One radix-R stage over `nbatch` transforms of length n stored in LDS with
+// element stride es and batch stride bs.  Ns = product of earlier radices.
+// Twiddle for input q of butterfly j: exp(-2 pi i q (j mod Ns) / (Ns R)),
+// read from tw[t] = exp(-2 pi i t / n) at t = q (j mod Ns) n/(Ns R) < n.
+template <int R, int MAXE, typename T2>
+__device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, int Ns,
+                                      const T2* __restrict__ tw) {
+  constexpr int NBF = (MAXE + R - 1) / R;
+  const int nbf = n / R;
+  const int total = nbatch * nbf;
+  const int tstep = n / (Ns * R);
+  T2 v[NBF][R];
+  int dst[NBF];
+#pragma unroll
+  for (int u = 0; u < NBF; ++u) {
+    const int w = threadIdx.x + u * blockDim.x;
+    dst[u] = -1;
+    if (w < total) {
+      const int b = w / nbf;
+      const int j = w - b * nbf;
+      const int k = j % Ns;
+      const T2* base = s + b * bs;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        T2 a = base[(j + q * nbf) * es];
+        if (q > 0 && k > 0) a = cmul(a, tw[q * k * tstep]);
+        v[u][q] = a;
+      }
+      Dft<R, T2>::run(v[u]);
+      dst[u] = b * bs + ((j / Ns) * Ns * R + k) * es;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NBF; ++u) {
+    if (dst[u] >= 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) s[dst[u] + q * Ns * es] = v[u][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <int MAXE, typename T2>
+__device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, int bs,
+                                 const T2* __restrict__ tw) {
+  int Ns = 1;
+  for (int st = 0; st < ap.nst; ++st) {
+    const int R = ap.rad[st];
+    switch (R) {
+      case 2: stockham_stage<2, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 3: stockham_stage<3, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 4: stockham_stage<4, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 5: stockham_stage<5, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 7: stockham_stage<7, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+__device__ inline int wrap_m(int k, int n) { return (2 * k < n) ? k : k - n; }
+
+// ---------------------------------------------------------------- pass A
+// MODE 0: load psi.  MODE 1: load r = ax - theta x and write per-plane
+// partial sums of |r|^2 to partial[band*n0 + x].
+template <typename T, int MAXE, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
+         const double* __restrict__ theta, int64_t ld, c2<T>* __restrict__ dst, int64_t ldd,
+         const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, double* __restrict__ partial) {
+  using T2 = c2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* s = reinterpret_cast<T2*>(smem_raw);
+  __shared__ double red[kThreads / kWave];
+  const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  const int plane = n1 * n2;
+  const int band = blockIdx.x / n0;
+  const int x = blockIdx.x - band * n0;
+  const int64_t off = (int64_t)x * plane;
+  const T2* in = src + band * ld + off;
+  double acc = 0.0;
+  if (MODE == 1) {
+    const T2* in2 = src2 + band * ld + off;  // x
+    const T th = T(theta[band]);
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      T2 a = in[i];
+      T2 b = in2[i];
+      T2 r = cmake<T2>(a.x - th * b.x, a.y - th * b.y);
+      acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      s[i] = r;
+    }
+  } else {
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) s[i] = in[i];
+  }
+  __syncthreads();
+  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, tw2);  // z rows
+  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, tw1);  // y columns
+  T2* out = dst + band * ldd + off;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = s[i];
+  if (MODE == 1) {
+    double t = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------- pass B
+// MODE 0: multiply by T(G) = |G|^2/2.  MODE 1: multiply by the TPA factor
+// K(T(G)/E_band).  MODE 2: no inverse; partial[block] = sum T(G)|f(G)|^2.
+template <typename T>
+__device__ inline T kinetic_of(const Fft3& f, int kx, int ky, int kz) {
+  const T gx = T(f.twopi_over_L[0]) * T(wrap_m(kx, f.ax[0].n));
+  const T gy = T(f.twopi_over_L[1]) * T(wrap_m(ky, f.ax[1].n));
+  const T gz = T(f.twopi_over_L[2]) * T(wrap_m(kz, f.ax[2].n));
+  return T(0.5) * (gx * gx + gy * gy + gz * gz);
+}
+
+template <typename T> __device__ inline T tpa_factor(T x) {
+  const T num = T(27) + x * (T(18) + x * (T(12) + x * T(8)));
+  return num / (num + T(16) * x * x * x * x);
+}
+
+template <typename T, int MAXE, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __restrict__ tw0,
+         const double* __restrict__ E, double* __restrict__ partial) {
+  using T2 = c2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* s = reinterpret_cast<T2*>(smem_raw);
+  __shared__ double red[kThreads / kWave];
+  const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  const int nzc = n2 / zc;
+  int bid = blockIdx.x;
+  const int zt = bid % nzc; bid /= nzc;
+  const int y = bid % n1;
+  const int band = bid / n1;
+  const int z0 = zt * zc;
+  T2* base = buf + band * ld + (int64_t)y * n2 + z0;
+  const int64_t xs = (int64_t)n1 * n2;
+  const int tile = n0 * zc;
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int x = i / zc, z = i - x * zc;
+    s[i] = base[x * xs + z];
+  }
+  __syncthreads();
+  fft_batch<MAXE>(s, zc, f.ax[0], zc, 1, tw0);
+  if (MODE == 2) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int kx = i / zc, z = i - kx * zc;
+      const double t = (double)kinetic_of<T>(f, kx, y, z0 + z);
+      acc += t * ((double)s[i].x * s[i].x + (double)s[i].y * s[i].y);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    return;
+  }
+  const T einv = (MODE == 1) ? T(1.0 / E[band]) : T(0);
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int kx = i / zc, z = i - kx * zc;
+    const T t = kinetic_of<T>(f, kx, y, z0 + z);
+    const T fac = (MODE == 0) ? t : tpa_factor<T>(t * einv);
+    T2 v = s[i];
+    s[i] = cmake<T2>(v.x * fac, -v.y * fac);  // conj for the inverse transform
+  }
+  __syncthreads();
+  fft_batch<MAXE>(s, zc, f.ax[0], zc, 1, tw0);
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int x = i / zc, z = i - x * zc;
+    T2 v = s[i];
+    base[x * xs + z] = cmake<T2>(v.x, -v.y);
+  }
+}
+
+// ---------------------------------------------------------------- pass C
+// The input plane holds conj-free spectral data in (y, z); the inverse is
+// conj(FFT(conj(.))) / Ng.
+// MODE 0 (H): out = Tpsi + V psi + sum_e beta_e dc[band][proj_e].
+// MODE 1 (preconditioner): out = mask[band] * IFFT(.), mask from res > lock_tol.
+template <typename T, int MAXE, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict__ dst, int64_t ldd,
+         const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, const T* __restrict__ V,
+         const c2<T>* __restrict__ psi, int64_t ldp, const int32_t* __restrict__ pt_ptr,
+         const int32_t* __restrict__ pt_proj, const T* __restrict__ pt_beta,
+         const c2<T>* __restrict__ dc, int nproj, const double* __restrict__ res, double lock_tol) {
+  using T2 = c2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* s = reinterpret_cast<T2*>(smem_raw);
+  const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  const int plane = n1 * n2;
+  const int band = blockIdx.x / n0;
+  const int x = blockIdx.x - band * n0;
+  const int64_t off = (int64_t)x * plane;
+  const T2* in = src + band * lds_ + off;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) s[i] = cconj(in[i]);
+  __syncthreads();
+  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, tw1);  // y columns
+  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, tw2);  // z rows
+  const T scale = T(1.0 / ((double)n0 * (double)n1 * (double)n2));
+  T2* out = dst + band * ldd + off;
+  if (MODE == 0) {
+    const T2* ps = psi + band * ldp + off;
+    const T2* dcb = dc + (int64_t)band * nproj;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      const int64_t r = off + i;
+      T2 t = s[i];
+      T2 p = ps[i];
+      const T vr = V[r];
+      T ox = t.x * scale + vr * p.x;
+      T oy = -t.y * scale + vr * p.y;
+      if (pt_ptr != nullptr) {
+        const int e0 = pt_ptr[r], e1 = pt_ptr[r + 1];
+        for (int e = e0; e < e1; ++e) {
+          const T b = pt_beta[e];
+          const T2 c = dcb[pt_proj[e]];
+          ox += b * c.x;
+          oy += b * c.y;
+        }
+      }
+      out[i] = cmake<T2>(ox, oy);
+    }
+  } else {
+    const T m = (res[band] > lock_tol) ? scale : T(0);
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      T2 t = s[i];
+      out[i] = cmake<T2>(t.x * m, -t.y * m);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- nonlocal
+// Projection c[band][p] = sum_{s in S_a} beta_p(s) psi_band(s), scaled by D_p.
+// One block per (atom, tile of NBT bands); the support list is streamed
+// once per tile and every psi value feeds all projectors of the atom.
+// The block reduction is a fixed tree (deterministic).
+template <typename T, int MAXP, int NBT>
+__global__ void __launch_bounds__(kThreads)
+k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* __restrict__ supp_ptr,
+             const int32_t* __restrict__ supp_idx, const int32_t* __restrict__ proj_ptr,
+             const int64_t* __restrict__ beta_ptr, const T* __restrict__ beta,
+             const T* __restrict__ D, c2<T>* __restrict__ dc, int nproj) {
+  using T2 = c2<T>;
+  __shared__ double red[kThreads / kWave][MAXP * NBT * 2];
+  const int a = blockIdx.x;
+  const int b0 = blockIdx.y * NBT;
+  const int s0 = supp_ptr[a];
+  const int ns = supp_ptr[a + 1] - s0;
+  const int p0 = proj_ptr[a];
+  const int np = proj_ptr[a + 1] - p0;
+  const T* bet = beta + beta_ptr[a];
+  double acc[MAXP][NBT][2];
+#pragma unroll
+  for (int j = 0; j < MAXP; ++j)
+#pragma unroll
+    for (int b = 0; b < NBT; ++b) acc[j][b][0] = acc[j][b][1] = 0.0;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    const int idx = supp_idx[s0 + s];
+    T2 pv[NBT];
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+      pv[b] = (b0 + b < nb) ? psi[(int64_t)(b0 + b) * ld + idx] : cmake<T2>(T(0), T(0));
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      if (j < np) {
+        const double bv = (double)bet[(int64_t)j * ns + s];
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) {
+          acc[j][b][0] += bv * (double)pv[b].x;
+          acc[j][b][1] += bv * (double)pv[b].y;
+        }
+      }
+    }
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < MAXP; ++j)
+#pragma unroll
+    for (int b = 0; b < NBT; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double v = wave_sum(acc[j][b][c]);
+        if (lane == 0) red[wid][(j * NBT + b) * 2 + c] = v;
+      }
+  __syncthreads();
+  const int nw = blockDim.x / kWave;
+  for (int t = threadIdx.x; t < np * NBT; t += blockDim.x) {
+    const int j = t / NBT, b = t - j * NBT;
+    if (b0 + b >= nb) continue;
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      re += red[w][(j * NBT + b) * 2 + 0];
+      im += red[w][(j * NBT + b) * 2 + 1];
+    }
+    const double d = (double)D[p0 + j];
+    dc[(int64_t)(b0 + b) * nproj + p0 + j] = cmake<T2>(T(d * re), T(d * im));
+  }
+}
+
+// ---------------------------------------------------------------- reduce
+// out[b] = scale * sum_{i<cnt} partial[b*cnt + i], sequential (deterministic).
+__global__ void k_row_sum(const double* __restrict__ partial, int cnt, int nb, double scale,
+                          int take_sqrt, double* __restrict__ out) {
+  __shared__ double red[kThreads / kWave];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) acc += partial[(int64_t)b * cnt + i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) out[b] = take_sqrt ? sqrt(acc * scale) : acc * scale;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int MAXE>
+static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2,
+                          const double* theta, int64_t ld, c2<T>* dst, int64_t ldd, int nb,
+                          double* partial, hipStream_t s) {
+  const auto* tw1 = static_cast<const c2<T>*>(p.tw[1]);
+  const auto* tw2 = static_cast<const c2<T>*>(p.tw[2]);
+  dim3 grid(nb * p.fft.ax[0].n);
+  TimerScope ts(KF_PASS_A, s);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, src2,
+                       theta, ld, dst, ldd, tw1, tw2, partial);
+  else
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, src2,
+                       theta, ld, dst, ldd, tw1, tw2, partial);
+  KS_LAUNCH_CHECK("pass A");
+  return 0;
+}
+
+template <typename T>
+static int pass_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2, const double* theta,
+                  int64_t ld, c2<T>* dst, int64_t ldd, int nb, double* partial, hipStream_t s) {
+  switch (p.maxe_plane) {
+    case 4: return launch_plane_a<T, 4>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 16: return launch_plane_a<T, 16>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 48: return launch_plane_a<T, 48>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 64: return launch_plane_a<T, 64>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    default: return fail(KS_E_UNSUPPORTED, "plane too large for the LDS FFT");
+  }
+}
+
+template <typename T, int MAXE>
+static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst,
+                          int64_t ldd, int nb, const T* V, const c2<T>* psi, int64_t ldp,
+                          const c2<T>* dc, const double* res, double lock_tol, hipStream_t s) {
+  const auto* tw1 = static_cast<const c2<T>*>(p.tw[1]);
+  const auto* tw2 = static_cast<const c2<T>*>(p.tw[2]);
+  dim3 grid(nb * p.fft.ax[0].n);
+  TimerScope ts(KF_PASS_C, s);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
+                       dst, ldd, tw1, tw2, V, psi, ldp, p.nproj ? p.pt_ptr : nullptr, p.pt_proj,
+                       static_cast<const T*>(p.pt_beta), dc, p.nproj, res, lock_tol);
+  else
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
+                       dst, ldd, tw1, tw2, V, psi, ldp, nullptr, nullptr, (const T*)nullptr, dc, 0, res,
+                       lock_tol);
+  KS_LAUNCH_CHECK("pass C");
+  return 0;
+}
+
+template <typename T>
+static int pass_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst, int64_t ldd,
+                  int nb, const T* V, const c2<T>* psi, int64_t ldp, const c2<T>* dc,
+                  const double* res, double lock_tol, hipStream_t s) {
+  switch (p.maxe_plane) {
+    case 4: return launch_plane_c<T, 4>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 16: return launch_plane_c<T, 16>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 48: return launch_plane_c<T, 48>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 64: return launch_plane_c<T, 64>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    default: return fail(KS_E_UNSUPPORTED, "plane too large for the LDS FFT");
+  }
+}
+
+template <typename T>
+static int pass_b(const ks_plan& p, int mode, c2<T>* buf, int64_t ld, int nb, const double* E,
+                  double* partial, hipStream_t s) {
+  const auto* tw0 = static_cast<const c2<T>*>(p.tw[0]);
+  const int n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
+  dim3 grid(nb * n1 * (n2 / p.zc));
+  TimerScope ts(KF_PASS_B, s);
+  if (p.maxe_pencil != 16) return fail(KS_E_UNSUPPORTED, "pencil tile size");
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 0>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 1>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 2>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+  }
+  KS_LAUNCH_CHECK("pass B");
+  return 0;
+}
+
+template <typename T>
+static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2<T>* dc, hipStream_t s) {
+  constexpr int NBT = 4;
+  dim3 grid(p.natoms, (unsigned)ceil_div(nb, NBT));
+  TimerScope ts(KF_NL_PROJECT, s);
+  const T* beta = static_cast<const T*>(p.beta);
+  const T* D = static_cast<const T*>(p.Dcoef);
+  if (p.maxp <= 1)
+    hipLaunchKernelGGL((k_nl_project<T, 1, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
+                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+  else if (p.maxp <= 4)
+    hipLaunchKernelGGL((k_nl_project<T, 4, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
+                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+  else if (p.maxp <= 9)
+    hipLaunchKernelGGL((k_nl_project<T, 9, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
+                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+  else
+    return fail(KS_E_UNSUPPORTED, "more than 9 projectors per atom");
+  KS_LAUNCH_CHECK("nl_project");
+  return 0;
+}
+
+template <typename T>
+int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* hpsi, int64_t ldh, int nb,
+            c2<T>* tmp, c2<T>* dc, hipStream_t s) {
+  int rc;
+  const int64_t ldt = p.Ng;
+  if (p.nproj > 0 && (rc = nl_project<T>(p, psi, ldp, nb, dc, s))) return rc;
+  if ((rc = pass_a<T>(p, 0, psi, nullptr, nullptr, ldp, tmp, ldt, nb, nullptr, s))) return rc;
+  if ((rc = pass_b<T>(p, 0, tmp, ldt, nb, nullptr, nullptr, s))) return rc;
+  return pass_c<T>(p, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s);
+}
+
+template <typename T>
+int kinetic_energy(const ks_plan& p, const c2<T>* X, int64_t ld, int nb, c2<T>* tmp, double* partial,
+                   double* E, hipStream_t s) {
+  int rc;
+  const int64_t ldt = p.Ng;
+  if ((rc = pass_a<T>(p, 0, X, nullptr, nullptr, ld, tmp, ldt, nb, nullptr, s))) return rc;
+  if ((rc = pass_b<T>(p, 2, tmp, ldt, nb, nullptr, partial, s))) return rc;
+  const int cnt = p.fft.ax[1].n * (p.fft.ax[2].n / p.zc);
+  hipLaunchKernelGGL(k_row_sum, dim3(nb), dim3(kThreads), 0, s, partial, cnt, nb, 1.0 / (double)p.Ng, 0, E);
+  KS_LAUNCH_CHECK("row_sum");
+  return 0;
+}
+
+template <typename T>
+int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, const double* theta,
+                  int64_t ld, int nb, double lock_tol, c2<T>* W, double* res, c2<T>* tmp, double* partial,
+                  double* E, hipStream_t s) {
+  int rc;
+  const int64_t ldt = p.Ng;
+  if (kind == KS_PRECOND_TPA) {
+    if ((rc = kinetic_energy<T>(p, X, ld, nb, tmp, partial, E, s))) return rc;
+  }
+  // residual, its norms, and the forward (y,z) transform in one pass
+  if ((rc = pass_a<T>(p, 1, AX, X, theta, ld, tmp, ldt, nb, partial, s))) return rc;
+  hipLaunchKernelGGL(k_row_sum, dim3(nb), dim3(kThreads), 0, s, partial, p.fft.ax[0].n, nb, 1.0, 1, res);
+  KS_LAUNCH_CHECK("row_sum");
+  // identity preconditioner: the (y,z) forward and inverse passes cancel
+  if (kind == KS_PRECOND_TPA) {
+    if ((rc = pass_b<T>(p, 1, tmp, ldt, nb, E, nullptr, s))) return rc;
+  }
+  return pass_c<T>(p, 1, tmp, ldt, W, ld, nb, nullptr, nullptr, 0, nullptr, res, lock_tol, s);
+}
+
+size_t apply_h_work_bytes(const ks_plan& p, int nb) {
+  const size_t es = p.prec == KS_FP64 ? 16 : 8;
+  size_t tmp = (size_t)p.Ng * nb * es;
+  size_t dc = (size_t)nb * (p.nproj > 0 ? p.nproj : 1) * es;
+  return ((tmp + 255) / 256) * 256 + ((dc + 255) / 256) * 256;
+}
+
+size_t precond_work_bytes(const ks_plan& p, int nb) {
+  const size_t es = p.prec == KS_FP64 ? 16 : 8;
+  size_t tmp = (size_t)p.Ng * nb * es;
+  const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
+  size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p.zc));
+  size_t partial = (size_t)nb * cnt * 8;
+  size_t E = (size_t)nb * 8;
+  return ((tmp + 255) / 256) * 256 + ((partial + 255) / 256) * 256 + ((E + 255) / 256) * 256;
+}
+
+template int apply_h<double>(const ks_plan&, const double*, const double2*, int64_t, double2*, int64_t, int,
+                             double2*, double2*, hipStream_t);
+template int apply_h<float>(const ks_plan&, const float*, const float2*, int64_t, float2*, int64_t, int,
+                            float2*, float2*, hipStream_t);
+template int kinetic_energy<double>(const ks_plan&, const double2*, int64_t, int, double2*, double*, double*,
+                                    hipStream_t);
+template int kinetic_energy<float>(const ks_plan&, const float2*, int64_t, int, float2*, double*, double*,
+                                   hipStream_t);
+template int precond_apply<double>(const ks_plan&, int, const double2*, const double2*, const double*, int64_t,
+                                   int, double, double2*, double*, double2*, double*, double*, hipStream_t);
+template int precond_apply<float>(const ks_plan&, int, const float2*, const float2*, const double*, int64_t,
+                                  int, double, float2*, double*, float2*, double*, double*, hipStream_t);
+
+}  // namespace ks

@@ -1,0 +1,465 @@
+// Complex Gram and rotation GEMMs on CDNA4 MFMA (task (2) of the SCF task
+// list: the dense products that form the LOBPCG subspace matrices H and S,
+// and the rotation of the block by the Ritz coefficients).
+//
+// Complex products use four real MFMAs per 16x16x4 step on the real and
+// imaginary parts (no Gauss trick, which loses accuracy).  Operand layout of
+// v_mfma_{f64,f32}_16x16x4: lane l holds A[l%16][l/16] and B[l/16][l%16];
+// the 16x16 result sits in 4 accumulators per lane, D[4*(l/16)+v][l%16].
+#include "gemm.hpp"
+
+namespace ks {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = d4;
+  __device__ static inline acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc = f4;
+  __device__ static inline acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int TILE = 64;  // output tile edge per workgroup
+constexpr int KC = 16;    // K chunk staged in LDS
+constexpr int PAD = KC + 1;
+
+// Column c of a three-segment block list (segments of nb columns each).
+template <typename T2>
+__device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
+  const int s = c / b.nb;
+  return b.p[s] + (int64_t)(c - s * b.nb) * b.ld;
+}
+
+// ---------------------------------------------------------------- Gram
+// For upper tile (ti, tj) and K split `sp`: S_tile = A_I^H B1_J and, when
+// TWO, H_tile = A_I^H B2_J.  Partials (FP64) go to part[(sp*ntu + t)*4096 +
+// i*64 + j] (row-major within the tile).
+template <typename T, bool TWO>
+__global__ void __launch_bounds__(256)
+k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int64_t K, int64_t kper,
+       int ntile, int ntu, double2* __restrict__ partS, double2* __restrict__ partH) {
+  using T2 = c2<T>;
+  using M = Mfma<T>;
+  __shared__ T2 As[TILE][PAD];
+  __shared__ T2 Bs[TILE][PAD];
+  __shared__ T2 B2s[TWO ? TILE : 1][PAD];
+  // upper tile index -> (ti, tj), ti <= tj
+  int t = blockIdx.x;
+  int ti = 0;
+  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  const int tj = ti + t;
+  const int sp = blockIdx.y;
+  const int64_t k0 = (int64_t)sp * kper;
+  const int64_t k1 = min(K, k0 + kper);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  typename M::acc sr[2][2], si[2][2], hr[2][2], hi[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = hr[a][b][v] = hi[a][b][v] = T(0);
+  // loader: thread -> (column, 4 consecutive k)
+  const int lc = threadIdx.x >> 2;
+  const int lk = (threadIdx.x & 3) * 4;
+  const int ca = ti * TILE + lc;
+  const int cb = tj * TILE + lc;
+  const T2* pa = ca < m ? seg_col(A, ca) : nullptr;
+  const T2* pb = cb < m ? seg_col(B1, cb) : nullptr;
+  const T2* pb2 = (TWO && cb < m) ? seg_col(B2, cb) : nullptr;
+  const T2 z = cmake<T2>(T(0), T(0));
+  // FP32 products accumulate in FP32 over KFLUSH points, then in FP64.
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int KFLUSH = 256;
+  double dsr[F32 ? 2 : 1][2][4], dsi[F32 ? 2 : 1][2][4], dhr[F32 ? 2 : 1][2][4], dhi[F32 ? 2 : 1][2][4];
+  if constexpr (F32) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dsr[a][b][v] = dsi[a][b][v] = dhr[a][b][v] = dhi[a][b][v] = 0.0;
+  }
+  auto flush = [&]() {
+    if constexpr (F32) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            dsr[a][b][v] += (double)sr[a][b][v];
+            dsi[a][b][v] += (double)si[a][b][v];
+            sr[a][b][v] = si[a][b][v] = T(0);
+            if (TWO) {
+              dhr[a][b][v] += (double)hr[a][b][v];
+              dhi[a][b][v] += (double)hi[a][b][v];
+              hr[a][b][v] = hi[a][b][v] = T(0);
+            }
+          }
+    }
+  };
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+    if (F32 && kb > k0 && ((kb - k0) % KFLUSH) == 0) flush();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = kb + lk + q;
+      const bool ok = k < k1;
+      As[lc][lk + q] = (pa && ok) ? pa[k] : z;
+      Bs[lc][lk + q] = (pb && ok) ? pb[k] : z;
+      if (TWO) B2s[lc][lk + q] = (pb2 && ok) ? pb2[k] : z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T2 a[2], b[2], b2[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a[u] = As[wi * 32 + u * 16 + (lane & 15)][kr];
+        b[u] = Bs[wj * 32 + u * 16 + (lane & 15)][kr];
+        if (TWO) b2[u] = B2s[wj * 32 + u * 16 + (lane & 15)][kr];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
+          sr[u][w] = M::run(a[u].x, b[w].x, sr[u][w]);
+          sr[u][w] = M::run(a[u].y, b[w].y, sr[u][w]);
+          si[u][w] = M::run(a[u].x, b[w].y, si[u][w]);
+          si[u][w] = M::run(-a[u].y, b[w].x, si[u][w]);
+          if (TWO) {
+            hr[u][w] = M::run(a[u].x, b2[w].x, hr[u][w]);
+            hr[u][w] = M::run(a[u].y, b2[w].y, hr[u][w]);
+            hi[u][w] = M::run(a[u].x, b2[w].y, hi[u][w]);
+            hi[u][w] = M::run(-a[u].y, b2[w].x, hi[u][w]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  flush();
+  const int64_t base = ((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE);
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wi * 32 + u * 16 + 4 * (lane >> 4) + v;
+        const int j = wj * 32 + w * 16 + (lane & 15);
+        if constexpr (F32) {
+          partS[base + i * TILE + j] = make_double2(dsr[u][w][v], dsi[u][w][v]);
+          if (TWO) partH[base + i * TILE + j] = make_double2(dhr[u][w][v], dhi[u][w][v]);
+        } else {
+          partS[base + i * TILE + j] = make_double2((double)sr[u][w][v], (double)si[u][w][v]);
+          if (TWO) partH[base + i * TILE + j] = make_double2((double)hr[u][w][v], (double)hi[u][w][v]);
+        }
+      }
+}
+
+// Sum the K splits in order and write the Hermitian m x m result
+// (column-major, ldo).  Diagonal tiles are Hermitised, (G + G^H)/2.
+__global__ void __launch_bounds__(256)
+k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, int m,
+              double2* __restrict__ out, int ldo) {
+  int t = blockIdx.x;
+  int ti = 0;
+  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  const int tj = ti + t;
+  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
+    const int i = e / TILE, j = e - i * TILE;
+    const int gi = ti * TILE + i, gj = tj * TILE + j;
+    if (gi >= m || gj >= m) continue;
+    if (ti == tj && j < i) continue;  // handled by its mirror
+    double2 s = make_double2(0.0, 0.0);
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const double2 v = part[((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE) + e];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    if (ti == tj) {
+      double2 s2 = make_double2(0.0, 0.0);
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const double2 v = part[((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE) + j * TILE + i];
+        s2.x += v.x;
+        s2.y += v.y;
+      }
+      s.x = 0.5 * (s.x + s2.x);
+      s.y = 0.5 * (s.y - s2.y);
+      if (i == j) s.y = 0.0;
+    }
+    out[gi + (int64_t)gj * ldo] = s;
+    out[gj + (int64_t)gi * ldo] = make_double2(s.x, -s.y);
+  }
+}
+
+GramShape gram_shape(int m, int64_t K) {
+  GramShape g;
+  g.ntile = (int)ceil_div(m, TILE);
+  g.ntu = g.ntile * (g.ntile + 1) / 2;
+  int64_t ns = ceil_div(1024, g.ntu);
+  const int64_t kmax_split = std::max<int64_t>(1, K / 512);
+  ns = std::min<int64_t>(ns, kmax_split);
+  // keep partials (two matrices) under 256 MB
+  const int64_t cap = std::max<int64_t>(1, (int64_t)(256ll << 20) / ((int64_t)g.ntu * TILE * TILE * 16 * 2));
+  ns = std::max<int64_t>(1, std::min(ns, cap));
+  g.kper = ceil_div(ceil_div(K, ns), KC) * KC;
+  g.nsplit = (int)ceil_div(K, g.kper);
+  return g;
+}
+
+size_t gram_work_bytes(int m, int64_t K) {
+  GramShape g = gram_shape(m, K);
+  return (size_t)g.nsplit * g.ntu * TILE * TILE * sizeof(double2) * 2;
+}
+
+template <typename T>
+int gram(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m, int64_t K,
+         double2* S, int lds_, double2* H, int ldh, void* work, hipStream_t s) {
+  if (m <= 0) return 0;
+  GramShape g = gram_shape(m, K);
+  double2* partS = static_cast<double2*>(work);
+  double2* partH = partS + (size_t)g.nsplit * g.ntu * TILE * TILE;
+  dim3 grid(g.ntu, g.nsplit);
+  TimerScope ts(KF_GRAM, s);
+  if (B2)
+    hipLaunchKernelGGL((k_gram<T, true>), grid, dim3(256), 0, s, A, B1, *B2, m, K, g.kper, g.ntile, g.ntu, partS,
+                       partH);
+  else
+    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, partS,
+                       partH);
+  KS_LAUNCH_CHECK("gram");
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, S, lds_);
+  KS_LAUNCH_CHECK("gram_reduce");
+  if (B2) {
+    hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partH, g.nsplit, g.ntile, g.ntu, m, H, ldh);
+    KS_LAUNCH_CHECK("gram_reduce");
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- rotation
+// Y = V C for a block list V (Ng x m) and C (m x ncol, column-major, ldc in
+// the block precision).  Computed as Y^T = C^T V^T so that the accumulator
+// layout stores 16 consecutive grid points per band (coalesced).  When Yp
+// is given, the sum over columns [pstart, m) is stored to Yp first, then the
+// columns [0, pstart) are added and the total stored to Y.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int ldc, int ncol, int64_t Ng,
+         c2<T>* __restrict__ Y, c2<T>* __restrict__ Yp, int64_t ldy) {
+  using T2 = c2<T>;
+  using M = Mfma<T>;
+  __shared__ T2 Vs[KC][TILE + 1];  // [i][r]
+  __shared__ T2 Cs[TILE][PAD];     // [band][i]
+  const int64_t r0 = (int64_t)blockIdx.x * TILE;
+  const int b0 = blockIdx.y * TILE;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  const int wb = wave >> 1, wr = wave & 1;  // wave's band half, row half
+  typename M::acc dr[2][2], di[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dr[a][b][v] = di[a][b][v] = T(0);
+  const T2 z = cmake<T2>(T(0), T(0));
+  // loaders
+  const int vi = threadIdx.x >> 4, vr = (threadIdx.x & 15) * 4;  // V: column vi, rows vr..vr+3
+  const int cb = threadIdx.x >> 2, ci = (threadIdx.x & 3) * 4;   // C: band cb, i ci..ci+3
+  const int npass = Yp ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int lo = (Yp && pass == 0) ? pstart : 0;
+    const int hi = (Yp && pass == 0) ? m : (Yp ? pstart : m);
+    for (int c0 = lo; c0 < hi; c0 += KC) {
+      {
+        const int c = c0 + vi;
+        const T2* col = (c < hi) ? seg_col(V, c) : nullptr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = r0 + vr + q;
+          Vs[vi][vr + q] = (col && r < Ng) ? col[r] : z;
+        }
+      }
+      {
+        const int band = b0 + cb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = c0 + ci + q;
+          Cs[cb][ci + q] = (band < ncol && i < hi) ? C[i + (int64_t)band * ldc] : z;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T2 a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          a[u] = Cs[wb * 32 + u * 16 + (lane & 15)][kr];  // A = C^T: [band][i]
+          b[u] = Vs[kr][wr * 32 + u * 16 + (lane & 15)];  // B = V^T: [i][r]
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int w = 0; w < 2; ++w) {
+            // c * v: re = cr vr - ci vi, im = cr vi + ci vr
+            dr[u][w] = M::run(a[u].x, b[w].x, dr[u][w]);
+            dr[u][w] = M::run(-a[u].y, b[w].y, dr[u][w]);
+            di[u][w] = M::run(a[u].x, b[w].y, di[u][w]);
+            di[u][w] = M::run(a[u].y, b[w].x, di[u][w]);
+          }
+      }
+      __syncthreads();
+    }
+    T2* out = (Yp && pass == 0) ? Yp : Y;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int band = b0 + wb * 32 + u * 16 + 4 * (lane >> 4) + v;
+          const int64_t r = r0 + wr * 32 + w * 16 + (lane & 15);
+          if (band < ncol && r < Ng) out[(int64_t)band * ldy + r] = cmake<T2>(dr[u][w][v], di[u][w][v]);
+        }
+  }
+}
+
+template <typename T>
+int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng,
+           c2<T>* Y, c2<T>* Yp, int64_t ldy, hipStream_t s) {
+  if (ncol <= 0) return 0;
+  dim3 grid((unsigned)ceil_div(Ng, TILE), (unsigned)ceil_div(ncol, TILE));
+  TimerScope ts(KF_ROTATE, s);
+  hipLaunchKernelGGL((k_rotate<T>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy);
+  KS_LAUNCH_CHECK("rotate");
+  return 0;
+}
+
+// ---------------------------------------------------------------- zgemm
+// C = alpha op(A) op(B) + beta C, FP64 complex, column-major; op = 'N' or 'C'
+// (conjugate transpose); alpha and beta real.  For the small subspace
+// matrices of the dense solver.
+template <bool CA, bool CB>
+__global__ void __launch_bounds__(256)
+k_zgemm(int M, int N, int K, double alpha, const double2* __restrict__ A, int lda,
+        const double2* __restrict__ B, int ldb, double beta, double2* __restrict__ C, int ldc) {
+  using Mf = Mfma<double>;
+  __shared__ double2 As[KC][TILE + 1];  // [k][i]
+  __shared__ double2 Bs[TILE][PAD];     // [j][k]
+  const int i0 = blockIdx.x * TILE, j0 = blockIdx.y * TILE;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0.0;
+  const double2 z = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * TILE; e += 256) {
+      // A tile: op(A)[i][k]
+      int i, k;
+      if (!CA) { i = e % TILE; k = e / TILE; } else { k = e % KC; i = e / KC; }
+      const int gi = i0 + i, gk = k0 + k;
+      double2 v = z;
+      if (gi < M && gk < K) {
+        if (!CA) v = A[gi + (int64_t)gk * lda];
+        else { v = A[gk + (int64_t)gi * lda]; v.y = -v.y; }
+      }
+      As[k][i] = v;
+      // B tile: op(B)[k][j]
+      int j, kb;
+      if (!CB) { kb = e % KC; j = e / KC; } else { j = e % TILE; kb = e / TILE; }
+      const int gj = j0 + j, gkb = k0 + kb;
+      double2 w = z;
+      if (gj < N && gkb < K) {
+        if (!CB) w = B[gkb + (int64_t)gj * ldb];
+        else { w = B[gj + (int64_t)gkb * ldb]; w.y = -w.y; }
+      }
+      Bs[j][kb] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double2 a[2], b[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a[u] = As[kr][wi * 32 + u * 16 + (lane & 15)];
+        b[u] = Bs[wj * 32 + u * 16 + (lane & 15)][kr];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          cr[u][w] = Mf::run(a[u].x, b[w].x, cr[u][w]);
+          cr[u][w] = Mf::run(-a[u].y, b[w].y, cr[u][w]);
+          ci[u][w] = Mf::run(a[u].x, b[w].y, ci[u][w]);
+          ci[u][w] = Mf::run(a[u].y, b[w].x, ci[u][w]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wi * 32 + u * 16 + 4 * (lane >> 4) + v;
+        const int gj = j0 + wj * 32 + w * 16 + (lane & 15);
+        if (gi < M && gj < N) {
+          double2* c = C + gi + (int64_t)gj * ldc;
+          double2 o = make_double2(alpha * cr[u][w][v], alpha * ci[u][w][v]);
+          if (beta != 0.0) {
+            o.x += beta * c->x;
+            o.y += beta * c->y;
+          }
+          *c = o;
+        }
+      }
+}
+
+int zgemm(char ta, char tb, int M, int N, int K, double alpha, const double2* A, int lda, const double2* B,
+          int ldb, double beta, double2* C, int ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return 0;
+  dim3 grid((unsigned)ceil_div(M, TILE), (unsigned)ceil_div(N, TILE));
+  const bool ca = ta == 'C', cb = tb == 'C';
+  TimerScope ts(KF_ZGEMM, s);
+  if (!ca && !cb)
+    hipLaunchKernelGGL((k_zgemm<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (ca && !cb)
+    hipLaunchKernelGGL((k_zgemm<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (!ca && cb)
+    hipLaunchKernelGGL((k_zgemm<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  else
+    hipLaunchKernelGGL((k_zgemm<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  KS_LAUNCH_CHECK("zgemm");
+  return 0;
+}
+
+template int gram<double>(const BlockList<double2>&, const BlockList<double2>&, const BlockList<double2>*, int,
+                          int64_t, double2*, int, double2*, int, void*, hipStream_t);
+template int gram<float>(const BlockList<float2>&, const BlockList<float2>&, const BlockList<float2>*, int,
+                         int64_t, double2*, int, double2*, int, void*, hipStream_t);
+template int rotate<double>(const BlockList<double2>&, int, int, const double2*, int, int, int64_t, double2*,
+                            double2*, int64_t, hipStream_t);
+template int rotate<float>(const BlockList<float2>&, int, int, const float2*, int, int, int64_t, float2*, float2*,
+                           int64_t, hipStream_t);
+
+}  // namespace ks

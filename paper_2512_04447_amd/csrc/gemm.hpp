@@ -1,0 +1,52 @@
+// GEMM and dense-solver entry points shared between translation units.
+#pragma once
+
+#include <algorithm>
+
+#include "ks_plan.hpp"
+
+namespace ks {
+
+// Up to three column segments of nb columns each, sharing ld: the LOBPCG
+// basis V = [X W P] without copying it into one buffer.
+template <typename T2>
+struct BlockList {
+  const T2* p[3];
+  int64_t ld;
+  int nb;
+};
+
+struct GramShape {
+  int ntile, ntu, nsplit;
+  int64_t kper;
+};
+GramShape gram_shape(int m, int64_t K);
+size_t gram_work_bytes(int m, int64_t K);
+
+// S = A^H B1 (and H = A^H B2 when B2 != null) for the first m columns of the
+// block lists, K rows; outputs Hermitian, FP64 complex, column-major.
+template <typename T>
+int gram(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m, int64_t K,
+         double2* S, int lds, double2* H, int ldh, void* work, hipStream_t s);
+
+// Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.
+template <typename T>
+int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng, c2<T>* Y,
+           c2<T>* Yp, int64_t ldy, hipStream_t s);
+
+int zgemm(char ta, char tb, int M, int N, int K, double alpha, const double2* A, int lda, const double2* B,
+          int ldb, double beta, double2* C, int ldc, hipStream_t s);
+
+// ---- dense FP64 solver (dense.hip) ----
+size_t hegv_work(int n, int nev);
+int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds, double* w, double2* C, int ldc, void* work,
+         int32_t* info, hipStream_t s);
+// Cholesky S = L L^H in place (lower), info as for hegv (k, not n + k).
+size_t potrf_work(int n);
+int potrf(int n, double2* S, int lds, void* work, int32_t* info, hipStream_t s);
+// B <- op(L)^-1 B for the lower factor L from potrf (its workspace holds
+// the inverted diagonal blocks); op 'N' or 'C'.
+int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ldb, void* potrf_ws, void* tmp,
+         const int32_t* info, hipStream_t s);
+
+}  // namespace ks

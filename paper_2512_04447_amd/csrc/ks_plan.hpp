@@ -1,0 +1,80 @@
+// Internal plan structure and the launch functions shared between the
+// translation units of the ksh library.
+#pragma once
+
+#include <vector>
+
+#include "ks_common.hpp"
+
+namespace ks {
+
+constexpr int kMaxStages = 10;
+constexpr int kThreads = 256;
+
+// Radix schedule of one axis for the Stockham passes.
+struct AxisPlan {
+  int n;
+  int nst;
+  int rad[kMaxStages];
+};
+
+struct Fft3 {
+  AxisPlan ax[3];
+  double twopi_over_L[3];
+};
+
+}  // namespace ks
+
+struct ks_plan {
+  ks_grid grid;
+  int32_t nb_max;
+  int32_t prec;
+  int64_t Ng;
+  ks::Fft3 fft;
+  void* tw[3];   // per-axis twiddles exp(-2 pi i t/n), plan precision
+  int maxe_plane;  // elements per thread for the (y,z) plane passes
+  int maxe_pencil; // elements per thread for the x-pencil pass
+  int zc;          // z extent of one x-pencil tile
+  size_t lds_plane;
+  size_t lds_pencil;
+  // projectors
+  int32_t natoms = 0;
+  int32_t nproj = 0;
+  int32_t maxp = 0;  // max projectors per atom
+  int64_t nsupp = 0;
+  int64_t nnz = 0;   // entries of the per-point inverse table
+  int32_t* supp_ptr = nullptr;
+  int32_t* supp_idx = nullptr;
+  int32_t* proj_ptr = nullptr;
+  int64_t* beta_ptr = nullptr;
+  void* beta = nullptr;      // plan precision
+  void* Dcoef = nullptr;     // plan precision
+  int32_t* pt_ptr = nullptr; // Ng + 1
+  int32_t* pt_proj = nullptr;
+  void* pt_beta = nullptr;   // plan precision
+};
+
+namespace ks {
+
+// ---- H-apply and preconditioner (fft.hip) ----
+template <typename T>
+int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* hpsi, int64_t ldh,
+            int nb, c2<T>* tmp, c2<T>* dc, hipStream_t s);
+
+// E[b] = <x_b|T|x_b> for nb columns of X (uses tmp as scratch and
+// `partial` of nb*n0*n1 doubles).
+template <typename T>
+int kinetic_energy(const ks_plan& p, const c2<T>* X, int64_t ld, int nb, c2<T>* tmp, double* partial,
+                   double* E, hipStream_t s);
+
+// R = AX - X theta -> res norms; W = precond(R) masked by res > lock_tol.
+// partial: nb*n0 doubles; E: nb doubles (kinetic energies, TPA only).
+template <typename T>
+int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, const double* theta,
+                  int64_t ld, int nb, double lock_tol, c2<T>* W, double* res, c2<T>* tmp,
+                  double* partial, double* E, hipStream_t s);
+
+size_t apply_h_work_bytes(const ks_plan& p, int nb);
+size_t precond_work_bytes(const ks_plan& p, int nb);
+
+}  // namespace ks

