@@ -119,9 +119,12 @@ typedef struct {
   int32_t pad_;
 } ks_lobpcg_state;
 
-/* Preconditioner kinds. */
+/* Preconditioner kinds.  KS_PRECOND_CNN applies the learned network below to
+ * each residual (input channels Re r~, Im r~, h^2 (V_loc - theta_i), with
+ * r~ = r sqrt(Ng)/||r|| and h = L0/n0; output w = y0 + i y1). */
 #define KS_PRECOND_NONE 0
 #define KS_PRECOND_TPA 1
+#define KS_PRECOND_CNN 2
 
 typedef struct {
   int32_t precond;  /* KS_PRECOND_* */
@@ -129,7 +132,16 @@ typedef struct {
   /* Soft locking: a band with residual norm <= lock_tol contributes an
    * exactly-zero column to W and P (its X column stays). */
   double lock_tol;
+  const float* cnn_params; /* device, KS_CNN_NPARAM floats; KS_PRECOND_CNN only */
 } ks_lobpcg_opts;
+
+/* Learned preconditioner: three periodic 3x3x3 convolutions 3 -> 16 -> 16 -> 2
+ * with bias and SiLU between them (no activation after the last).  Parameter
+ * vector (FP32): w1[16][3][27], b1[16], w2[16][16][27], b2[16], w3[2][16][27],
+ * b3[2], with w[o][i][(dx+1)*9 + (dy+1)*3 + dz+1] weighting in[i](x+dx, y+dy,
+ * z+dz) (cross-correlation, periodic).  Activations FP32, layout
+ * [sample][channel][Ng]. */
+#define KS_CNN_NPARAM 9106
 
 /* Which operation a workspace query is for. */
 #define KS_OP_APPLY_H 1
@@ -200,6 +212,45 @@ int lobpcg_init(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st, voi
  * solve back to the host. */
 int lobpcg_step(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st,
                 const ks_lobpcg_opts* opts, void* work, size_t work_bytes, void* stream);
+
+/* Training targets for the learned preconditioner: for every column i at
+ * once, solve the Jacobi-Davidson correction equation
+ *   P (H - theta_i) P t_i = P r_i,  P = I - X X^H,  t_i in range(P)
+ * by conjugate gradients (X: nb orthonormal columns, e.g. the current Ritz
+ * block; R: right-hand sides; T: output; all with leading dimension ld).
+ * A column stops when ||residual|| <= rtol ||P r_i|| or its curvature
+ * p^H A p is not positive.  iters[i] (device int32) receives the iterations
+ * used, negated for a curvature stop.  Reads a 4-byte count back every 16
+ * iterations to stop early.  Workspace: ks_workspace_size(KS_OP_JD). */
+#define KS_OP_JD 4
+int ks_jd_correction(const ks_plan* plan, const void* v_loc, const void* X, const double* theta,
+                     const void* R, int64_t ld, int32_t nb, int32_t maxit, double rtol, void* T,
+                     int32_t* iters, void* work, size_t work_bytes, void* stream);
+
+/* Learned-preconditioner training kernels (FP32 activations and weights,
+ * FP64 reductions).  cnn_workspace_size: floats of forward activations kept
+ * for backward (act_floats) and bytes of backward workspace for nbatch
+ * samples on the plan's grid. */
+int cnn_workspace_size(const ks_plan* plan, int32_t nbatch, size_t* act_floats, size_t* work_bytes);
+/* y[nbatch][2][Ng] = net(x[nbatch][3][Ng]); acts receives the activations. */
+int cnn_forward(const ks_plan* plan, const float* params, int32_t nbatch, const float* x, float* y,
+                float* acts, void* stream);
+/* grads[KS_CNN_NPARAM] = dL/dparams given gy = dL/dy (overwritten, not
+ * accumulated); sums over samples and grid points in a fixed order. */
+int cnn_backward(const ks_plan* plan, const float* params, int32_t nbatch, const float* x,
+                 const float* acts, const float* gy, float* grads, void* work, size_t work_bytes,
+                 void* stream);
+/* Scale-invariant loss per sample, loss[b] = ||y_b/|y_b| - t_b/|t_b| ||^2,
+ * and gy = d(mean_b loss_b)/dy.  sums: 3*nbatch doubles of scratch. */
+int cnn_loss(int32_t nbatch, int64_t Ng, const float* y, const float* t, float* gy, double* loss,
+             double* sums, void* stream);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8); t >= 1. */
+int cnn_adam_step(float* params, const float* grads, float* m, float* v, int32_t nparam, int32_t t,
+                  float lr, void* stream);
+/* Network input x[nb][3][Ng] from residual columns R (ld), their norms
+ * rnorm[nb], v_loc and theta[nb]. */
+int cnn_make_input(const ks_plan* plan, const void* R, int64_t ld, const double* rnorm,
+                   const void* v_loc, const double* theta, int32_t nb, float* x, void* stream);
 
 /* Kernel timing for measurement (not needed to solve anything).
  * ks_kernel_timer(1, id) starts recording a HIP event pair around every

@@ -17,8 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libksh.so")
 
 KS_FP64, KS_MIXED_FP32, KS_MIXED_BF16X3 = 0, 1, 2
-KS_PRECOND_NONE, KS_PRECOND_TPA = 0, 1
-KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG = 1, 2, 3
+KS_PRECOND_NONE, KS_PRECOND_TPA, KS_PRECOND_CNN = 0, 1, 2
+KS_CNN_NPARAM = 9106
+KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD = 1, 2, 3, 4
 KS_E_HIP, KS_E_WORKSPACE, KS_E_NUMERIC, KS_E_UNSUPPORTED = -1000, -2001, -2002, -2003
 
 EXPORTS = (
@@ -31,6 +32,13 @@ EXPORTS = (
     "hegv_workspace_size",
     "lobpcg_init",
     "lobpcg_step",
+    "ks_jd_correction",
+    "cnn_workspace_size",
+    "cnn_forward",
+    "cnn_backward",
+    "cnn_loss",
+    "cnn_adam_step",
+    "cnn_make_input",
     "ks_kernel_timer",
     "ks_kernel_timer_read",
     "ks_last_error",
@@ -84,7 +92,7 @@ class KsLobpcgState(C.Structure):
 
 
 class KsLobpcgOpts(C.Structure):
-    _fields_ = [("precond", C.c_int32), ("pad_", C.c_int32), ("lock_tol", C.c_double)]
+    _fields_ = [("precond", C.c_int32), ("pad_", C.c_int32), ("lock_tol", C.c_double), ("cnn_params", C.c_void_p)]
 
 
 class KsError(RuntimeError):
@@ -112,6 +120,14 @@ def load() -> C.CDLL:
     lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
     lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
     lib.lobpcg_step.argtypes = [vp, vp, C.POINTER(KsLobpcgState), C.POINTER(KsLobpcgOpts), vp, sz, vp]
+    f32 = C.c_float
+    lib.ks_jd_correction.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, C.c_double, vp, vp, vp, sz, vp]
+    lib.cnn_workspace_size.argtypes = [vp, i32, C.POINTER(sz), C.POINTER(sz)]
+    lib.cnn_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.cnn_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.cnn_loss.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+    lib.cnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, f32, vp]
+    lib.cnn_make_input.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp]
     lib.ks_kernel_timer.argtypes = [i32, i32]
     lib.ks_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.ks_last_error.restype = C.c_char_p
@@ -344,3 +360,74 @@ class Lobpcg:
     @property
     def AP(self):
         return self.block("AP") if self.st.has_p else None
+
+
+def ks_jd_correction(plan: Plan, v, X, theta, R, T, iters, maxit: int = 500, rtol: float = 1e-6, work=None,
+                     stream=None):
+    """T = CG solution of P (H - theta_i) P t_i = P r_i for every column."""
+    nb = X.shape[0]
+    if work is None:
+        work = _work(plan.workspace_size(KS_OP_JD, nb), X.device)
+    rc = load().ks_jd_correction(plan.handle, _ptr(v), _ptr(X), _ptr(theta), _ptr(R), X.stride(0), nb, int(maxit),
+                                 float(rtol), _ptr(T), _ptr(iters), _ptr(work), work.numel(),
+                                 C.c_void_p(_stream(stream)))
+    check(rc, "ks_jd_correction")
+    return T
+
+
+class Cnn:
+    """Parameters, Adam state and buffers of the learned preconditioner."""
+
+    def __init__(self, plan: Plan, params, nbatch: int):
+        import torch
+
+        self.plan = plan
+        self.nbatch = nbatch
+        dev = params.device
+        self.params = params.contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.t = 0
+        a = C.c_size_t()
+        wb = C.c_size_t()
+        check(load().cnn_workspace_size(plan.handle, nbatch, C.byref(a), C.byref(wb)), "cnn_workspace_size")
+        self.acts = torch.empty(int(a.value), dtype=torch.float32, device=dev)
+        self.work = _work(int(wb.value), dev)
+        self.y = torch.empty((nbatch, 2, plan.Ng), dtype=torch.float32, device=dev)
+        self.gy = torch.empty_like(self.y)
+        self.loss = torch.zeros(nbatch, dtype=torch.float64, device=dev)
+        self.sums = torch.zeros(3 * nbatch, dtype=torch.float64, device=dev)
+
+    def forward(self, x, nb=None, stream=None):
+        nb = x.shape[0] if nb is None else nb
+        check(load().cnn_forward(self.plan.handle, _ptr(self.params), nb, _ptr(x), _ptr(self.y), _ptr(self.acts),
+                                 C.c_void_p(_stream(stream))), "cnn_forward")
+        return self.y[:nb]
+
+    def loss_grad(self, t, nb=None, stream=None):
+        nb = t.shape[0] if nb is None else nb
+        check(load().cnn_loss(nb, self.plan.Ng, _ptr(self.y), _ptr(t), _ptr(self.gy), _ptr(self.loss), _ptr(self.sums),
+                              C.c_void_p(_stream(stream))), "cnn_loss")
+        return self.loss[:nb]
+
+    def backward(self, x, gy=None, nb=None, stream=None):
+        nb = x.shape[0] if nb is None else nb
+        g = self.gy if gy is None else gy
+        check(load().cnn_backward(self.plan.handle, _ptr(self.params), nb, _ptr(x), _ptr(self.acts), _ptr(g),
+                                  _ptr(self.grads), _ptr(self.work), self.work.numel(), C.c_void_p(_stream(stream))),
+              "cnn_backward")
+        return self.grads
+
+    def adam(self, lr: float = 1e-3, stream=None):
+        self.t += 1
+        check(load().cnn_adam_step(_ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v),
+                                   self.params.numel(), self.t, float(lr), C.c_void_p(_stream(stream))),
+              "cnn_adam_step")
+
+
+def cnn_make_input(plan: Plan, R, rnorm, v, theta, x, stream=None):
+    nb = R.shape[0]
+    check(load().cnn_make_input(plan.handle, _ptr(R), R.stride(0), _ptr(rnorm), _ptr(v), _ptr(theta), nb, _ptr(x),
+                                C.c_void_p(_stream(stream))), "cnn_make_input")
+    return x

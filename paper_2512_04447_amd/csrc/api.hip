@@ -264,6 +264,10 @@ struct LobWs {
   void* hegv;
   void* potrf;
   double2* ttmp;
+  int cnn_chunk;
+  float* cnn_x;    // chunk x 3 x Ng
+  float* cnn_buf;  // chunk x 32 x Ng
+  float* cnn_y;    // chunk x 2 x Ng
   char* end;
 };
 
@@ -294,6 +298,10 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.hegv = take(hegv_work(m, nb));
   w.potrf = take(potrf_work(nb));
   w.ttmp = reinterpret_cast<double2*>(take((size_t)32 * std::max(nb, 1) * 16));
+  w.cnn_chunk = std::min(nb, 32);
+  w.cnn_x = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 3 * p.Ng * 4));
+  w.cnn_buf = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 32 * p.Ng * 4));
+  w.cnn_y = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 2 * p.Ng * 4));
   w.end = q;
   return w;
 }
@@ -408,10 +416,22 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   int rc;
   using T2 = c2<T>;
   // 1. residual, its norms, preconditioned and lock-masked W (into Xn)
-  if ((rc = precond_apply<T>(p, o->precond, static_cast<const T2*>(st->X), static_cast<const T2*>(st->AX), st->theta,
-                             ld, nb, o->lock_tol, static_cast<T2*>(st->Xn), st->res, static_cast<T2*>(st->T1),
-                             w.partial, w.E, s)))
+  const int kind = o->precond == KS_PRECOND_CNN ? KS_PRECOND_NONE : o->precond;
+  if ((rc = precond_apply<T>(p, kind, static_cast<const T2*>(st->X), static_cast<const T2*>(st->AX), st->theta, ld,
+                             nb, o->lock_tol, static_cast<T2*>(st->Xn), st->res, static_cast<T2*>(st->T1), w.partial,
+                             w.E, s)))
     return rc;
+  if (o->precond == KS_PRECOND_CNN) {
+    // learned preconditioner on the residual, in band chunks
+    for (int b0 = 0; b0 < nb; b0 += w.cnn_chunk) {
+      const int nc = std::min(w.cnn_chunk, nb - b0);
+      T2* R = static_cast<T2*>(st->Xn) + (int64_t)b0 * ld;
+      if ((rc = cnn_input_impl<T>(p, R, ld, st->res + b0, static_cast<const T*>(v), st->theta + b0, nc, w.cnn_x, s)))
+        return rc;
+      if ((rc = cnn_infer_impl(p, o->cnn_params, nc, w.cnn_x, w.cnn_y, w.cnn_buf, s))) return rc;
+      if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, R, ld, s))) return rc;
+    }
+  }
   // 2. W <- W D L^-H
   if ((rc = block_orthonormalise<T>(p, w, st->Xn, nullptr, st->W, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
   // 3. AW = H W
@@ -608,6 +628,7 @@ int ks_workspace_size(const ks_plan* p, int32_t op, int32_t nb, size_t* bytes) {
     case KS_OP_APPLY_H: *bytes = apply_h_work_bytes(*p, nb); return 0;
     case KS_OP_PRECOND: *bytes = precond_work_bytes(*p, nb); return 0;
     case KS_OP_LOBPCG: *bytes = lobpcg_work_bytes(*p, nb); return 0;
+    case KS_OP_JD: *bytes = jd_work_bytes(*p, nb); return 0;
     default: return fail(-2, "unknown op");
   }
 }
@@ -724,12 +745,127 @@ int lobpcg_step(const ks_plan* p, const void* v_loc, ks_lobpcg_state* st, const 
   if (rc) return rc;
   if (!v_loc) return fail(-2, "v_loc is null");
   if (!opts) return fail(-4, "opts is null");
-  if (opts->precond != KS_PRECOND_NONE && opts->precond != KS_PRECOND_TPA) return fail(-4, "unknown preconditioner");
+  if (opts->precond != KS_PRECOND_NONE && opts->precond != KS_PRECOND_TPA && opts->precond != KS_PRECOND_CNN)
+    return fail(-4, "unknown preconditioner");
+  if (opts->precond == KS_PRECOND_CNN && !opts->cnn_params) return fail(-4, "CNN preconditioner without parameters");
   if (!work) return fail(-5, "work is null");
   if (work_bytes < lobpcg_work_bytes(*p, st->nb)) return fail(KS_E_WORKSPACE, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return p->prec == KS_FP64 ? lob_step<double>(*p, v_loc, st, opts, work, s)
                             : lob_step<float>(*p, v_loc, st, opts, work, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned preconditioner ABI
+extern "C" {
+
+int ks_jd_correction(const ks_plan* p, const void* v_loc, const void* X, const double* theta, const void* R, int64_t ld,
+                     int32_t nb, int32_t maxit, double rtol, void* Tout, int32_t* iters, void* work, size_t work_bytes,
+                     void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!v_loc) return fail(-2, "v_loc is null");
+  if (!X) return fail(-3, "X is null");
+  if (!theta) return fail(-4, "theta is null");
+  if (!R) return fail(-5, "R is null");
+  if (ld < p->Ng) return fail(-6, "ld < Ng");
+  if (nb <= 0 || nb > p->nb_max) return fail(-7, "nb out of range");
+  if (maxit < 0) return fail(-8, "maxit negative");
+  if (!(rtol >= 0.0)) return fail(-9, "rtol negative");
+  if (!Tout) return fail(-10, "T is null");
+  if (!iters) return fail(-11, "iters is null");
+  if (!work) return fail(-12, "work is null");
+  if (work_bytes < jd_work_bytes(*p, nb)) return fail(KS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->prec == KS_FP64)
+    return jd_correction<double>(*p, static_cast<const double*>(v_loc), static_cast<const double2*>(X), theta,
+                                 static_cast<const double2*>(R), ld, nb, maxit, rtol, static_cast<double2*>(Tout), iters,
+                                 work, s);
+  return jd_correction<float>(*p, static_cast<const float*>(v_loc), static_cast<const float2*>(X), theta,
+                              static_cast<const float2*>(R), ld, nb, maxit, rtol, static_cast<float2*>(Tout), iters,
+                              work, s);
+}
+
+int cnn_workspace_size(const ks_plan* p, int32_t nbatch, size_t* act_floats, size_t* work_bytes) {
+  if (!p) return fail(-1, "plan is null");
+  if (nbatch <= 0) return fail(-2, "nbatch must be positive");
+  if (!act_floats) return fail(-3, "act_floats is null");
+  if (!work_bytes) return fail(-4, "work_bytes is null");
+  *act_floats = cnn_act_floats(*p, nbatch);
+  *work_bytes = cnn_backward_work(*p, nbatch);
+  return 0;
+}
+
+int cnn_forward(const ks_plan* p, const float* params, int32_t nbatch, const float* x, float* y, float* acts,
+                void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!params) return fail(-2, "params is null");
+  if (nbatch <= 0) return fail(-3, "nbatch must be positive");
+  if (!x) return fail(-4, "x is null");
+  if (!y) return fail(-5, "y is null");
+  if (!acts) return fail(-6, "acts is null");
+  return cnn_forward_impl(*p, params, nbatch, x, y, acts, static_cast<hipStream_t>(stream));
+}
+
+int cnn_backward(const ks_plan* p, const float* params, int32_t nbatch, const float* x, const float* acts,
+                 const float* gy, float* grads, void* work, size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!params) return fail(-2, "params is null");
+  if (nbatch <= 0) return fail(-3, "nbatch must be positive");
+  if (!x) return fail(-4, "x is null");
+  if (!acts) return fail(-5, "acts is null");
+  if (!gy) return fail(-6, "gy is null");
+  if (!grads) return fail(-7, "grads is null");
+  if (!work) return fail(-8, "work is null");
+  if (work_bytes < cnn_backward_work(*p, nbatch)) return fail(KS_E_WORKSPACE, "workspace too small");
+  return cnn_backward_impl(*p, params, nbatch, x, acts, gy, grads, work, static_cast<hipStream_t>(stream));
+}
+
+int cnn_loss(int32_t nbatch, int64_t Ng, const float* y, const float* t, float* gy, double* loss, double* sums,
+             void* stream) {
+  g_last_error.clear();
+  if (nbatch <= 0) return fail(-1, "nbatch must be positive");
+  if (Ng <= 0) return fail(-2, "Ng must be positive");
+  if (!y) return fail(-3, "y is null");
+  if (!t) return fail(-4, "t is null");
+  if (!gy) return fail(-5, "gy is null");
+  if (!loss) return fail(-6, "loss is null");
+  if (!sums) return fail(-7, "sums is null");
+  return cnn_loss_impl(y, t, nbatch, Ng, gy, loss, sums, static_cast<hipStream_t>(stream));
+}
+
+int cnn_adam_step(float* params, const float* grads, float* m, float* v, int32_t nparam, int32_t t, float lr,
+                  void* stream) {
+  g_last_error.clear();
+  if (!params) return fail(-1, "params is null");
+  if (!grads) return fail(-2, "grads is null");
+  if (!m) return fail(-3, "m is null");
+  if (!v) return fail(-4, "v is null");
+  if (nparam <= 0) return fail(-5, "nparam must be positive");
+  if (t < 1) return fail(-6, "t counts from 1");
+  return cnn_adam_impl(params, grads, m, v, nparam, t, lr, static_cast<hipStream_t>(stream));
+}
+
+int cnn_make_input(const ks_plan* p, const void* R, int64_t ld, const double* rnorm, const void* v_loc,
+                   const double* theta, int32_t nb, float* x, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!R) return fail(-2, "R is null");
+  if (ld < p->Ng) return fail(-3, "ld < Ng");
+  if (!rnorm) return fail(-4, "rnorm is null");
+  if (!v_loc) return fail(-5, "v_loc is null");
+  if (!theta) return fail(-6, "theta is null");
+  if (nb <= 0) return fail(-7, "nb must be positive");
+  if (!x) return fail(-8, "x is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->prec == KS_FP64)
+    return cnn_input_impl<double>(*p, static_cast<const double2*>(R), ld, rnorm, static_cast<const double*>(v_loc),
+                                  theta, nb, x, s);
+  return cnn_input_impl<float>(*p, static_cast<const float2*>(R), ld, rnorm, static_cast<const float*>(v_loc), theta,
+                               nb, x, s);
 }
 
 }  // extern "C"

@@ -4,8 +4,9 @@
 //
 // Complex products use four real MFMAs per 16x16x4 step on the real and
 // imaginary parts (no Gauss trick, which loses accuracy).  Operand layout of
-// v_mfma_{f64,f32}_16x16x4: lane l holds A[l%16][l/16] and B[l/16][l%16];
-// the 16x16 result sits in 4 accumulators per lane, D[4*(l/16)+v][l%16].
+// v_mfma_{f64,f32}_16x16x4 (measured on gfx950): lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; the 16x16 result sits in 4 accumulators per lane,
+// column l%16, row 4*(l/16)+v for f32 but row l/16+4*v for f64.
 #include "gemm.hpp"
 
 namespace ks {
@@ -19,12 +20,14 @@ template <> struct Mfma<double> {
   __device__ static inline acc run(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 template <> struct Mfma<float> {
   using acc = f4;
   __device__ static inline acc run(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 constexpr int TILE = 64;  // output tile edge per workgroup
@@ -45,17 +48,22 @@ __device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
 template <typename T, bool TWO>
 __global__ void __launch_bounds__(256)
 k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int64_t K, int64_t kper,
-       int ntile, int ntu, double2* __restrict__ partS, double2* __restrict__ partH) {
+       int ntile, int ntu, int full, double2* __restrict__ partS, double2* __restrict__ partH) {
   using T2 = c2<T>;
   using M = Mfma<T>;
   __shared__ T2 As[TILE][PAD];
   __shared__ T2 Bs[TILE][PAD];
   __shared__ T2 B2s[TWO ? TILE : 1][PAD];
-  // upper tile index -> (ti, tj), ti <= tj
+  // tile index -> (ti, tj): upper tiles ti <= tj, or every tile when full
   int t = blockIdx.x;
   int ti = 0;
-  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
-  const int tj = ti + t;
+  if (full) {
+    ti = t / ntile;
+    t -= ti * ntile;
+  } else {
+    while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  }
+  const int tj = full ? t : ti + t;
   const int sp = blockIdx.y;
   const int64_t k0 = (int64_t)sp * kper;
   const int64_t k1 = min(K, k0 + kper);
@@ -156,7 +164,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
     for (int w = 0; w < 2; ++w)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = wi * 32 + u * 16 + 4 * (lane >> 4) + v;
+        const int i = wi * 32 + u * 16 + M::row(lane, v);
         const int j = wj * 32 + w * 16 + (lane & 15);
         if constexpr (F32) {
           partS[base + i * TILE + j] = make_double2(dsr[u][w][v], dsi[u][w][v]);
@@ -171,16 +179,31 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
 // Sum the K splits in order and write the Hermitian m x m result
 // (column-major, ldo).  Diagonal tiles are Hermitised, (G + G^H)/2.
 __global__ void __launch_bounds__(256)
-k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, int m,
+k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, int m, int full,
               double2* __restrict__ out, int ldo) {
   int t = blockIdx.x;
   int ti = 0;
-  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
-  const int tj = ti + t;
+  if (full) {
+    ti = t / ntile;
+    t -= ti * ntile;
+  } else {
+    while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  }
+  const int tj = full ? t : ti + t;
   for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
     const int i = e / TILE, j = e - i * TILE;
     const int gi = ti * TILE + i, gj = tj * TILE + j;
     if (gi >= m || gj >= m) continue;
+    if (full) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const double2 v = part[((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE) + e];
+        s.x += v.x;
+        s.y += v.y;
+      }
+      out[gi + (int64_t)gj * ldo] = s;
+      continue;
+    }
     if (ti == tj && j < i) continue;  // handled by its mirror
     double2 s = make_double2(0.0, 0.0);
     for (int sp = 0; sp < nsplit; ++sp) {
@@ -204,10 +227,10 @@ k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, 
   }
 }
 
-GramShape gram_shape(int m, int64_t K) {
+GramShape gram_shape(int m, int64_t K, bool full) {
   GramShape g;
   g.ntile = (int)ceil_div(m, TILE);
-  g.ntu = g.ntile * (g.ntile + 1) / 2;
+  g.ntu = full ? g.ntile * g.ntile : g.ntile * (g.ntile + 1) / 2;
   int64_t ns = ceil_div(1024, g.ntu);
   const int64_t kmax_split = std::max<int64_t>(1, K / 512);
   ns = std::min<int64_t>(ns, kmax_split);
@@ -220,34 +243,56 @@ GramShape gram_shape(int m, int64_t K) {
 }
 
 size_t gram_work_bytes(int m, int64_t K) {
-  GramShape g = gram_shape(m, K);
-  return (size_t)g.nsplit * g.ntu * TILE * TILE * sizeof(double2) * 2;
+  size_t mx = 0;
+  for (int f = 0; f < 2; ++f) {
+    GramShape g = gram_shape(m, K, f == 1);
+    mx = std::max(mx, (size_t)g.nsplit * g.ntu * TILE * TILE * sizeof(double2) * 2);
+  }
+  return mx;
+}
+
+template <typename T>
+static int gram_impl(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m,
+                     int64_t K, bool full, double2* S, int lds_, double2* H, int ldh, void* work, hipStream_t s) {
+  if (m <= 0) return 0;
+  GramShape g = gram_shape(m, K, full);
+  double2* partS = static_cast<double2*>(work);
+  double2* partH = partS + (size_t)g.nsplit * g.ntu * TILE * TILE;
+  dim3 grid(g.ntu, g.nsplit);
+  const int fl = full ? 1 : 0;
+  TimerScope ts(KF_GRAM, s);
+  if (B2)
+    hipLaunchKernelGGL((k_gram<T, true>), grid, dim3(256), 0, s, A, B1, *B2, m, K, g.kper, g.ntile, g.ntu, fl, partS,
+                       partH);
+  else
+    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, fl, partS,
+                       partH);
+  KS_LAUNCH_CHECK("gram");
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, fl, S, lds_);
+  KS_LAUNCH_CHECK("gram_reduce");
+  if (B2) {
+    hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partH, g.nsplit, g.ntile, g.ntu, m, fl, H, ldh);
+    KS_LAUNCH_CHECK("gram_reduce");
+  }
+  return 0;
 }
 
 template <typename T>
 int gram(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m, int64_t K,
          double2* S, int lds_, double2* H, int ldh, void* work, hipStream_t s) {
-  if (m <= 0) return 0;
-  GramShape g = gram_shape(m, K);
-  double2* partS = static_cast<double2*>(work);
-  double2* partH = partS + (size_t)g.nsplit * g.ntu * TILE * TILE;
-  dim3 grid(g.ntu, g.nsplit);
-  TimerScope ts(KF_GRAM, s);
-  if (B2)
-    hipLaunchKernelGGL((k_gram<T, true>), grid, dim3(256), 0, s, A, B1, *B2, m, K, g.kper, g.ntile, g.ntu, partS,
-                       partH);
-  else
-    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, partS,
-                       partH);
-  KS_LAUNCH_CHECK("gram");
-  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, S, lds_);
-  KS_LAUNCH_CHECK("gram_reduce");
-  if (B2) {
-    hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partH, g.nsplit, g.ntile, g.ntu, m, H, ldh);
-    KS_LAUNCH_CHECK("gram_reduce");
-  }
-  return 0;
+  return gram_impl<T>(A, B1, B2, m, K, false, S, lds_, H, ldh, work, s);
 }
+
+template <typename T>
+int gram_general(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B, int m, int64_t K, double2* G, int ldg,
+                 void* work, hipStream_t s) {
+  return gram_impl<T>(A, B, nullptr, m, K, true, G, ldg, nullptr, 0, work, s);
+}
+
+template int gram_general<double>(const BlockList<double2>&, const BlockList<double2>&, int, int64_t, double2*, int,
+                                  void*, hipStream_t);
+template int gram_general<float>(const BlockList<float2>&, const BlockList<float2>&, int, int64_t, double2*, int,
+                                 void*, hipStream_t);
 
 // ---------------------------------------------------------------- rotation
 // Y = V C for a block list V (Ng x m) and C (m x ncol, column-major, ldc in
@@ -330,7 +375,7 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
       for (int w = 0; w < 2; ++w)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int band = b0 + wb * 32 + u * 16 + 4 * (lane >> 4) + v;
+          const int band = b0 + wb * 32 + u * 16 + M::row(lane, v);
           const int64_t r = r0 + wr * 32 + w * 16 + (lane & 15);
           if (band < ncol && r < Ng) out[(int64_t)band * ldy + r] = cmake<T2>(dr[u][w][v], di[u][w][v]);
         }
@@ -421,7 +466,7 @@ k_zgemm(int M, int N, int K, double alpha, const double2* __restrict__ A, int ld
     for (int w = 0; w < 2; ++w)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = i0 + wi * 32 + u * 16 + 4 * (lane >> 4) + v;
+        const int gi = i0 + wi * 32 + u * 16 + Mf::row(lane, v);
         const int gj = j0 + wj * 32 + w * 16 + (lane & 15);
         if (gi < M && gj < N) {
           double2* c = C + gi + (int64_t)gj * ldc;

@@ -20,7 +20,7 @@ struct GramShape {
   int ntile, ntu, nsplit;
   int64_t kper;
 };
-GramShape gram_shape(int m, int64_t K);
+GramShape gram_shape(int m, int64_t K, bool full);
 size_t gram_work_bytes(int m, int64_t K);
 
 // S = A^H B1 (and H = A^H B2 when B2 != null) for the first m columns of the
@@ -28,6 +28,11 @@ size_t gram_work_bytes(int m, int64_t K);
 template <typename T>
 int gram(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m, int64_t K,
          double2* S, int lds, double2* H, int ldh, void* work, hipStream_t s);
+
+// G = A^H B (every tile, not Hermitian), FP64 complex column-major.
+template <typename T>
+int gram_general(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B, int m, int64_t K, double2* G, int ldg,
+                 void* work, hipStream_t s);
 
 // Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.
 template <typename T>

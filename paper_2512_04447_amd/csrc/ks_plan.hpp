@@ -77,4 +77,30 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
 size_t apply_h_work_bytes(const ks_plan& p, int nb);
 size_t precond_work_bytes(const ks_plan& p, int nb);
 
+// ---- projected CG for training targets (cg.hip) ----
+size_t jd_work_bytes(const ks_plan& p, int nb);
+template <typename T>
+int jd_correction(const ks_plan& p, const T* v, const c2<T>* X, const double* theta, const c2<T>* R, int64_t ld,
+                  int nb, int maxit, double rtol, c2<T>* Tout, int32_t* iters, void* work, hipStream_t s);
+
+// ---- learned preconditioner (cnn.hip) ----
+constexpr int kCnnParams = 9106;
+size_t cnn_act_floats(const ks_plan& p, int nbatch);
+size_t cnn_backward_work(const ks_plan& p, int nbatch);
+int cnn_forward_impl(const ks_plan& p, const float* params, int nbatch, const float* x, float* y, float* acts,
+                     hipStream_t s);
+int cnn_infer_impl(const ks_plan& p, const float* params, int nbatch, const float* x, float* y, float* buf,
+                   hipStream_t s);
+int cnn_backward_impl(const ks_plan& p, const float* params, int nbatch, const float* x, const float* acts,
+                      const float* gy, float* grads, void* work, hipStream_t s);
+int cnn_loss_impl(const float* y, const float* t, int nbatch, int64_t Ng, float* gy, double* loss, double* sums,
+                  hipStream_t s);
+int cnn_adam_impl(float* params, const float* grads, float* m, float* v, int n, int t, float lr, hipStream_t s);
+template <typename T>
+int cnn_input_impl(const ks_plan& p, const c2<T>* R, int64_t ld, const double* rnorm, const T* V,
+                   const double* theta, int nb, float* x, hipStream_t s);
+template <typename T>
+int cnn_output_impl(const ks_plan& p, const float* y, int nb, const double* res, double lock_tol, c2<T>* W, int64_t ld,
+                    hipStream_t s);
+
 }  // namespace ks

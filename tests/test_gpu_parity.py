@@ -99,7 +99,8 @@ def test_tpa_preconditioner_and_residual_match_oracle(ks, name, nb):
     assert np.abs(dres.cpu().numpy() - res).max() <= 1e-12 * res.max()
     assert np.abs(W.cpu().numpy() - Wref).max() <= 1e-12 * np.abs(Wref).max()
     # lock mask: columns with res <= lock_tol are exact zeros
-    lock = float(np.sort(res)[nb // 2])
+    rs = np.sort(res)
+    lock = float(0.5 * (rs[nb // 2] + rs[nb // 2 + 1]))  # strictly between two residuals
     b.ks_precond_apply(plan, b.KS_PRECOND_TPA, to_dev(st.X), to_dev(st.AX), to_dev(st.theta), W, dres, lock)
     Wl = W.cpu().numpy()
     for i in range(nb):
