@@ -1,0 +1,182 @@
+"""Parity of the learned-preconditioner kernels and the projected-CG
+training-target solver (HIP, through the C ABI) with the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import ksinputs as ki
+from oracle import cg as ocg
+from oracle import cnn as ocnn
+from oracle import hamiltonian as oh
+from oracle import lobpcg as olob
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def flat_params(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def plan_for(n, L=7.0, nb=4):
+    from paper_2512_04447_amd import binding as b
+
+    return b.Plan((n, n, n), L, None, nb, b.KS_FP64)
+
+
+def rand_params(seed):
+    params = ocnn.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    # non-zero biases so the bias gradients are exercised
+    return [(w, 0.1 * rng.standard_normal(b.shape)) for w, b in params]
+
+
+@pytest.mark.parametrize("n,nbatch", [(10, 2), (16, 3)])
+def test_cnn_forward_matches_oracle(ks, n, nbatch):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    _say("cnn forward", n, nbatch)
+    params = rand_params(2)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((nbatch, 3, n, n, n))
+    ref = np.stack([ocnn.forward(params, x[s])[0] for s in range(nbatch)])
+    plan = plan_for(n)
+    net = b.Cnn(plan, dev(flat_params(params)), nbatch)
+    y = net.forward(dev(x.reshape(nbatch, 3, -1), torch.float32))
+    got = y.cpu().numpy().reshape(ref.shape)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err <= 2e-5
+
+
+@pytest.mark.parametrize("n,nbatch", [(10, 2), (16, 2)])
+def test_cnn_backward_matches_oracle(ks, n, nbatch):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    _say("cnn backward", n, nbatch)
+    params = rand_params(3)
+    rng = np.random.default_rng(7 * n)
+    x = rng.standard_normal((nbatch, 3, n, n, n))
+    t = rng.standard_normal((nbatch, 2, n, n, n))
+    gref = [np.zeros_like(w) for w, _ in params] + [np.zeros_like(bb) for _, bb in params]
+    loss_ref = []
+    for s in range(nbatch):
+        y, cache = ocnn.forward(params, x[s])
+        loss, gy = ocnn.normalised_loss(y, t[s])
+        loss_ref.append(loss)
+        grads, _ = ocnn.backward(params, cache, gy / nbatch)
+        for k, (dw, db) in enumerate(grads):
+            gref[k] += dw
+            gref[3 + k] += db
+    ref = np.concatenate([np.concatenate([gref[k].ravel(), gref[3 + k].ravel()]) for k in range(3)])
+    plan = plan_for(n)
+    net = b.Cnn(plan, dev(flat_params(params)), nbatch)
+    xd = dev(x.reshape(nbatch, 3, -1), torch.float32)
+    net.forward(xd)
+    loss = net.loss_grad(dev(t.reshape(nbatch, 2, -1), torch.float32))
+    g = net.backward(xd).cpu().numpy()
+    assert np.abs(loss.cpu().numpy() - np.array(loss_ref)).max() <= 1e-5
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    _say("  grad rel err", err)
+    assert err <= 1e-4
+    # per-block check: each parameter group within 1e-3 of its own scale
+    off = 0
+    for k in range(3):
+        for arr in (gref[k], gref[3 + k]):
+            seg = g[off:off + arr.size]
+            assert np.abs(seg - arr.ravel()).max() <= 1e-3 * max(np.abs(arr).max(), 1e-12)
+            off += arr.size
+
+
+def test_adam_matches_oracle(ks):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    plan = plan_for(8)
+    rng = np.random.default_rng(5)
+    p0 = rng.standard_normal(b.KS_CNN_NPARAM).astype(np.float32)
+    net = b.Cnn(plan, dev(p0), 1)
+    p, m, v = p0.astype(np.float64), np.zeros(p0.size), np.zeros(p0.size)
+    for step in range(1, 4):
+        g = rng.standard_normal(p0.size).astype(np.float32)
+        net.grads.copy_(dev(g))
+        net.adam(1e-3)
+        p, m, v = ocnn.adam_update(p, g.astype(np.float64), m, v, step, lr=1e-3)
+    torch.cuda.synchronize()
+    assert np.abs(net.params.cpu().numpy() - p).max() <= 1e-6
+
+
+def test_cnn_input_matches_oracle(ks):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    cfg = ki.custom_config("in", 7.0, 10, ((0.2, 0.3, 0.4),), 3)
+    cell = ki.make_cell(cfg)
+    rng = np.random.default_rng(9)
+    R = rng.standard_normal((3, cfg.Ng)) + 1j * rng.standard_normal((3, cfg.Ng))
+    theta = np.array([-0.3, 0.1, 0.7])
+    rn = np.linalg.norm(R, axis=1)
+    plan = b.Plan(cell.n, cell.L, None, 3, b.KS_FP64)
+    x = torch.empty((3, 3, cfg.Ng), dtype=torch.float32, device="cuda")
+    b.cnn_make_input(plan, dev(R), dev(rn), dev(cell.V), dev(theta), x)
+    got = x.cpu().numpy()
+    for i in range(3):
+        ref = ocnn.make_input(R[i], cell.V, theta[i], cfg.n, cfg.h).reshape(3, -1)
+        assert np.abs(got[i] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_jd_correction_matches_oracle(ks):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    cfg = ki.custom_config("jd", 7.0, 10, ((0.1, 0.2, 0.3), (0.6, 0.55, 0.45)), 6, lmax=1, rc=0.61)
+    cell = ki.make_cell(cfg)
+    oc = oh.oracle_cell(cfg, cell.D)
+    pc = olob.tpa_preconditioner(oc)
+    st = olob.initial_state(oc, ki.make_x0(cfg))
+    for _ in range(4):
+        st = olob.step(oc, st, pc)
+    R, _ = olob.residual(st)
+    _say("jd correction")
+    refs, its = [], []
+    for i in range(cfg.nb):
+        t, it, ok = ocg.projected_cg(lambda v: oh.apply_h(oc, v), st.X, st.theta[i], R[i], rtol=1e-10, maxit=400)
+        refs.append(t)
+        its.append(it if ok else -it)
+    ref = np.array(refs)
+    proj = b.ProjectorArrays.from_cell(cell)
+    plan = b.Plan(cell.n, cell.L, proj, cfg.nb, b.KS_FP64)
+    T = torch.empty((cfg.nb, cfg.Ng), dtype=torch.complex128, device="cuda")
+    iters = torch.zeros(cfg.nb, dtype=torch.int32, device="cuda")
+    b.ks_jd_correction(plan, dev(cell.V), dev(st.X), dev(st.theta), dev(R), T, iters, maxit=400, rtol=1e-10)
+    got = T.cpu().numpy()
+    git = iters.cpu().numpy()
+    _say("  oracle iters", its, "gpu iters", git.tolist())
+    for i in range(cfg.nb):
+        if its[i] > 0:
+            assert git[i] > 0
+            assert np.linalg.norm(got[i] - ref[i]) <= 1e-7 * np.linalg.norm(ref[i])
+            assert abs(int(git[i]) - its[i]) <= 2
+    # the correction is orthogonal to X
+    assert np.abs(np.conj(st.X) @ got.T).max() <= 1e-10 * np.abs(got).max()
