@@ -30,6 +30,10 @@ Readings of points the paper leaves open (each listed in the design notes):
 * On a Cholesky failure of the subspace overlap the P block is dropped and
   the reduction is retried; a second failure is an error.
 * H_s and S_s are Hermitised, (A + A^H)/2, before the reduction.
+* AX and AP are formed by applying H to the new X and P every iteration,
+  not by rotating AV with the Ritz coefficients: the rotated products drift
+  from H X once the basis is ill-conditioned (the drift grows geometrically
+  and ends the convergence), while a fresh H-apply has no memory.
 
 Blocks are stored band-major, shape (nb, Ng); as matrices they are the
 transposes (Ng x nb).
@@ -90,7 +94,8 @@ def initial_state(cell: OracleCell, X0: np.ndarray) -> State:
     AX = apply_h(cell, X)
     Hs = _herm(gram(X, AX))
     w, Z = jacobi_eigh(Hs)
-    return State(rotate(X, Z), rotate(AX, Z), w.copy())
+    Xr = rotate(X, Z)
+    return State(Xr, apply_h(cell, Xr), w.copy())
 
 
 def residual(st: State):
@@ -149,11 +154,11 @@ def step(cell: OracleCell, st: State, precond: Optional[Callable] = None,
     blocks = [st.X, W]
     ablocks = [st.AX, AW]
     if st.P is not None:
-        P, AP, info = orthonormalise_block(st.P * active[:, None], st.AP * active[:, None])
+        P, _, info = orthonormalise_block(st.P * active[:, None])
         if info:
             events.append("p_not_orthonormalised")
         blocks.append(P)
-        ablocks.append(AP)
+        ablocks.append(apply_h(cell, P))
     while True:
         V = np.concatenate(blocks, axis=0)
         AV = np.concatenate(ablocks, axis=0)
@@ -169,10 +174,8 @@ def step(cell: OracleCell, st: State, precond: Optional[Callable] = None,
             continue
         raise np.linalg.LinAlgError(f"subspace overlap not positive definite (info={info})")
     Xn = rotate(V, C)
-    AXn = rotate(AV, C)
     Pn = rotate(V[nb:], C[nb:])
-    APn = rotate(AV[nb:], C[nb:])
-    return State(Xn, AXn, w.copy(), Pn, APn, st.iteration + 1, st.events + events)
+    return State(Xn, apply_h(cell, Xn), w.copy(), Pn, None, st.iteration + 1, st.events + events)
 
 
 def tpa_preconditioner(cell: OracleCell):

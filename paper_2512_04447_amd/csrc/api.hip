@@ -396,9 +396,12 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
                      static_cast<c2<T>*>(w.Cb), nb, nb, nb);
   const auto* Cb = static_cast<const c2<T>*>(w.Cb);
   if ((rc = rotate<T>(L1, nb, nb, Cb, nb, nb, p.Ng, static_cast<c2<T>*>(st->Xn), nullptr, ld, s))) return rc;
-  if ((rc = rotate<T>(L2, nb, nb, Cb, nb, nb, p.Ng, static_cast<c2<T>*>(st->AXn), nullptr, ld, s))) return rc;
   std::swap(st->X, st->Xn);
-  std::swap(st->AX, st->AXn);
+  // AX by a fresh H-apply of the rotated block (no rotation drift)
+  if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const c2<T>*>(st->X), ld,
+                       static_cast<c2<T>*>(st->AX), ld, nb, static_cast<c2<T>*>(st->T1), static_cast<c2<T>*>(w.dc),
+                       s)))
+    return rc;
   KS_HIP(hipMemcpyAsync(st->theta, w.wnew, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
   st->has_p = 0;
   st->iter = 0;
@@ -440,10 +443,12 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
     return rc;
   // 4. P, AP masked and orthonormalised
   if (st->has_p) {
-    if ((rc = block_orthonormalise<T>(p, w, st->P, st->AP, st->Pn, st->APn, ld, nb, st->res, o->lock_tol, s)))
+    if ((rc = block_orthonormalise<T>(p, w, st->P, nullptr, st->Pn, nullptr, ld, nb, st->res, o->lock_tol, s)))
       return rc;
     std::swap(st->P, st->Pn);
-    std::swap(st->AP, st->APn);
+    if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->P), ld, static_cast<T2*>(st->AP), ld,
+                         nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))
+      return rc;
   }
   // 5. subspace matrices
   const int mfull = st->has_p ? 3 * nb : 2 * nb;
@@ -475,25 +480,24 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   }
   st->last_info = hinfo;
   if (hinfo != 0) return fail(KS_E_NUMERIC, "subspace overlap is not positive definite");
-  // 7. rotation: X <- V C, P <- V[:, nb:] C[nb:, :], same for AV
+  // 7. rotation: X <- V C and P <- V[:, nb:] C[nb:, :] in one pass over V
   hipLaunchKernelGGL((k_to_block<T>), dim3(grid_for((int64_t)m * nb)), dim3(256), 0, s, w.C, m,
                      static_cast<T2*>(w.Cb), m, m, nb);
   KS_LAUNCH_CHECK("to_block");
   const auto* Cb = static_cast<const T2*>(w.Cb);
   if ((rc = rotate<T>(LV, m, nb, Cb, m, nb, p.Ng, static_cast<T2*>(st->Xn), static_cast<T2*>(st->Pn), ld, s)))
     return rc;
-  if ((rc = rotate<T>(LAV, m, nb, Cb, m, nb, p.Ng, static_cast<T2*>(st->AXn), static_cast<T2*>(st->APn), ld, s)))
-    return rc;
   std::swap(st->X, st->Xn);
-  std::swap(st->AX, st->AXn);
   std::swap(st->P, st->Pn);
-  std::swap(st->AP, st->APn);
-  // 8. mixed plans: FP64-factor Cholesky-QR of X (and the same transform of AX)
+  // 8. mixed plans: FP64-factor Cholesky-QR of X
   if (p.prec != KS_FP64) {
-    if ((rc = block_orthonormalise<T>(p, w, st->X, st->AX, st->Xn, st->AXn, ld, nb, nullptr, 0.0, s))) return rc;
+    if ((rc = block_orthonormalise<T>(p, w, st->X, nullptr, st->Xn, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
     std::swap(st->X, st->Xn);
-    std::swap(st->AX, st->AXn);
   }
+  // 9. AX by a fresh H-apply (AP is formed the same way next step)
+  if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->X), ld, static_cast<T2*>(st->AX), ld,
+                       nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))
+    return rc;
   KS_HIP(hipMemcpyAsync(st->theta, w.wnew, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
   st->has_p = 1;
   st->iter += 1;

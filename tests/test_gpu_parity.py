@@ -183,9 +183,7 @@ def _gpu_state_from_oracle(lob, st):
         setattr(lob.st, k, int(lob.buf[k].data_ptr()))
     if st.P is not None:
         lob.buf["P"].copy_(to_dev(st.P))
-        lob.buf["AP"].copy_(to_dev(st.AP))
         lob.st.P = int(lob.buf["P"].data_ptr())
-        lob.st.AP = int(lob.buf["AP"].data_ptr())
         lob.st.has_p = 1
     torch.cuda.synchronize()
 
