@@ -53,17 +53,18 @@ def family_work(cfg, steps_info):
     m = 3 * nb
     es = 16
     blk = Ng * nb * es
+    n_h = 3  # H-applies per step: W, P and the new X
     return {
         # Hermitian triangles: W and P self-Grams (S only), basis Gram (S and H)
         "gram_flops": 8 * Ng * nb * (nb + 1) / 2 * 2 + 2 * 8 * Ng * m * (m + 1) / 2,
-        # W and P/AP Cholesky-QR rotations, X/P from V and AX/AP from AV
-        "rotate_flops": 8 * Ng * nb * nb * 3 + 2 * 8 * Ng * m * nb,
-        # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-apply of W (R+W)
-        "pass_a_bytes": blk * (2 + 3 + 2),
-        # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W)
-        "pass_b_bytes": blk * (1 + 2 + 2),
-        # pass C: TPA (R+W), H (tmp R + psi R + W)
-        "pass_c_bytes": blk * (2 + 3),
+        # W and P Cholesky-QR rotations, X and P from one pass over V
+        "rotate_flops": 8 * Ng * nb * nb * 2 + 8 * Ng * m * nb,
+        # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-applies (R+W)
+        "pass_a_bytes": blk * (2 + 3 + 2 * n_h),
+        # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W) per H-apply
+        "pass_b_bytes": blk * (1 + 2 + 2 * n_h),
+        # pass C: TPA (R+W), H (tmp R + psi R + W) per H-apply
+        "pass_c_bytes": blk * (2 + 3 * n_h),
     }
 
 

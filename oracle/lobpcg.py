@@ -11,14 +11,19 @@ because the pseudopotentials are norm-conserving (benchmark-target
 paragraph).
 
 Readings of points the paper leaves open (each listed in the design notes):
-* W is the preconditioned residual.  Soft locking with fixed shapes: a band
-  whose residual norm is at most ``lock_tol`` contributes an exactly-zero
-  column to W and to P (its X column stays in the Rayleigh-Ritz step).
+* W is the preconditioned residual, made orthogonal to X by one classical
+  Gram-Schmidt pass, W <- W - X (X^H W).  Soft locking with fixed shapes: a
+  band whose residual norm is at most ``lock_tol`` contributes an
+  exactly-zero column to W and to P (its X column stays in the Rayleigh-Ritz
+  step).
 * W and P are each orthonormalised *within their own block* before the Gram
   matrices are formed: columns are scaled to unit length (a zero column
   stays zero), then B <- B L^-H with L L^H = B^H B (Cholesky-QR; a zero
-  column gets a unit pivot).  If that Cholesky fails the block keeps only
-  the unit-length scaling.  Without this the basis loses rank as the
+  column gets a unit pivot).  If that Cholesky fails the block is
+  orthonormalised through the eigen-decomposition of its Gram matrix
+  instead (SVQB, Stathopoulos and Wu, SIAM J. Sci. Comput. 23 (2002)):
+  directions with eigenvalue below 1e-12 of the largest become zero
+  columns.  Without this the basis loses rank as the
   residuals fall and the iteration stalls near 1e-6 (Hetmaniuk and
   Lehoucq, "Basis selection in LOBPCG", J. Comput. Phys. 218 (2006),
   analyse the same loss).
@@ -48,6 +53,9 @@ import numpy as np
 from .hamiltonian import OracleCell, apply_h
 from .linalg import cholesky_lower, hegv_two_trsm, jacobi_eigh, solve_lower
 from .precond import band_kinetic_energy, tpa_apply
+
+
+SVQB_TOL = 1e-12
 
 
 def _herm(A: np.ndarray) -> np.ndarray:
@@ -108,8 +116,8 @@ def orthonormalise_block(B: np.ndarray, AB: Optional[np.ndarray] = None):
 
     D = diag(1/||b_i||) (0 for a zero column) and L L^H = D B^H B D with a
     unit pivot for zero columns.  AB (= H B) receives the same transform.
-    Returns (B', AB', info); on a Cholesky failure (info > 0) only the
-    scaling D is applied.
+    Returns (B', AB', info); on a Cholesky failure (info > 0) the block
+    is orthonormalised by SVQB instead.
     """
     nrm = np.linalg.norm(B, axis=1)
     d = np.where(nrm > 0.0, 1.0 / np.where(nrm > 0.0, nrm, 1.0), 0.0)
@@ -120,7 +128,16 @@ def orthonormalise_block(B: np.ndarray, AB: Optional[np.ndarray] = None):
     G[zero, zero] = 1.0
     L, info = cholesky_lower(G)
     if info:
-        return Bs, ABs, info
+        # SVQB: G = U diag(lam) U^H; keep lam > svqb_tol * max(lam), B <- Bs U lam^-1/2
+        # with the columns of dropped directions set to zero
+        Gs = G.copy()
+        Gs[zero, zero] = 0.0  # zero columns stay zero directions (dropped)
+        lam, U = jacobi_eigh(Gs)
+        keep = lam > SVQB_TOL * np.max(lam)
+        M = np.where(keep[None, :], U / np.sqrt(np.where(keep, lam, 1.0))[None, :], 0.0)
+        Bq = rotate(Bs, M)
+        ABq = None if ABs is None else rotate(ABs, M)
+        return Bq, ABq, info
     Bq = np.conj(solve_lower(L, np.conj(Bs)))
     ABq = None if ABs is None else np.conj(solve_lower(L, np.conj(ABs)))
     return Bq, ABq, 0
@@ -147,6 +164,7 @@ def step(cell: OracleCell, st: State, precond: Optional[Callable] = None,
     active = (res > lock_tol).astype(np.float64)
     R = R * active[:, None]
     W = R if precond is None else precond(R, st)
+    W = W - rotate(st.X, gram(st.X, W))
     W, _, info = orthonormalise_block(W)
     if info:
         events.append("w_not_orthonormalised")

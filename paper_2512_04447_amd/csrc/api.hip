@@ -256,6 +256,7 @@ struct LobWs {
   void* M;      // nb x nb block precision
   double* dvec; // nb
   double* wnew; // m
+  double* lam;  // nb, SVQB eigenvalues
   int32_t* info;  // 4 ints
   double* partial;
   double* E;
@@ -288,6 +289,7 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.M = take((size_t)nb * nb * es);
   w.dvec = reinterpret_cast<double*>(take((size_t)nb * 8));
   w.wnew = reinterpret_cast<double*>(take((size_t)m * 8));
+  w.lam = reinterpret_cast<double*>(take((size_t)nb * 8));
   w.info = reinterpret_cast<int32_t*>(take(16));
   const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
   const size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p.zc));
@@ -325,8 +327,38 @@ static BlockList<c2<T>> blist(const void* a, const void* b, const void* c, int64
   return L;
 }
 
-// B <- B D L^-H (columns scaled to unit norm, then Cholesky-QR; on a failed
-// Cholesky only the scaling), written to out (and AB to aout when given).
+__global__ void k_zero_dead_diag(double2* __restrict__ G, int ldg, int n, const double* __restrict__ dvec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && dvec[i] == 0.0) G[i + (int64_t)i * ldg] = make_double2(0.0, 0.0);
+}
+
+static int read_info(const int32_t* dev, int32_t* host, hipStream_t s) {
+  KS_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  KS_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+// SVQB coefficients: M[:, j] = d .* U[:, j] / sqrt(lam_j) when lam_j > tol *
+// lam_max, else zero (lam ascending, so lam_max = lam[n-1]).
+template <typename T>
+__global__ void k_svqb_coef(const double2* __restrict__ U, int ldu, int n, const double* __restrict__ lam,
+                            const double* __restrict__ dvec, double tol, c2<T>* __restrict__ M, int ldm) {
+  const int64_t total = (int64_t)n * n;
+  const double lmax = lam[n - 1];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const bool keep = lam[j] > tol * lmax;
+    const double sc = keep ? dvec[i] / sqrt(lam[j]) : 0.0;
+    const double2 u = U[i + (int64_t)j * ldu];
+    M[i + (int64_t)j * ldm] = cmake<c2<T>>((T)(sc * u.x), (T)(sc * u.y));
+  }
+}
+
+// B <- B D L^-H (columns scaled to unit norm, then Cholesky-QR), written to
+// out (and AB to aout when given).  If the Cholesky fails the block is
+// orthonormalised through the eigenvectors of its scaled Gram matrix (SVQB)
+// and directions with eigenvalue below svqb_tol * max become zero columns;
+// this reads the Cholesky info back to the host.
 template <typename T>
 static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B, const void* AB, void* out, void* aout,
                                 int64_t ld, int nb, const double* res, double lock_tol, hipStream_t s) {
@@ -337,24 +369,33 @@ static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B,
                      w.dvec);
   hipLaunchKernelGGL(k_scale_gram, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.G, nb, nb, w.dvec);
   KS_LAUNCH_CHECK("colscale");
+  // keep the scaled Gram for the SVQB fallback, zero columns with a zero
+  // diagonal so that they are dropped exactly
+  hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.G, nb, w.H0, nb, nb, nb);
+  hipLaunchKernelGGL(k_zero_dead_diag, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, w.H0, nb, nb, w.dvec);
   if ((rc = potrf(nb, w.G, nb, w.potrf, w.info + 1, s))) return rc;
-  hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb);
-  if ((rc = trsm('C', nb, nb, w.G, nb, w.Y, nb, w.potrf, w.ttmp, w.info + 1, s))) return rc;
-  hipLaunchKernelGGL((k_cholqr_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb, w.dvec,
-                     w.info + 1, static_cast<c2<T>*>(w.M), nb);
-  KS_LAUNCH_CHECK("cholqr_coef");
+  int32_t hinfo = 0;
+  if ((rc = read_info(w.info + 1, &hinfo, s))) return rc;
+  if (hinfo == 0) {
+    hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb);
+    if ((rc = trsm('C', nb, nb, w.G, nb, w.Y, nb, w.potrf, w.ttmp, w.info + 1, s))) return rc;
+    hipLaunchKernelGGL((k_cholqr_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb, w.dvec,
+                       w.info + 1, static_cast<c2<T>*>(w.M), nb);
+    KS_LAUNCH_CHECK("cholqr_coef");
+  } else {
+    hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.S0, nb, nb);
+    if ((rc = hegv(nb, nb, w.H0, nb, w.S0, nb, w.lam, w.C, nb, w.hegv, w.info + 2, s))) return rc;
+    const double tol = p.prec == KS_FP64 ? 1e-12 : 1e-6;
+    hipLaunchKernelGGL((k_svqb_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.C, nb, nb, w.lam,
+                       w.dvec, tol, static_cast<c2<T>*>(w.M), nb);
+    KS_LAUNCH_CHECK("svqb_coef");
+  }
   const auto* M = static_cast<const c2<T>*>(w.M);
   if ((rc = rotate<T>(L1, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(out), nullptr, ld, s))) return rc;
   if (AB) {
     auto L2 = blist<T>(AB, nullptr, nullptr, ld, nb);
     if ((rc = rotate<T>(L2, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(aout), nullptr, ld, s))) return rc;
   }
-  return 0;
-}
-
-static int read_info(const int32_t* dev, int32_t* host, hipStream_t s) {
-  KS_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  KS_HIP(hipStreamSynchronize(s));
   return 0;
 }
 
@@ -435,8 +476,12 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
       if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, R, ld, s))) return rc;
     }
   }
-  // 2. W <- W D L^-H
-  if ((rc = block_orthonormalise<T>(p, w, st->Xn, nullptr, st->W, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
+  // 2. W <- W - X (X^H W), then W <- W D L^-H
+  if ((rc = project_out<T>(static_cast<const T2*>(st->X), static_cast<const T2*>(st->Xn), static_cast<T2*>(st->W), ld,
+                           nb, p.Ng, w.G, w.Cb, w.gram, s)))
+    return rc;
+  if ((rc = block_orthonormalise<T>(p, w, st->W, nullptr, st->Xn, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
+  std::swap(st->W, st->Xn);
   // 3. AW = H W
   if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->W), ld, static_cast<T2*>(st->AW), ld,
                        nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))

@@ -212,19 +212,31 @@ static int coldot(const c2<T>* A, const c2<T>* B, int64_t ld, int nb, int64_t Ng
   return 0;
 }
 
-// out = V - X (X^H V)
+// out = V - X (X^H V): one classical Gram-Schmidt pass (a Gram GEMM and a
+// rotation GEMM).  G: nb x nb FP64 scratch; Cbuf: 2nb x nb block precision.
 template <typename T>
-static int project(const ks_plan& p, const CgWs& w, const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb,
-                   hipStream_t s) {
+int project_out(const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb, int64_t Ng, double2* G, void* Cbuf,
+                void* gram_ws, hipStream_t s) {
   int rc;
   BlockList<c2<T>> LX{{X, nullptr, nullptr}, ld, nb};
   BlockList<c2<T>> LV{{V, nullptr, nullptr}, ld, nb};
-  if ((rc = gram_general<T>(LX, LV, nb, p.Ng, w.G, nb, w.gram, s))) return rc;
+  if ((rc = gram_general<T>(LX, LV, nb, Ng, G, nb, gram_ws, s))) return rc;
   hipLaunchKernelGGL((k_proj_coef<T>), dim3((unsigned)std::min<int64_t>(ceil_div(2 * (int64_t)nb * nb, 256), 4096)),
-                     dim3(256), 0, s, w.G, nb, static_cast<c2<T>*>(w.C));
+                     dim3(256), 0, s, G, nb, static_cast<c2<T>*>(Cbuf));
   KS_LAUNCH_CHECK("proj_coef");
   BlockList<c2<T>> LXV{{X, V, nullptr}, ld, nb};
-  return rotate<T>(LXV, 2 * nb, 2 * nb, static_cast<const c2<T>*>(w.C), 2 * nb, nb, p.Ng, out, nullptr, ld, s);
+  return rotate<T>(LXV, 2 * nb, 2 * nb, static_cast<const c2<T>*>(Cbuf), 2 * nb, nb, Ng, out, nullptr, ld, s);
+}
+
+template int project_out<double>(const double2*, const double2*, double2*, int64_t, int, int64_t, double2*, void*,
+                                 void*, hipStream_t);
+template int project_out<float>(const float2*, const float2*, float2*, int64_t, int, int64_t, double2*, void*, void*,
+                                hipStream_t);
+
+template <typename T>
+static int project(const ks_plan& p, const CgWs& w, const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb,
+                   hipStream_t s) {
+  return project_out<T>(X, V, out, ld, nb, p.Ng, w.G, w.C, w.gram, s);
 }
 
 template <typename T>

@@ -395,37 +395,67 @@ __device__ inline int sturm_count(const double* d, const double* e, int n, doubl
   return cnt;
 }
 
-__global__ void k_bisect(const double* __restrict__ d, const double* __restrict__ e, int n, int nev,
-                         double* __restrict__ w, double* __restrict__ tnorm_out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nev) return;
-  double gl = DBL_MAX, gu = -DBL_MAX;
-  for (int i = 0; i < n; ++i) {
+// Eigenvalue idx = blockIdx.x by multisection: each of the 64 lanes takes a
+// Sturm count at one of 64 interior points of [lo, hi], and the interval
+// shrinks to the sub-interval where the count passes idx (65x per round).
+__global__ void __launch_bounds__(64)
+k_bisect(const double* __restrict__ d, const double* __restrict__ e, int n, int nev, double* __restrict__ w,
+         double* __restrict__ tnorm_out) {
+  __shared__ int cnt[64];
+  __shared__ double red[2];
+  const int idx = blockIdx.x;
+  const int t = threadIdx.x;
+  double gl = DBL_MAX, gu = -DBL_MAX, em = 1.0;
+  for (int i = t; i < n; i += 64) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
     gl = fmin(gl, d[i] - r);
     gu = fmax(gu, d[i] + r);
+    if (i + 1 < n) em = fmax(em, e[i] * e[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, off, 64));
+    gu = fmax(gu, __shfl_xor(gu, off, 64));
+    em = fmax(em, __shfl_xor(em, off, 64));
   }
   const double tnorm = fmax(fabs(gl), fabs(gu));
-  const double pivmin = pivmin_of(e, n);
-  gl -= 2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
-  gu += 2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
-  double lo = gl, hi = gu;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
+  const double pivmin = DBL_MIN * em;
+  double lo = gl - (2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin);
+  double hi = gu + (2.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin);
+  for (int round = 0; round < 40; ++round) {
     if (hi - lo <= fmax(4.0 * DBL_EPSILON * tnorm, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) + pivmin) break;
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_count(d, e, n, mid, pivmin) <= idx) lo = mid; else hi = mid;
+    const double x = lo + (hi - lo) * (double)(t + 1) / 65.0;
+    cnt[t] = sturm_count(d, e, n, x, pivmin);
+    __syncthreads();
+    if (t == 0) {
+      // first point whose count exceeds idx: the eigenvalue lies below it
+      int k = 64;
+      for (int q = 0; q < 64; ++q)
+        if (cnt[q] > idx) { k = q; break; }
+      const double nlo = k == 0 ? lo : lo + (hi - lo) * (double)k / 65.0;
+      const double nhi = k == 64 ? hi : lo + (hi - lo) * (double)(k + 1) / 65.0;
+      red[0] = nlo;
+      red[1] = nhi;
+    }
+    __syncthreads();
+    const double nlo = red[0], nhi = red[1];
+    __syncthreads();
+    if (!(nhi < hi || nlo > lo)) break;  // no progress in floating point
+    lo = nlo;
+    hi = nhi;
   }
-  w[idx] = 0.5 * (lo + hi);
-  if (idx == 0) *tnorm_out = tnorm;
+  if (t == 0) {
+    w[idx] = 0.5 * (lo + hi);
+    if (idx == 0) *tnorm_out = tnorm;
+  }
 }
 
-// Clusters of eigenvalues closer than 1e-3 ||T|| (consecutive in w): start
-// indices cl[0..ncl), cl[ncl] = nev; *ncl_out = ncl.
+// Clusters of eigenvalues closer than 1e-5 ||T|| (consecutive in w): start
+// indices cl[0..ncl), cl[ncl] = nev; *ncl_out = ncl.  Outside a cluster the
+// inverse-iteration vectors are orthogonal to about eps ||T|| / gap <= 1e-11.
 __global__ void k_clusters(const double* __restrict__ w, int nev, const double* __restrict__ tnorm,
                            int32_t* __restrict__ cl, int32_t* __restrict__ ncl_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double ortol = 1e-3 * (*tnorm);
+  const double ortol = 1e-5 * (*tnorm);
   int ncl = 0;
   for (int i = 0; i < nev; ++i) {
     if (i == 0 || w[i] - w[i - 1] > ortol) cl[ncl++] = i;
@@ -652,7 +682,7 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   }
   KS_LAUNCH_CHECK("tridiagonalisation");
   hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
-  hipLaunchKernelGGL(k_bisect, dim3((unsigned)ceil_div(nev, 64)), dim3(64), 0, s, ws.d, ws.e, n, nev, w, ws.tnorm);
+  hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), 0, s, ws.d, ws.e, n, nev, w, ws.tnorm);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, w, nev, ws.tnorm, ws.cl, ws.ncl);
   hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), 0, s, ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl,
                      ws.Z, n, ws.scratch);

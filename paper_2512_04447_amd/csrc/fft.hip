@@ -416,7 +416,48 @@ k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* _
       im += red[w][(j * NBT + b) * 2 + 1];
     }
     const double d = (double)D[p0 + j];
-    dc[(int64_t)(b0 + b) * nproj + p0 + j] = cmake<T2>(T(d * re), T(d * im));
+    dc[(int64_t)(p0 + j) * nb + b0 + b] = cmake<T2>(T(d * re), T(d * im));
+  }
+}
+
+// Nonlocal scatter: hpsi[b][r] += sum_{e in row r} beta_e dc[proj_e][b] through
+// the per-point inverse table (no atomics; fixed order).  A thread owns one
+// grid point and NBS bands, so each table entry is read once per NBS bands;
+// dc is [projector][band].
+template <typename T, int NBS>
+__global__ void __launch_bounds__(256)
+k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int32_t* __restrict__ pt_ptr,
+             const int32_t* __restrict__ pt_proj, const T* __restrict__ pt_beta, const c2<T>* __restrict__ dc) {
+  using T2 = c2<T>;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b0 = blockIdx.y * NBS;
+  if (r >= Ng) return;
+  T ax[NBS], ay[NBS];
+#pragma unroll
+  for (int b = 0; b < NBS; ++b) ax[b] = ay[b] = T(0);
+  const int e0 = pt_ptr[r], e1 = pt_ptr[r + 1];
+  const int nbl = min(NBS, nb - b0);
+  for (int e = e0; e < e1; ++e) {
+    const T be = pt_beta[e];
+    const T2* c = dc + (int64_t)pt_proj[e] * nb + b0;
+#pragma unroll
+    for (int b = 0; b < NBS; ++b) {
+      if (b < nbl) {
+        const T2 v = c[b];
+        ax[b] += be * v.x;
+        ay[b] += be * v.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NBS; ++b) {
+    if (b < nbl) {
+      T2* o = hpsi + (int64_t)(b0 + b) * ld + r;
+      T2 v = *o;
+      v.x += ax[b];
+      v.y += ay[b];
+      *o = v;
+    }
   }
 }
 
@@ -473,7 +514,7 @@ static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t 
   TimerScope ts(KF_PASS_C, s);
   if (mode == 0)
     hipLaunchKernelGGL((k_pass_c<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
-                       dst, ldd, tw1, tw2, V, psi, ldp, p.nproj ? p.pt_ptr : nullptr, p.pt_proj,
+                       dst, ldd, tw1, tw2, V, psi, ldp, nullptr, p.pt_proj,
                        static_cast<const T*>(p.pt_beta), dc, p.nproj, res, lock_tol);
   else
     hipLaunchKernelGGL((k_pass_c<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
@@ -552,7 +593,16 @@ int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* 
   if (p.nproj > 0 && (rc = nl_project<T>(p, psi, ldp, nb, dc, s))) return rc;
   if ((rc = pass_a<T>(p, 0, psi, nullptr, nullptr, ldp, tmp, ldt, nb, nullptr, s))) return rc;
   if ((rc = pass_b<T>(p, 0, tmp, ldt, nb, nullptr, nullptr, s))) return rc;
-  return pass_c<T>(p, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s);
+  if ((rc = pass_c<T>(p, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s))) return rc;
+  if (p.nproj > 0) {
+    constexpr int NBS = 16;
+    dim3 grid((unsigned)ceil_div(p.Ng, 256), (unsigned)ceil_div(nb, NBS));
+    TimerScope ts(KF_NL_PROJECT, s);
+    hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(256), 0, s, hpsi, ldh, nb, p.Ng, p.pt_ptr, p.pt_proj,
+                       static_cast<const T*>(p.pt_beta), dc);
+    KS_LAUNCH_CHECK("nl_scatter");
+  }
+  return 0;
 }
 
 template <typename T>

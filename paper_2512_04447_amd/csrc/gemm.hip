@@ -190,7 +190,7 @@ k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, 
     while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
   }
   const int tj = full ? t : ti + t;
-  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < TILE * TILE; e += gridDim.y * blockDim.x) {
     const int i = e / TILE, j = e - i * TILE;
     const int gi = ti * TILE + i, gj = tj * TILE + j;
     if (gi >= m || gj >= m) continue;
@@ -268,10 +268,10 @@ static int gram_impl(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, cons
     hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, fl, partS,
                        partH);
   KS_LAUNCH_CHECK("gram");
-  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, fl, S, lds_);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu, 16), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, fl, S, lds_);
   KS_LAUNCH_CHECK("gram_reduce");
   if (B2) {
-    hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu), dim3(256), 0, s, partH, g.nsplit, g.ntile, g.ntu, m, fl, H, ldh);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu, 16), dim3(256), 0, s, partH, g.nsplit, g.ntile, g.ntu, m, fl, H, ldh);
     KS_LAUNCH_CHECK("gram_reduce");
   }
   return 0;

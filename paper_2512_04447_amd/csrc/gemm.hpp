@@ -34,6 +34,12 @@ template <typename T>
 int gram_general(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B, int m, int64_t K, double2* G, int ldg,
                  void* work, hipStream_t s);
 
+// out = V - X (X^H V) for nb-column blocks (cg.hip).  G: nb x nb FP64;
+// Cbuf: 2nb x nb in the block precision; gram_ws: gram_work_bytes(nb, Ng).
+template <typename T>
+int project_out(const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb, int64_t Ng, double2* G, void* Cbuf,
+                void* gram_ws, hipStream_t s);
+
 // Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng, c2<T>* Y,

@@ -63,7 +63,8 @@ def test_mixed_lobpcg_c1_eigenvalues_within_1e6(ks):
     lob.init()
     best = None
     for it in range(60):
-        lob.step(b.KS_PRECOND_TPA, 1e-6)
+        # lock above the FP32 residual floor (about eps32 * ||H||)
+        lob.step(b.KS_PRECOND_TPA, 1e-4)
         th = lob.theta.cpu().numpy()
         err = np.abs(th - st_ref.theta).max()
         best = err if best is None else min(best, err)
