@@ -44,7 +44,73 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true")
+    ap.add_argument("--compare", default=None,
+                    help="time-to-1e-6-Ha comparison on one cell (C2, C3 or C4) instead of the throughput bench")
+    ap.add_argument("--mixed-lock", type=float, default=1e-4)
+    ap.add_argument("--weights", default=None, help="FP32 parameters of the learned preconditioner (.npy)")
+    ap.add_argument("--maxit", type=int, default=150)
     return ap.parse_args()
+
+
+def compare(args):
+    """Time to 1e-6 Ha from the same initial block: FP64 + TPA (the plain
+    path, run to residual 1e-8; its final Ritz values are the reference),
+    then the mixed-precision path with TPA and with the trained network.
+    The FP64 run's own time to 1e-6 Ha is read from its history."""
+    import torch
+
+    import ksinputs as ki
+    from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import learned as lr
+
+    cfg = ki.config(args.compare)
+    cell = ki.make_cell(cfg)
+    t0 = time.perf_counter()
+    X0 = ki.make_x0(cfg)
+    log(f"[compare] {cfg.name}: n={cfg.n} nb={cfg.nb} ntrack={cfg.ntrack} X0 in {time.perf_counter() - t0:.1f}s")
+    proj = b.ProjectorArrays.from_cell(cell) if cell.nproj else None
+    x0 = torch.from_numpy(X0).cuda()
+    del X0
+    out = {}
+
+    def leg(name, prec, pc, lock, ref=None, res_tol=0.0, params=None):
+        plan = b.Plan(cell.n, cell.L, proj, cfg.nb, prec)
+        dt = torch.float64 if prec == b.KS_FP64 else torch.float32
+        v = torch.from_numpy(cell.V).to(dt).cuda()
+        xs = x0 if prec == b.KS_FP64 else x0.to(torch.complex64)
+        r = lr.run_to_tolerance(plan, v, xs, cfg.ntrack, pc, lock, args.maxit, ref=ref, res_tol=res_tol,
+                                cnn_params=params, log=log)
+        lob = r.pop("lobpcg")
+        th = lob.theta[: cfg.ntrack].cpu().numpy()
+        hist = r.pop("history")
+        log(f"[compare] {name}: {r['iterations']} iterations, {r['seconds']:.2f}s, max res {r['max_res']:.2e}")
+        r["max_res_history"] = [float(f"{h[1]:.3e}") for h in hist]
+        del lob, xs, v
+        torch.cuda.empty_cache()
+        return r, hist, th
+
+    r64, h64, ref = leg("fp64+tpa", b.KS_FP64, b.KS_PRECOND_TPA, 0.1 * cfg.res_tol, res_tol=cfg.res_tol)
+    # FP64's own time to 1e-6 Ha against its converged values
+    first = next((i for i, h in enumerate(h64) if np.abs(h[3] - ref).max() <= 1e-6), len(h64) - 1)
+    out["fp64_tpa"] = {"seconds_to_1e-6_Ha": round(h64[first][0], 3), "iterations_to_1e-6_Ha": first + 1,
+                       "converged_iterations": r64["iterations"], "final_max_res": r64["max_res"],
+                       "s_per_iter": round(r64["seconds"] / r64["iterations"], 4),
+                       "max_res_history": r64["max_res_history"]}
+    rm, hm, thm = leg("mixed+tpa", b.KS_MIXED_FP32, b.KS_PRECOND_TPA, args.mixed_lock, ref=ref)
+    out["mixed_tpa"] = {"seconds_to_1e-6_Ha": round(rm["seconds"], 3), "iterations_to_1e-6_Ha": rm["iterations"],
+                        "max_err_Ha": rm["max_err"], "s_per_iter": round(rm["seconds"] / rm["iterations"], 4),
+                        "reached": bool(rm["max_err"] <= 1e-6), "max_res_history": rm["max_res_history"]}
+    wpath = args.weights or lr.WEIGHTS
+    if os.path.exists(wpath):
+        params = torch.from_numpy(np.load(wpath)).cuda()
+        rc, hc, thc = leg("mixed+cnn", b.KS_MIXED_FP32, b.KS_PRECOND_CNN, args.mixed_lock, ref=ref, params=params)
+        out["mixed_cnn"] = {"seconds_to_1e-6_Ha": round(rc["seconds"], 3), "iterations_to_1e-6_Ha": rc["iterations"],
+                            "max_err_Ha": rc["max_err"], "s_per_iter": round(rc["seconds"] / rc["iterations"], 4),
+                            "reached": bool(rc["max_err"] <= 1e-6), "switched_to_tpa_at": rc["switched_to_tpa_at"],
+                            "max_res_history": rc["max_res_history"]}
+    print(json.dumps({"metric": METRIC, "compare": cfg.name, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": cfg.name, "Ng": cfg.Ng, "bands": cfg.nb, "tracked": cfg.ntrack},
+                      "legs": out}))
 
 
 def family_work(cfg, steps_info):
@@ -80,6 +146,9 @@ def main():
     from paper_2512_04447_amd import binding as b
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.compare:
+        compare(args)
+        return
     cfg = ki.config(args.config)
     cell = ki.make_cell(cfg)
     X0 = ki.make_x0(cfg)

@@ -337,10 +337,16 @@ class Lobpcg:
                                 C.c_void_p(_stream(self.stream)))
         check(rc, "lobpcg_init")
 
-    def step(self, precond: int = KS_PRECOND_TPA, lock_tol: float = 0.0):
+    def step(self, precond: int = KS_PRECOND_TPA, lock_tol: float = 0.0, cnn_params=None):
+        """One iteration; ``cnn_params`` (FP32 device tensor of KS_CNN_NPARAM
+        values) is required for KS_PRECOND_CNN."""
         o = KsLobpcgOpts()
         o.precond = precond
         o.lock_tol = float(lock_tol)
+        if cnn_params is not None:
+            if cnn_params.numel() != KS_CNN_NPARAM:
+                raise KsError("cnn_params must hold KS_CNN_NPARAM values")
+            o.cnn_params = _ptr(cnn_params)
         rc = load().lobpcg_step(self.plan.handle, _ptr(self.v), C.byref(self.st), C.byref(o), _ptr(self.work),
                                 self.work.numel(), C.c_void_p(_stream(self.stream)))
         check(rc, "lobpcg_step")

@@ -122,6 +122,28 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
       }
     }
   }
+  // per block of kScatterPts points: the projectors its entries touch, and
+  // the entries' projector ids rewritten as indices into that list
+  const int64_t nblk = (p->Ng + kScatterPts - 1) / kScatterPts;
+  std::vector<int32_t> blk_ptr(nblk + 1, 0), blk_proj;
+  std::vector<int32_t> local(ps->n_proj, -1);
+  int maxl = 0;
+  for (int64_t k = 0; k < nblk; ++k) {
+    const int64_t r0 = k * kScatterPts, r1 = std::min<int64_t>(p->Ng, r0 + kScatterPts);
+    const size_t first = blk_proj.size();
+    for (int32_t e = cnt[r0]; e < cnt[r1]; ++e)
+      if (local[pt_proj[e]] < 0) {
+        local[pt_proj[e]] = 0;
+        blk_proj.push_back(pt_proj[e]);
+      }
+    std::sort(blk_proj.begin() + first, blk_proj.end());
+    for (size_t i = first; i < blk_proj.size(); ++i) local[blk_proj[i]] = (int32_t)(i - first);
+    for (int32_t e = cnt[r0]; e < cnt[r1]; ++e) pt_proj[e] = local[pt_proj[e]];
+    for (size_t i = first; i < blk_proj.size(); ++i) local[blk_proj[i]] = -1;
+    blk_ptr[k + 1] = (int32_t)blk_proj.size();
+    maxl = std::max(maxl, (int)(blk_proj.size() - first));
+  }
+  if (blk_proj.empty()) blk_proj.push_back(0);
   int maxp = 0;
   for (int a = 0; a < na; ++a) maxp = std::max(maxp, pp[a + 1] - pp[a]);
   p->natoms = na;
@@ -129,7 +151,10 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
   p->maxp = maxp;
   p->nsupp = ps->n_supp;
   p->nnz = nnz;
+  p->maxl = maxl;
   int rc;
+  if ((rc = upload_vec(blk_ptr, &p->blk_ptr))) return rc;
+  if ((rc = upload_vec(blk_proj, &p->blk_proj))) return rc;
   if ((rc = upload_vec(sp, &p->supp_ptr))) return rc;
   if ((rc = upload_vec(si, &p->supp_idx))) return rc;
   if ((rc = upload_vec(pp, &p->proj_ptr))) return rc;
@@ -269,6 +294,7 @@ struct LobWs {
   float* cnn_x;    // chunk x 3 x Ng
   float* cnn_buf;  // chunk x 32 x Ng
   float* cnn_y;    // chunk x 2 x Ng
+  int32_t* cnn_bad; // chunk flags: non-finite network output
   char* end;
 };
 
@@ -304,6 +330,7 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.cnn_x = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 3 * p.Ng * 4));
   w.cnn_buf = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 32 * p.Ng * 4));
   w.cnn_y = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 2 * p.Ng * 4));
+  w.cnn_bad = reinterpret_cast<int32_t*>(take((size_t)w.cnn_chunk * 4));
   w.end = q;
   return w;
 }
@@ -473,7 +500,7 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
       if ((rc = cnn_input_impl<T>(p, R, ld, st->res + b0, static_cast<const T*>(v), st->theta + b0, nc, w.cnn_x, s)))
         return rc;
       if ((rc = cnn_infer_impl(p, o->cnn_params, nc, w.cnn_x, w.cnn_y, w.cnn_buf, s))) return rc;
-      if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, R, ld, s))) return rc;
+      if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, w.cnn_bad, R, ld, s))) return rc;
     }
   }
   // 2. W <- W - X (X^H W), then W <- W D L^-H
@@ -662,7 +689,8 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
 int ks_plan_destroy(ks_plan* p) {
   if (!p) return 0;
   for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
-  void* bufs[] = {p->supp_ptr, p->supp_idx, p->proj_ptr, p->beta_ptr, p->beta, p->Dcoef, p->pt_ptr, p->pt_proj, p->pt_beta};
+  void* bufs[] = {p->supp_ptr, p->supp_idx, p->proj_ptr, p->beta_ptr, p->beta, p->Dcoef, p->pt_ptr, p->pt_proj, p->pt_beta,
+                  p->blk_ptr, p->blk_proj};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;

@@ -39,69 +39,80 @@ __global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, doub
 
 // Unblocked Cholesky of the diagonal block at k0 (kb <= NB columns) in LDS,
 // then the inverse of that block (for the panel and the triangular solves).
+// Step j updates the trailing block with the unscaled column j divided by
+// the pivot d_j; scaling column j by 1/sqrt(d_j) touches only column j, so it
+// runs in the same phase as the next step's update and one barrier per
+// column suffices.
 __global__ void __launch_bounds__(256)
 k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restrict__ dmax,
         int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv) {
   __shared__ double2 a[NB][NB + 1];
-  __shared__ int failed;
+  __shared__ double2 x[NB][NB + 1];
   if (*info != 0) return;
   const double tol = CHOL_TOL * (*dmax);
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
     const int i = e % NB, j = e / NB;
     a[i][j] = (i < kb && j < kb) ? S[(k0 + i) + (int64_t)(k0 + j) * lds] : make_double2(0.0, 0.0);
   }
-  if (threadIdx.x == 0) failed = 0;
   __syncthreads();
   for (int j = 0; j < kb; ++j) {
     const double d = a[j][j].x;
     if (!(d > tol)) {
-      if (threadIdx.x == 0) { failed = 1; *info = info_offset + k0 + j + 1; }
+      if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
       return;  // uniform: every thread read the same d
     }
-    const double ljj = sqrt(d);
-    __syncthreads();
-    if (threadIdx.x == 0) a[j][j] = make_double2(ljj, 0.0);
-    for (int i = j + 1 + threadIdx.x; i < kb; i += blockDim.x) {
-      a[i][j].x /= ljj;
-      a[i][j].y /= ljj;
-    }
-    __syncthreads();
-    // trailing update of the block: a[i][p] -= a[i][j] conj(a[p][j]), j < p <= i
+    // column j-1 was scaled in the previous phase by other threads: no
+    // thread reads it here.  Update a[i][p] -= a[i][j] conj(a[p][j]) / d.
+    const double rd = 1.0 / d;
     for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
       const int i = e % kb, p = e / kb;
       if (p > j && i >= p) {
-        const double2 x = a[i][j], y = a[p][j];
-        a[i][p].x -= x.x * y.x + x.y * y.y;
-        a[i][p].y -= x.y * y.x - x.x * y.y;
+        const double2 u = a[i][j], v = a[p][j];
+        a[i][p].x -= (u.x * v.x + u.y * v.y) * rd;
+        a[i][p].y -= (u.y * v.x - u.x * v.y) * rd;
       }
     }
+    // scale column j (entries i > j are read above only by this step)
     __syncthreads();
+    const double ljj = sqrt(d), rl = 1.0 / ljj;
+    for (int i = j + threadIdx.x; i < kb; i += blockDim.x) {
+      if (i == j) a[j][j] = make_double2(ljj, 0.0);
+      else { a[i][j].x *= rl; a[i][j].y *= rl; }
+    }
   }
-  // write L_kk (lower part) back
+  __syncthreads();
   for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
     const int i = e % kb, j = e / kb;
     if (i >= j) S[(k0 + i) + (int64_t)(k0 + j) * lds] = a[i][j];
   }
-  // inverse: column c of X = L^-1 solves L x = e_c by forward substitution
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    double2 x[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) x[i] = make_double2(0.0, 0.0);
-    if (c < kb) {
-      for (int i = c; i < kb; ++i) {
-        double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
-        for (int p = c; p < i; ++p) {
-          const double2 l = a[i][p];
-          s.x -= l.x * x[p].x - l.y * x[p].y;
-          s.y -= l.x * x[p].y + l.y * x[p].x;
-        }
-        const double inv = 1.0 / a[i][i].x;
-        x[i] = make_double2(s.x * inv, s.y * inv);
+  // inverse X = L^-1 by rows: X[i][c] = (delta_ic - sum_{c<=p<i} L[i][p] X[p][c]) / L[i][i];
+  // 8 threads per column c split the sum over p and combine by shuffles
+  const int c = threadIdx.x >> 3, part = threadIdx.x & 7;
+  for (int i = 0; i < NB; ++i) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (c < kb && i < kb && c < i)
+      for (int p = c + part; p < i; p += 8) {
+        const double2 l = a[i][p], y = x[p][c];
+        acc.x += l.x * y.x - l.y * y.y;
+        acc.y += l.x * y.y + l.y * y.x;
       }
+    for (int off = 4; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 8);
+      acc.y += __shfl_xor(acc.y, off, 8);
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) linv[i + (int64_t)c * NB] = x[i];
+    if (part == 0 && c < NB) {
+      double2 v = make_double2(0.0, 0.0);
+      if (c < kb && i < kb && c <= i) {
+        const double inv = 1.0 / a[i][i].x;
+        v = make_double2(((i == c ? 1.0 : 0.0) - acc.x) * inv, -acc.y * inv);
+      }
+      x[i][c] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    linv[i + (int64_t)j * NB] = x[i][j];
   }
 }
 

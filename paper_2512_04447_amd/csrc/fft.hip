@@ -297,15 +297,13 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
 // ---------------------------------------------------------------- pass C
 // The input plane holds conj-free spectral data in (y, z); the inverse is
 // conj(FFT(conj(.))) / Ng.
-// MODE 0 (H): out = Tpsi + V psi + sum_e beta_e dc[band][proj_e].
+// MODE 0 (H): out = Tpsi + V psi.
 // MODE 1 (preconditioner): out = mask[band] * IFFT(.), mask from res > lock_tol.
 template <typename T, int MAXE, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict__ dst, int64_t ldd,
          const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, const T* __restrict__ V,
-         const c2<T>* __restrict__ psi, int64_t ldp, const int32_t* __restrict__ pt_ptr,
-         const int32_t* __restrict__ pt_proj, const T* __restrict__ pt_beta,
-         const c2<T>* __restrict__ dc, int nproj, const double* __restrict__ res, double lock_tol) {
+         const c2<T>* __restrict__ psi, int64_t ldp, const double* __restrict__ res, double lock_tol) {
   using T2 = c2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* s = reinterpret_cast<T2*>(smem_raw);
@@ -323,24 +321,11 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   T2* out = dst + band * ldd + off;
   if (MODE == 0) {
     const T2* ps = psi + band * ldp + off;
-    const T2* dcb = dc + (int64_t)band * nproj;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      const int64_t r = off + i;
       T2 t = s[i];
       T2 p = ps[i];
-      const T vr = V[r];
-      T ox = t.x * scale + vr * p.x;
-      T oy = -t.y * scale + vr * p.y;
-      if (pt_ptr != nullptr) {
-        const int e0 = pt_ptr[r], e1 = pt_ptr[r + 1];
-        for (int e = e0; e < e1; ++e) {
-          const T b = pt_beta[e];
-          const T2 c = dcb[pt_proj[e]];
-          ox += b * c.x;
-          oy += b * c.y;
-        }
-      }
-      out[i] = cmake<T2>(ox, oy);
+      const T vr = V[off + i];
+      out[i] = cmake<T2>(t.x * scale + vr * p.x, -t.y * scale + vr * p.y);
     }
   } else {
     const T m = (res[band] > lock_tol) ? scale : T(0);
@@ -421,32 +406,44 @@ k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* _
 }
 
 // Nonlocal scatter: hpsi[b][r] += sum_{e in row r} beta_e dc[proj_e][b] through
-// the per-point inverse table (no atomics; fixed order).  A thread owns one
-// grid point and NBS bands, so each table entry is read once per NBS bands;
-// dc is [projector][band].
+// the per-point inverse table (no atomics; fixed order).  A block owns
+// kScatterPts consecutive grid points and NBS bands; the dc rows of the
+// projectors its points touch are staged in LDS first (rows padded by one
+// element so that lanes reading different rows fall in different banks),
+// and each table entry indexes that list.  dc is [projector][band].
 template <typename T, int NBS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kScatterPts)
 k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int32_t* __restrict__ pt_ptr,
-             const int32_t* __restrict__ pt_proj, const T* __restrict__ pt_beta, const c2<T>* __restrict__ dc) {
+             const int32_t* __restrict__ pt_lproj, const T* __restrict__ pt_beta,
+             const int32_t* __restrict__ blk_ptr, const int32_t* __restrict__ blk_proj,
+             const c2<T>* __restrict__ dc) {
   using T2 = c2<T>;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int ROW = NBS + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* sdc = reinterpret_cast<T2*>(smem_raw);
   const int b0 = blockIdx.y * NBS;
+  const int nbl = min(NBS, nb - b0);
+  const int l0 = blk_ptr[blockIdx.x];
+  const int nl = blk_ptr[blockIdx.x + 1] - l0;
+  for (int i = threadIdx.x; i < nl * NBS; i += blockDim.x) {
+    const int l = i / NBS, b = i - l * NBS;
+    sdc[l * ROW + b] = b < nbl ? dc[(int64_t)blk_proj[l0 + l] * nb + b0 + b] : cmake<T2>(T(0), T(0));
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * kScatterPts + threadIdx.x;
   if (r >= Ng) return;
   T ax[NBS], ay[NBS];
 #pragma unroll
   for (int b = 0; b < NBS; ++b) ax[b] = ay[b] = T(0);
   const int e0 = pt_ptr[r], e1 = pt_ptr[r + 1];
-  const int nbl = min(NBS, nb - b0);
   for (int e = e0; e < e1; ++e) {
     const T be = pt_beta[e];
-    const T2* c = dc + (int64_t)pt_proj[e] * nb + b0;
+    const T2* c = sdc + pt_lproj[e] * ROW;
 #pragma unroll
     for (int b = 0; b < NBS; ++b) {
-      if (b < nbl) {
-        const T2 v = c[b];
-        ax[b] += be * v.x;
-        ay[b] += be * v.y;
-      }
+      const T2 v = c[b];
+      ax[b] += be * v.x;
+      ay[b] += be * v.y;
     }
   }
 #pragma unroll
@@ -514,12 +511,10 @@ static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t 
   TimerScope ts(KF_PASS_C, s);
   if (mode == 0)
     hipLaunchKernelGGL((k_pass_c<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
-                       dst, ldd, tw1, tw2, V, psi, ldp, nullptr, p.pt_proj,
-                       static_cast<const T*>(p.pt_beta), dc, p.nproj, res, lock_tol);
+                       dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   else
     hipLaunchKernelGGL((k_pass_c<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
-                       dst, ldd, tw1, tw2, V, psi, ldp, nullptr, nullptr, (const T*)nullptr, dc, 0, res,
-                       lock_tol);
+                       dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   KS_LAUNCH_CHECK("pass C");
   return 0;
 }
@@ -585,6 +580,32 @@ static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2
   return 0;
 }
 
+template <typename T, int NBS>
+static void launch_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
+  const size_t lds = (size_t)p.maxl * (NBS + 1) * sizeof(c2<T>);
+  dim3 grid((unsigned)ceil_div(p.Ng, kScatterPts), (unsigned)ceil_div(nb, NBS));
+  hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(kScatterPts), lds, s, hpsi, ldh, nb, p.Ng, p.pt_ptr,
+                     p.pt_proj, static_cast<const T*>(p.pt_beta), p.blk_ptr, p.blk_proj, dc);
+}
+
+// The widest band group whose staged projector rows fit in 64 KB of LDS.
+template <typename T>
+static int nl_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
+  TimerScope ts(KF_NL_PROJECT, s);
+  const size_t row = (size_t)p.maxl * sizeof(c2<T>);
+  constexpr size_t kMax = 64 * 1024;
+  if (row * 17 <= kMax)
+    launch_scatter<T, 16>(p, hpsi, ldh, nb, dc, s);
+  else if (row * 9 <= kMax)
+    launch_scatter<T, 8>(p, hpsi, ldh, nb, dc, s);
+  else if (row * 5 <= kMax)
+    launch_scatter<T, 4>(p, hpsi, ldh, nb, dc, s);
+  else
+    return fail(KS_E_UNSUPPORTED, "too many projectors touch one block of grid points");
+  KS_LAUNCH_CHECK("nl_scatter");
+  return 0;
+}
+
 template <typename T>
 int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* hpsi, int64_t ldh, int nb,
             c2<T>* tmp, c2<T>* dc, hipStream_t s) {
@@ -594,14 +615,7 @@ int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* 
   if ((rc = pass_a<T>(p, 0, psi, nullptr, nullptr, ldp, tmp, ldt, nb, nullptr, s))) return rc;
   if ((rc = pass_b<T>(p, 0, tmp, ldt, nb, nullptr, nullptr, s))) return rc;
   if ((rc = pass_c<T>(p, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s))) return rc;
-  if (p.nproj > 0) {
-    constexpr int NBS = 16;
-    dim3 grid((unsigned)ceil_div(p.Ng, 256), (unsigned)ceil_div(nb, NBS));
-    TimerScope ts(KF_NL_PROJECT, s);
-    hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(256), 0, s, hpsi, ldh, nb, p.Ng, p.pt_ptr, p.pt_proj,
-                       static_cast<const T*>(p.pt_beta), dc);
-    KS_LAUNCH_CHECK("nl_scatter");
-  }
+  if (p.nproj > 0 && (rc = nl_scatter<T>(p, hpsi, ldh, nb, dc, s))) return rc;
   return 0;
 }
 

@@ -8,6 +8,10 @@
 
 namespace ks {
 
+// Points per block of the nonlocal scatter (its projector lists are built
+// for blocks of this many consecutive grid points).
+constexpr int kScatterPts = 256;
+
 constexpr int kMaxStages = 10;
 constexpr int kThreads = 256;
 
@@ -50,8 +54,12 @@ struct ks_plan {
   void* beta = nullptr;      // plan precision
   void* Dcoef = nullptr;     // plan precision
   int32_t* pt_ptr = nullptr; // Ng + 1
-  int32_t* pt_proj = nullptr;
+  int32_t* pt_proj = nullptr; // projector of each entry, local to its block of kScatterPts points
   void* pt_beta = nullptr;   // plan precision
+  // projectors touched by each block of kScatterPts consecutive points
+  int32_t* blk_ptr = nullptr;   // nblk + 1
+  int32_t* blk_proj = nullptr;  // global projector ids, ascending within a block
+  int32_t maxl = 0;             // largest per-block projector count
 };
 
 namespace ks {
@@ -100,7 +108,8 @@ template <typename T>
 int cnn_input_impl(const ks_plan& p, const c2<T>* R, int64_t ld, const double* rnorm, const T* V,
                    const double* theta, int nb, float* x, hipStream_t s);
 template <typename T>
-int cnn_output_impl(const ks_plan& p, const float* y, int nb, const double* res, double lock_tol, c2<T>* W, int64_t ld,
+int cnn_output_impl(const ks_plan& p, const float* y, int nb, const double* res, double lock_tol, int32_t* bad,
+                    c2<T>* W, int64_t ld,
                     hipStream_t s);
 
 }  // namespace ks

@@ -80,6 +80,108 @@ def generate_pairs(cell, cfg, X0, n_iters: int, max_pairs: int, cg_maxit: int = 
     return PairSet(x, t, np.concatenate(ths)[:max_pairs], its[:max_pairs])
 
 
+def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 2, val_frac: float = 0.1,
+                log=print, params=None):
+    """Adam over pairs from several grids: ``sets`` is a list of (plan, PairSet).
+
+    Every batch comes from one grid (the convolution kernels take one grid
+    per call); batches of all grids are shuffled together.  One parameter
+    vector and one Adam state are shared.  Returns (params, history) with the
+    validation loss (mean over held-out pairs of all grids) per epoch.
+    """
+    import torch
+
+    rng = np.random.default_rng(seed)
+    if params is None:
+        params = torch.from_numpy(kaiming_params(seed)).cuda()
+    nets, splits = [], []
+    for plan, pairs in sets:
+        net = b.Cnn(plan, params, batch)
+        if nets:
+            net.params, net.m, net.v, net.grads = nets[0].params, nets[0].m, nets[0].v, nets[0].grads
+        nets.append(net)
+        n = pairs.x.shape[0]
+        perm = rng.permutation(n)
+        nval = max(1, int(round(val_frac * n)))
+        splits.append((perm[:nval], perm[nval:]))
+    step = [0]
+
+    def evaluate():
+        tot, cnt = 0.0, 0
+        for net, (plan, pairs), (val, _) in zip(nets, sets, splits):
+            for s0 in range(0, len(val), batch):
+                j = torch.from_numpy(val[s0:s0 + batch]).cuda()
+                net.forward(pairs.x[j])
+                tot += float(net.loss_grad(pairs.t[j]).sum())
+                cnt += len(j)
+        return tot / max(cnt, 1)
+
+    hist = [(0, evaluate())]
+    log(f"[train] epoch 0 val loss {hist[-1][1]:.4f}")
+    for ep in range(1, epochs + 1):
+        t0 = time.time()
+        work = []
+        for g, (_, tr) in enumerate(splits):
+            order = rng.permutation(tr)
+            work.extend((g, order[s0:s0 + batch]) for s0 in range(0, len(order) - batch + 1, batch))
+        for k in rng.permutation(len(work)):
+            g, idx = work[k]
+            net, pairs = nets[g], sets[g][1]
+            j = torch.from_numpy(idx).cuda()
+            xb, tb = pairs.x[j], pairs.t[j]
+            net.forward(xb)
+            net.loss_grad(tb)
+            net.backward(xb)
+            step[0] += 1
+            net.t = step[0] - 1
+            net.adam(lr)
+        hist.append((ep, evaluate()))
+        log(f"[train] epoch {ep} val loss {hist[-1][1]:.4f} ({time.time() - t0:.1f}s, {len(work)} batches)")
+    return nets[0].params, hist
+
+
+def run_to_tolerance(plan, v, X0, ntrack: int, precond: int, lock_tol: float, maxit: int, ref=None,
+                     tol_ha: float = 1e-6, res_tol: float = 0.0, cnn_params=None, switch_to_tpa: bool = True,
+                     log=print):
+    """LOBPCG from X0 with one D2H read of (theta, res) per iteration.
+
+    Stops at the first iteration where every tracked |theta_i - ref_i| <=
+    tol_ha (when ref is given), or max tracked residual <= res_tol, or
+    maxit.  With the learned preconditioner the run switches to TPA for
+    good when the max tracked residual has not dropped by 10% over 3
+    iterations.  Returns a dict with the wall time from X0 (init included),
+    the iteration count and the per-iteration history.
+    """
+    import torch
+
+    lob = b.Lobpcg(plan, v, X0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lob.init()
+    hist = []
+    pc = precond
+    switched = None
+    for it in range(1, maxit + 1):
+        lob.step(pc, lock_tol, cnn_params if pc == b.KS_PRECOND_CNN else None)
+        tr = torch.cat([lob.theta[:ntrack], lob.res[:ntrack]]).cpu().numpy()
+        th, res = tr[:ntrack], tr[ntrack:]
+        rmax = float(res.max())
+        err = float(np.abs(th - ref).max()) if ref is not None else None
+        hist.append((time.perf_counter() - t0, rmax, err, th))
+        if it % 5 == 0:
+            log(f"[tta] iteration {it}: max res {rmax:.3e}" + (f", max err {err:.3e}" if err is not None else "")
+                + f", {hist[-1][0]:.1f}s")
+        if pc == b.KS_PRECOND_CNN and switch_to_tpa and it > 3 and rmax > 0.9 * hist[-4][1]:
+            pc = b.KS_PRECOND_TPA
+            switched = it
+            log(f"[tta] learned preconditioner stalled at iteration {it}; switching to TPA")
+        if (ref is not None and err <= tol_ha) or rmax <= res_tol:
+            break
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t0, "iterations": it, "max_res": rmax, "max_err": err,
+            "switched_to_tpa_at": switched, "history": hist, "lobpcg": lob}
+
+
 def train(plan, pairs: PairSet, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 2, val_frac: float = 0.1,
           log=print):
     """Adam on the scale-invariant loss; returns (params tensor, history)."""
@@ -117,3 +219,64 @@ def train(plan, pairs: PairSet, epochs: int, batch: int = 16, lr: float = 1e-3, 
         hist.append((ep, evaluate(val)))
         log(f"[train] epoch {ep} val loss {hist[-1][1]:.4f} ({time.time() - t0:.1f}s)")
     return net.params, hist
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights", "cnn_precond.npy")
+
+
+def main(argv=None):
+    """Generate pairs on the 8-atom (16^3) and 64-atom (48^3) cells, train
+    on the GPU and save the FP32 parameters."""
+    import argparse
+    import json
+    import os
+    import sys
+
+    import torch
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import ksinputs as ki
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--c1-seeds", type=int, default=8)
+    ap.add_argument("--c1-iters", type=int, default=40)
+    ap.add_argument("--c2-seeds", type=int, default=2)
+    ap.add_argument("--c2-iters", type=int, default=25)
+    ap.add_argument("--max-pairs", type=int, default=12000)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--log", default=None)
+    a = ap.parse_args(argv)
+
+    def log(*x):
+        print(*x, flush=True)
+
+    sets = []
+    for name, nseed, nit in (("C1", a.c1_seeds, a.c1_iters), ("C2", a.c2_seeds, a.c2_iters)):
+        cfg = ki.config(name)
+        cell = ki.make_cell(cfg)
+        parts = []
+        for sd in range(1, nseed + 1):
+            ps = generate_pairs(cell, cfg, ki.make_x0(cfg, seed=sd), nit, a.max_pairs // 2, log=log)
+            parts.append(ps)
+        pairs = PairSet(torch.cat([p.x for p in parts]), torch.cat([p.t for p in parts]),
+                        np.concatenate([p.theta for p in parts]), sum((p.iterations for p in parts), []))
+        # the convolution kernels take only the grid from a plan
+        plan = b.Plan(cell.n, cell.L, None, 16, b.KS_MIXED_FP32)
+        log(f"[pairs] {name}: {pairs.x.shape[0]} pairs, CG iterations median {int(np.median(pairs.iterations))}")
+        sets.append((plan, pairs))
+    t0 = time.time()
+    params, hist = train_multi(sets, a.epochs, log=log)
+    log(f"[train] {a.epochs} epochs in {time.time() - t0:.1f}s")
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    np.save(a.out, params.cpu().numpy())
+    log(f"[train] wrote {a.out}")
+    if a.log:
+        with open(a.log, "w") as f:
+            json.dump({"pairs": {n: int(s[1].x.shape[0]) for n, s in zip(("C1", "C2"), sets)},
+                       "val_loss": hist}, f)
+
+
+if __name__ == "__main__":
+    main()
