@@ -27,6 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time to 1e-6 Ha eigenpairs & LOBPCG iter/s: FP64 vs mixed+learned precond"
+WORKLOADS = {
+    "C1": "diamond 8-atom cell, L=6.74 bohr, 16^3 grid, 16 bands, local potential only",
+    "C2": "diamond-like 2x2x2 supercell, 64 atoms, L=13.48 bohr, 48^3 grid, 160 bands, s+p KB projectors",
+    "C3": "diamond-like 3x3x3 supercell, 216 atoms, L=20.22 bohr, 96^3 grid, 480 bands, s+p KB projectors",
+    "C4": "bcc 4x4x4 supercell, 128 atoms, L=23.92 bohr, 112^3 grid, 960 bands, s+p+d KB projectors",
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
@@ -42,6 +48,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64 (the default workload) or mixed (complex64 blocks, FP32 products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true")
     ap.add_argument("--compare", default=None,
@@ -113,18 +121,22 @@ def compare(args):
                       "legs": out}))
 
 
-def family_work(cfg, steps_info):
-    """Algorithmic flops / bytes per step for each kernel family (FP64 C2)."""
+def family_work(cfg, es):
+    """Algorithmic flops / bytes per step for each kernel family; es is the
+    bytes of one complex element of the blocks (16 FP64, 8 mixed)."""
     Ng, nb = cfg.Ng, cfg.nb
     m = 3 * nb
-    es = 16
     blk = Ng * nb * es
     n_h = 3  # H-applies per step: W, P and the new X
+    # mixed path: re-orthonormalisation of X (one more self-Gram and rotation)
+    extra = 1 if es == 8 else 0
     return {
-        # Hermitian triangles: W and P self-Grams (S only), basis Gram (S and H)
-        "gram_flops": 8 * Ng * nb * (nb + 1) / 2 * 2 + 2 * 8 * Ng * m * (m + 1) / 2,
-        # W and P Cholesky-QR rotations, X and P from one pass over V
-        "rotate_flops": 8 * Ng * nb * nb * 2 + 8 * Ng * m * nb,
+        # Hermitian triangles of the W and P self-Grams (S only) and of the
+        # basis Gram (S and H); the full X^H W of the projection W - X X^H W
+        "gram_flops": 8 * Ng * (nb * (nb + 1) / 2 * (2 + extra) + nb * nb + 2 * m * (m + 1) / 2),
+        # W and P orthonormalising rotations, the projection update, and one
+        # pass over V giving X' = V C and P' = V[:, nb:] C[nb:]
+        "rotate_flops": 8 * Ng * (nb * nb * (3 + extra) + m * nb + 2 * nb * nb),
         # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-applies (R+W)
         "pass_a_bytes": blk * (2 + 3 + 2 * n_h),
         # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W) per H-apply
@@ -153,9 +165,14 @@ def main():
     cell = ki.make_cell(cfg)
     X0 = ki.make_x0(cfg)
     log(f"[bench] {cfg.name}: n={cfg.n} nb={cfg.nb} atoms={cell.natoms} nproj={cell.nproj}")
-    plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell), cfg.nb, b.KS_FP64)
+    mixed = args.precision == "mixed"
+    plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell) if cell.nproj else None, cfg.nb,
+                  b.KS_MIXED_FP32 if mixed else b.KS_FP64)
     v = torch.from_numpy(cell.V).cuda()
     x0 = torch.from_numpy(X0).cuda()
+    del X0
+    if mixed:
+        v, x0 = v.float(), x0.to(torch.complex64)
     lob = b.Lobpcg(plan, v, x0)
     lob.init()
     tol = cfg.res_tol
@@ -185,11 +202,12 @@ def main():
         b.kernel_timer(False, f)
         fam_ms[nm] = (ms / args.steps, n / args.steps)
     log("[bench] per-step ms by family: " + ", ".join(f"{k}={v[0]:.3f} ({v[1]:.0f} launches)" for k, v in fam_ms.items()))
-    work = family_work(cfg, None)
+    work = family_work(cfg, 8 if mixed else 16)
+    mma_peak = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
     rates = {
-        "gram": ("mfma", work["gram_flops"] / 1e12 / (fam_ms["gram"][0] / 1e3), FP64_PEAK_TFS, "TFLOP/s",
+        "gram": ("mfma", work["gram_flops"] / 1e12 / (fam_ms["gram"][0] / 1e3), mma_peak, "TFLOP/s",
                  work["gram_flops"] / max(fam_ms["gram"][1], 1)),
-        "rotate": ("mfma", work["rotate_flops"] / 1e12 / (fam_ms["rotate"][0] / 1e3), FP64_PEAK_TFS, "TFLOP/s",
+        "rotate": ("mfma", work["rotate_flops"] / 1e12 / (fam_ms["rotate"][0] / 1e3), mma_peak, "TFLOP/s",
                    work["rotate_flops"] / max(fam_ms["rotate"][1], 1)),
         "pass_a": ("hbm", work["pass_a_bytes"] / 1e9 / (fam_ms["pass_a"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
                    work["pass_a_bytes"] / max(fam_ms["pass_a"][1], 1)),
@@ -231,7 +249,7 @@ def main():
         log(f"[bench] time to 1e-6 Ha: {tta}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not mixed:
         from oracle import hamiltonian as oh
         from oracle import lobpcg as olob
 
@@ -257,11 +275,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "diamond-like 2x2x2 supercell, 64 atoms, L=13.48 bohr, 48^3 grid, 160 bands, "
-                               "s+p KB projectors, complex128, TPA preconditioner",
-                   "Ng": cfg.Ng, "bands": cfg.nb, "precision": "fp64"},
+        "config": {"workload": WORKLOADS.get(cfg.name, cfg.name) + (", complex64 blocks, FP32 products, FP64 subspace solve"
+                                                                   if mixed else ", complex128")
+                               + ", TPA preconditioner",
+                   "Ng": cfg.Ng, "bands": cfg.nb, "precision": args.precision},
         "roofline": roofline,
         "kernels": others,
         "time_to_1e-6_Ha": tta,

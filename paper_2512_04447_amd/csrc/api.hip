@@ -638,11 +638,14 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   const size_t es = precision == KS_FP64 ? 16 : 8;
   const int n0 = grid->n[0], n1 = grid->n[1], n2 = grid->n[2];
   const int plane = n1 * n2;
-  const int ept = (int)ceil_div(plane, kThreads);
-  const int choices[4] = {4, 16, 48, 64};
+  // planes above 4096 points use 1024-thread blocks: one or two such planes
+  // fill a CU's LDS, and the larger block keeps 16 or more waves resident
+  p->plane_threads = (plane > 4096 && plane <= 16384) ? 1024 : kThreads;
+  const int ept = (int)ceil_div(plane, p->plane_threads);
+  const int choices[5] = {4, 12, 16, 48, 64};
   p->maxe_plane = 0;
   for (int c : choices)
-    if (ept <= c) { p->maxe_plane = c; break; }
+    if (ept <= c && (c != 12 || p->plane_threads == 1024)) { p->maxe_plane = c; break; }
   if (p->maxe_plane == 0) { delete p; return fail(KS_E_UNSUPPORTED, "plane too large"); }
   p->zc = 1;
   for (int z = 1; z <= n2; ++z)

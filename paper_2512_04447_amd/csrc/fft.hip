@@ -124,6 +124,10 @@ template <typename T2> struct Dft<7, T2> : DftOdd<7, T2> {};
 // element stride es and batch stride bs.  Ns = product of earlier radices.
 // Twiddle for input q of butterfly j: exp(-2 pi i q (j mod Ns) / (Ns R)),
 // read from tw[t] = exp(-2 pi i t / n) at t = q (j mod Ns) n/(Ns R) < n.
+// Work item w -> (transform b, butterfly j): adjacent lanes take adjacent
+// transforms when those are the contiguous direction (bs < es), so a wave's
+// LDS accesses stride by bs rather than by es (a large power of two for the
+// y and x transforms, which would put every lane in one bank).
 template <int R, int MAXE, typename T2>
 __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, int Ns,
                                       const T2* __restrict__ tw) {
@@ -131,6 +135,7 @@ __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, 
   const int nbf = n / R;
   const int total = nbatch * nbf;
   const int tstep = n / (Ns * R);
+  const bool bfast = bs < es;
   T2 v[NBF][R];
   int dst[NBF];
 #pragma unroll
@@ -138,8 +143,8 @@ __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, 
     const int w = threadIdx.x + u * blockDim.x;
     dst[u] = -1;
     if (w < total) {
-      const int b = w / nbf;
-      const int j = w - b * nbf;
+      const int b = bfast ? w % nbatch : w / nbf;
+      const int j = bfast ? w / nbatch : w - b * nbf;
       const int k = j % Ns;
       const T2* base = s + b * bs;
 #pragma unroll
@@ -186,15 +191,15 @@ __device__ inline int wrap_m(int k, int n) { return (2 * k < n) ? k : k - n; }
 // ---------------------------------------------------------------- pass A
 // MODE 0: load psi.  MODE 1: load r = ax - theta x and write per-plane
 // partial sums of |r|^2 to partial[band*n0 + x].
-template <typename T, int MAXE, int MODE>
-__global__ void __launch_bounds__(kThreads)
+template <typename T, int MAXE, int MODE, int NT>
+__global__ void __launch_bounds__(NT)
 k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
          const double* __restrict__ theta, int64_t ld, c2<T>* __restrict__ dst, int64_t ldd,
          const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, double* __restrict__ partial) {
   using T2 = c2<T>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* s = reinterpret_cast<T2*>(smem_raw);
-  __shared__ double red[kThreads / kWave];
+  __shared__ double red[NT / kWave];
   const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
   const int plane = n1 * n2;
   const int band = blockIdx.x / n0;
@@ -299,8 +304,8 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
 // conj(FFT(conj(.))) / Ng.
 // MODE 0 (H): out = Tpsi + V psi.
 // MODE 1 (preconditioner): out = mask[band] * IFFT(.), mask from res > lock_tol.
-template <typename T, int MAXE, int MODE>
-__global__ void __launch_bounds__(kThreads)
+template <typename T, int MAXE, int MODE, int NT>
+__global__ void __launch_bounds__(NT)
 k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict__ dst, int64_t ldd,
          const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, const T* __restrict__ V,
          const c2<T>* __restrict__ psi, int64_t ldp, const double* __restrict__ res, double lock_tol) {
@@ -471,7 +476,7 @@ __global__ void k_row_sum(const double* __restrict__ partial, int cnt, int nb, d
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename T, int MAXE>
+template <typename T, int MAXE, int NT>
 static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2,
                           const double* theta, int64_t ld, c2<T>* dst, int64_t ldd, int nb,
                           double* partial, hipStream_t s) {
@@ -480,10 +485,10 @@ static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2
   dim3 grid(nb * p.fft.ax[0].n);
   TimerScope ts(KF_PASS_A, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_pass_a<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, src2,
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 0, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
                        theta, ld, dst, ldd, tw1, tw2, partial);
   else
-    hipLaunchKernelGGL((k_pass_a<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, src2,
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 1, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
                        theta, ld, dst, ldd, tw1, tw2, partial);
   KS_LAUNCH_CHECK("pass A");
   return 0;
@@ -492,16 +497,21 @@ static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2
 template <typename T>
 static int pass_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2, const double* theta,
                   int64_t ld, c2<T>* dst, int64_t ldd, int nb, double* partial, hipStream_t s) {
+  if (p.plane_threads == 1024) {
+    if (p.maxe_plane == 12) return launch_plane_a<T, 12, 1024>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    if (p.maxe_plane == 16) return launch_plane_a<T, 16, 1024>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    return fail(KS_E_UNSUPPORTED, "plane pass shape");
+  }
   switch (p.maxe_plane) {
-    case 4: return launch_plane_a<T, 4>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
-    case 16: return launch_plane_a<T, 16>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
-    case 48: return launch_plane_a<T, 48>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
-    case 64: return launch_plane_a<T, 64>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 4: return launch_plane_a<T, 4, kThreads>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 16: return launch_plane_a<T, 16, kThreads>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 48: return launch_plane_a<T, 48, kThreads>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 64: return launch_plane_a<T, 64, kThreads>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
     default: return fail(KS_E_UNSUPPORTED, "plane too large for the LDS FFT");
   }
 }
 
-template <typename T, int MAXE>
+template <typename T, int MAXE, int NT>
 static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst,
                           int64_t ldd, int nb, const T* V, const c2<T>* psi, int64_t ldp,
                           const c2<T>* dc, const double* res, double lock_tol, hipStream_t s) {
@@ -510,10 +520,10 @@ static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t 
   dim3 grid(nb * p.fft.ax[0].n);
   TimerScope ts(KF_PASS_C, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_pass_c<T, MAXE, 0>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 0, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
                        dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   else
-    hipLaunchKernelGGL((k_pass_c<T, MAXE, 1>), grid, dim3(kThreads), p.lds_plane, s, p.fft, src, lds_,
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 1, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
                        dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   KS_LAUNCH_CHECK("pass C");
   return 0;
@@ -523,11 +533,18 @@ template <typename T>
 static int pass_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst, int64_t ldd,
                   int nb, const T* V, const c2<T>* psi, int64_t ldp, const c2<T>* dc,
                   const double* res, double lock_tol, hipStream_t s) {
+  if (p.plane_threads == 1024) {
+    if (p.maxe_plane == 12)
+      return launch_plane_c<T, 12, 1024>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    if (p.maxe_plane == 16)
+      return launch_plane_c<T, 16, 1024>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    return fail(KS_E_UNSUPPORTED, "plane pass shape");
+  }
   switch (p.maxe_plane) {
-    case 4: return launch_plane_c<T, 4>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
-    case 16: return launch_plane_c<T, 16>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
-    case 48: return launch_plane_c<T, 48>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
-    case 64: return launch_plane_c<T, 64>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 4: return launch_plane_c<T, 4, kThreads>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 16: return launch_plane_c<T, 16, kThreads>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 48: return launch_plane_c<T, 48, kThreads>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 64: return launch_plane_c<T, 64, kThreads>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
     default: return fail(KS_E_UNSUPPORTED, "plane too large for the LDS FFT");
   }
 }

@@ -31,8 +31,11 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;  // output tile edge per workgroup
-constexpr int KC = 16;    // K chunk staged in LDS
+constexpr int KC = 16;    // K chunk staged in LDS (rotation)
 constexpr int PAD = KC + 1;
+// K chunk of the Gram: 16 (FP64) or 32 (FP32) points, so that one chunk of
+// the three operand panels stays near 52 KB of LDS either way.
+template <typename T> constexpr int gram_kc() { return sizeof(T) == 4 ? 32 : 16; }
 
 // Column c of a three-segment block list (segments of nb columns each).
 template <typename T2>
@@ -45,15 +48,28 @@ __device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
 // For upper tile (ti, tj) and K split `sp`: S_tile = A_I^H B1_J and, when
 // TWO, H_tile = A_I^H B2_J.  Partials (FP64) go to part[(sp*ntu + t)*4096 +
 // i*64 + j] (row-major within the tile).
+// Waves per tile in a 2 x WJ grid.  FP32: WJ = 4 (512 threads), a wave owns
+// a 32 x 16 sub-tile, which keeps the accumulators and the FP64 shadow sums
+// small enough for three waves per SIMD.  FP64: WJ = 2 (256 threads), a wave
+// owns 32 x 32 (measured faster for FP64 at both cell sizes).
+template <typename T> constexpr int gram_wj() { return sizeof(T) == 4 ? 4 : 2; }
+template <typename T> constexpr int gram_threads() { return 128 * gram_wj<T>(); }
+
 template <typename T, bool TWO>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(gram_threads<T>())
 k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int64_t K, int64_t kper,
        int ntile, int ntu, int full, double2* __restrict__ partS, double2* __restrict__ partH) {
   using T2 = c2<T>;
   using M = Mfma<T>;
-  __shared__ T2 As[TILE][PAD];
-  __shared__ T2 Bs[TILE][PAD];
-  __shared__ T2 B2s[TWO ? TILE : 1][PAD];
+  constexpr int GKC = gram_kc<T>();
+  constexpr int GPAD = GKC + 1;
+  constexpr int WJ = gram_wj<T>();
+  constexpr int WN = TILE / WJ / 16;          // 16-column MFMA tiles per wave
+  constexpr int LPC = gram_threads<T>() / TILE;  // loader threads per column
+  constexpr int EPT = GKC / LPC;            // K points per loader thread and operand
+  __shared__ T2 As[TILE][GPAD];
+  __shared__ T2 Bs[TILE][GPAD];
+  __shared__ T2 B2s[TWO ? TILE : 1][GPAD];
   // tile index -> (ti, tj): upper tiles ti <= tj, or every tile when full
   int t = blockIdx.x;
   int ti = 0;
@@ -68,17 +84,17 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   const int64_t k0 = (int64_t)sp * kper;
   const int64_t k1 = min(K, k0 + kper);
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wj = wave & 1;
-  typename M::acc sr[2][2], si[2][2], hr[2][2], hi[2][2];
+  const int wi = wave / WJ, wj = wave % WJ;
+  typename M::acc sr[2][WN], si[2][WN], hr[2][WN], hi[2][WN];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = hr[a][b][v] = hi[a][b][v] = T(0);
-  // loader: thread -> (column, 4 consecutive k)
-  const int lc = threadIdx.x >> 2;
-  const int lk = (threadIdx.x & 3) * 4;
+  // loader: thread -> (column, EPT consecutive k)
+  const int lc = threadIdx.x / LPC;
+  const int lk = (threadIdx.x % LPC) * EPT;
   const int ca = ti * TILE + lc;
   const int cb = tj * TILE + lc;
   const T2* pa = ca < m ? seg_col(A, ca) : nullptr;
@@ -88,12 +104,12 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   // FP32 products accumulate in FP32 over KFLUSH points, then in FP64.
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int KFLUSH = 256;
-  double dsr[F32 ? 2 : 1][2][4], dsi[F32 ? 2 : 1][2][4], dhr[F32 ? 2 : 1][2][4], dhi[F32 ? 2 : 1][2][4];
+  double dsr[F32 ? 2 : 1][WN][4], dsi[F32 ? 2 : 1][WN][4], dhr[F32 ? 2 : 1][WN][4], dhi[F32 ? 2 : 1][WN][4];
   if constexpr (F32) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < WN; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) dsr[a][b][v] = dsi[a][b][v] = dhr[a][b][v] = dhi[a][b][v] = 0.0;
   }
@@ -102,7 +118,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WN; ++b)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             dsr[a][b][v] += (double)sr[a][b][v];
@@ -116,31 +132,49 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
           }
     }
   };
-  for (int64_t kb = k0; kb < k1; kb += KC) {
-    if (F32 && kb > k0 && ((kb - k0) % KFLUSH) == 0) flush();
+  // FP32: register stage of the next chunk, whose global loads are in flight
+  // while the current chunk is multiplied out of LDS.  FP64 loads each chunk
+  // just before storing it (measured faster: the FP64 kernel is limited by
+  // its accumulator registers, not by load latency).
+  constexpr bool PREFETCH = F32;
+  T2 ra[EPT], rb[EPT], rb2[TWO ? EPT : 1];
+  auto fetch = [&](int64_t kb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < EPT; ++q) {
       const int64_t k = kb + lk + q;
       const bool ok = k < k1;
-      As[lc][lk + q] = (pa && ok) ? pa[k] : z;
-      Bs[lc][lk + q] = (pb && ok) ? pb[k] : z;
-      if (TWO) B2s[lc][lk + q] = (pb2 && ok) ? pb2[k] : z;
+      ra[q] = (pa && ok) ? pa[k] : z;
+      rb[q] = (pb && ok) ? pb[k] : z;
+      if (TWO) rb2[q] = (pb2 && ok) ? pb2[k] : z;
+    }
+  };
+  if (PREFETCH && k0 < k1) fetch(k0);
+  for (int64_t kb = k0; kb < k1; kb += GKC) {
+    if (!PREFETCH) fetch(kb);
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      As[lc][lk + q] = ra[q];
+      Bs[lc][lk + q] = rb[q];
+      if (TWO) B2s[lc][lk + q] = rb2[q];
     }
     __syncthreads();
+    if (PREFETCH && kb + GKC < k1) fetch(kb + GKC);
+    if (F32 && kb > k0 && ((kb - k0) % KFLUSH) == 0) flush();
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
+    for (int kk = 0; kk < GKC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T2 a[2], b[2], b2[2];
+      T2 a[2], b[WN], b2[WN];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        a[u] = As[wi * 32 + u * 16 + (lane & 15)][kr];
-        b[u] = Bs[wj * 32 + u * 16 + (lane & 15)][kr];
-        if (TWO) b2[u] = B2s[wj * 32 + u * 16 + (lane & 15)][kr];
+      for (int u = 0; u < 2; ++u) a[u] = As[wi * 32 + u * 16 + (lane & 15)][kr];
+#pragma unroll
+      for (int w = 0; w < WN; ++w) {
+        b[w] = Bs[wj * WN * 16 + w * 16 + (lane & 15)][kr];
+        if (TWO) b2[w] = B2s[wj * WN * 16 + w * 16 + (lane & 15)][kr];
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < WN; ++w) {
           // conj(a) * b: re = ar br + ai bi, im = ar bi - ai br
           sr[u][w] = M::run(a[u].x, b[w].x, sr[u][w]);
           sr[u][w] = M::run(a[u].y, b[w].y, sr[u][w]);
@@ -161,11 +195,11 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int w = 0; w < 2; ++w)
+    for (int w = 0; w < WN; ++w)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = wi * 32 + u * 16 + M::row(lane, v);
-        const int j = wj * 32 + w * 16 + (lane & 15);
+        const int j = wj * WN * 16 + w * 16 + (lane & 15);
         if constexpr (F32) {
           partS[base + i * TILE + j] = make_double2(dsr[u][w][v], dsi[u][w][v]);
           if (TWO) partH[base + i * TILE + j] = make_double2(dhr[u][w][v], dhi[u][w][v]);
@@ -237,7 +271,7 @@ GramShape gram_shape(int m, int64_t K, bool full) {
   // keep partials (two matrices) under 256 MB
   const int64_t cap = std::max<int64_t>(1, (int64_t)(256ll << 20) / ((int64_t)g.ntu * TILE * TILE * 16 * 2));
   ns = std::max<int64_t>(1, std::min(ns, cap));
-  g.kper = ceil_div(ceil_div(K, ns), KC) * KC;
+  g.kper = ceil_div(ceil_div(K, ns), 32) * 32;  // a multiple of either Gram chunk
   g.nsplit = (int)ceil_div(K, g.kper);
   return g;
 }
@@ -262,10 +296,10 @@ static int gram_impl(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, cons
   const int fl = full ? 1 : 0;
   TimerScope ts(KF_GRAM, s);
   if (B2)
-    hipLaunchKernelGGL((k_gram<T, true>), grid, dim3(256), 0, s, A, B1, *B2, m, K, g.kper, g.ntile, g.ntu, fl, partS,
+    hipLaunchKernelGGL((k_gram<T, true>), grid, dim3(gram_threads<T>()), 0, s, A, B1, *B2, m, K, g.kper, g.ntile, g.ntu, fl, partS,
                        partH);
   else
-    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(256), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, fl, partS,
+    hipLaunchKernelGGL((k_gram<T, false>), grid, dim3(gram_threads<T>()), 0, s, A, B1, B1, m, K, g.kper, g.ntile, g.ntu, fl, partS,
                        partH);
   KS_LAUNCH_CHECK("gram");
   hipLaunchKernelGGL(k_gram_reduce, dim3(g.ntu, 16), dim3(256), 0, s, partS, g.nsplit, g.ntile, g.ntu, m, fl, S, lds_);

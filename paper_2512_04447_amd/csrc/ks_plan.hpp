@@ -37,6 +37,7 @@ struct ks_plan {
   ks::Fft3 fft;
   void* tw[3];   // per-axis twiddles exp(-2 pi i t/n), plan precision
   int maxe_plane;  // elements per thread for the (y,z) plane passes
+  int plane_threads; // threads per block of the plane passes (256 or 1024)
   int maxe_pencil; // elements per thread for the x-pencil pass
   int zc;          // z extent of one x-pencil tile
   size_t lds_plane;
