@@ -37,7 +37,10 @@ void timer_begin(int f, hipStream_t s) {
   if (!t.on) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return;
+  }
   t.open = e;
 }
 
@@ -46,7 +49,10 @@ void timer_end(int f, hipStream_t s) {
   if (!t.on || !t.open) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return;
+  }
   t.ev.push_back(t.open);
   t.ev.push_back(e);
   t.open = nullptr;

@@ -257,21 +257,29 @@ __global__ void k_hermitise(double2* __restrict__ K, int ldk, int n) {
 // ---------------------------------------------------------------- tridiagonalisation
 // Step k: Householder vector of K[k+1:n, k].  With x = (alpha, x2),
 // beta = -sign(Re alpha) sqrt(|alpha|^2 + |x2|^2), tau = (beta - alpha)/beta,
-// v = (1, x2/(alpha - beta)), so that (I - tau v v^H)^H x = beta e_1.
-// v overwrites K[k+1:n, k]; d[k] = Re K[k][k], e[k] = beta.
+// v = (1, x2/(alpha - beta)), so that (I - tau v v^H)^H x = beta e_1;
+// d[k] = Re K[k][k], e[k] = beta.
+// Householder vector of step k fused with y = A22 v (A22 = K[k+1:, k+1:]).
+// One wave per entry of y.  Every wave computes the norm of x = K[k+1:, k]
+// in the same fixed order (identical results in every wave), forms
+// beta, tau and v = (1, x2/(alpha - beta)) on the fly, and since A22 is
+// Hermitian takes y_i = sum_j conj(A22[j][i]) v_j from the contiguous
+// column i.  Wave 0 of block 0 writes v to vbuf and tau[k], d[k], e[k];
+// column k of K still holds x during this kernel (the next kernel stores v
+// there for the back-transform).
 __global__ void __launch_bounds__(256)
-k_house(double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ tau, double* __restrict__ d,
-        double* __restrict__ e) {
-  __shared__ double red[4];
-  double2* x = K + (k + 1) + (int64_t)k * ldk;
+k_house_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ tau,
+             double* __restrict__ d, double* __restrict__ e, double2* __restrict__ vbuf, double2* __restrict__ y) {
   const int len = n - k - 1;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double2* x = K + (k + 1) + (int64_t)k * ldk;
   double s = 0.0;
-  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) s += x[i].x * x[i].x + x[i].y * x[i].y;
-  s = block_sum(s, red);
+  for (int j = 1 + lane; j < len; j += 64) s += x[j].x * x[j].x + x[j].y * x[j].y;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   const double2 alpha = x[0];
-  double2 t;
+  double2 t, scale;
   double beta;
-  double2 scale;
   if (s == 0.0 && alpha.y == 0.0) {
     t = make_double2(0.0, 0.0);
     beta = alpha.x;
@@ -280,65 +288,56 @@ k_house(double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ ta
     const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s);
     beta = alpha.x >= 0.0 ? -nrm : nrm;
     t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-    // 1/(alpha - beta)
     const double ar = alpha.x - beta, ai = alpha.y;
     const double den = ar * ar + ai * ai;
     scale = make_double2(ar / den, -ai / den);
   }
-  __syncthreads();
-  for (int i = 1 + threadIdx.x; i < len; i += blockDim.x) {
-    const double2 v = x[i];
-    x[i] = make_double2(v.x * scale.x - v.y * scale.y, v.x * scale.y + v.y * scale.x);
-  }
-  if (threadIdx.x == 0) {
-    x[0] = make_double2(1.0, 0.0);
-    tau[k] = t;
-    d[k] = K[k + (int64_t)k * ldk].x;
-    e[k] = beta;
-  }
-}
-
-// y = A22 v, A22 = K[k+1:, k+1:], v = K[k+1:, k].  16 rows per block,
-// 16 column groups per row, summed in a fixed order.
-__global__ void __launch_bounds__(256)
-k_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ y) {
-  __shared__ double2 part[16][17];
-  const int len = n - k - 1;
-  const double2* v = K + (k + 1) + (int64_t)k * ldk;
-  const double2* A = K + (k + 1) + (int64_t)(k + 1) * ldk;
-  const int ri = threadIdx.x & 15, jg = threadIdx.x >> 4;
-  const int i = blockIdx.x * 16 + ri;
-  double2 acc = make_double2(0.0, 0.0);
-  if (i < len) {
-    for (int j = jg; j < len; j += 16) {
-      const double2 a = A[i + (int64_t)j * ldk];
-      const double2 b = v[j];
-      acc.x += a.x * b.x - a.y * b.y;
-      acc.y += a.x * b.y + a.y * b.x;
+  if (row == 0) {
+    for (int j = lane; j < len; j += 64) {
+      const double2 xv = x[j];
+      vbuf[j] = j == 0 ? make_double2(1.0, 0.0)
+                       : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+    }
+    if (lane == 0) {
+      tau[k] = t;
+      d[k] = K[k + (int64_t)k * ldk].x;
+      e[k] = beta;
     }
   }
-  part[ri][jg] = acc;
-  __syncthreads();
-  if (jg == 0 && i < len) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int g = 0; g < 16; ++g) {
-      s.x += part[ri][g].x;
-      s.y += part[ri][g].y;
-    }
-    y[i] = s;
+  if (row >= len) return;
+  const double2* col = K + (k + 1) + (int64_t)(k + 1 + row) * ldk;
+  double ar = 0.0, ai = 0.0;
+  for (int j = lane; j < len; j += 64) {
+    const double2 xv = x[j];
+    const double2 v = j == 0 ? make_double2(1.0, 0.0)
+                             : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+    const double2 a = col[j];
+    // conj(a) v
+    ar += a.x * v.x + a.y * v.y;
+    ai += a.x * v.y - a.y * v.x;
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
+  }
+  if (lane == 0) y[row] = make_double2(ar, ai);
 }
 
 // A22 <- A22 - w v^H - v w^H with w = tau y - (1/2)|tau|^2 Re(v^H y) v.
 // Every block recomputes v^H y in the same order (identical result).
+// v comes from vbuf; blocks of the first column of tiles also store their
+// rows of v into K[k+1:, k] (kept there for the back-transform).
 __global__ void __launch_bounds__(256)
 k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict__ y,
-       const double2* __restrict__ tau) {
+       const double2* __restrict__ tau, const double2* __restrict__ v) {
   __shared__ double red[4];
   __shared__ double2 wi_s[32], vi_s[32], wj_s[32], vj_s[32];
   const int len = n - k - 1;
-  const double2* v = K + (k + 1) + (int64_t)k * ldk;
   double2* A = K + (k + 1) + (int64_t)(k + 1) * ldk;
+  if (blockIdx.y == 0 && threadIdx.x < 32) {
+    const int i = blockIdx.x * 32 + threadIdx.x;
+    if (i < len) K[(k + 1 + i) + (int64_t)k * ldk] = v[i];
+  }
   const double2 t = tau[k];
   double s = 0.0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) s += v[i].x * y[i].x + v[i].y * y[i].y;  // Re(conj(v) y)
@@ -632,6 +631,7 @@ struct HegvWs {
   void* potrf;
   double2* K;
   double2* y;
+  double2* v;
   double2* tau;
   double* d;
   double* e;
@@ -649,6 +649,7 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   w.potrf = p; p += al(potrf_work(n));
   w.K = reinterpret_cast<double2*>(p); p += al((size_t)n * n * sizeof(double2));
   w.y = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
+  w.v = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
   w.tau = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
   w.d = reinterpret_cast<double*>(p); p += al((size_t)n * 8);
   w.e = reinterpret_cast<double*>(p); p += al((size_t)n * 8);
@@ -662,7 +663,7 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
 }
 
 size_t hegv_work(int n, int nev) {
-  return al(potrf_work(n)) + al((size_t)n * n * 16) + 2 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
+  return al(potrf_work(n)) + al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
          al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)nev * 5 * n * 8) +
          al((size_t)NB * n * 16);
 }
@@ -686,10 +687,10 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   // Householder tridiagonalisation, one column per step
   for (int k = 0; k + 1 < n; ++k) {
     const int len = n - k - 1;
-    hipLaunchKernelGGL(k_house, dim3(1), dim3(256), 0, s, ws.K, n, n, k, ws.tau, ws.d, ws.e);
-    hipLaunchKernelGGL(k_hemv, dim3((unsigned)ceil_div(len, 16)), dim3(256), 0, s, ws.K, n, n, k, ws.y);
+    hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau, ws.d,
+                       ws.e, ws.v, ws.y);
     hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
-                       ws.K, n, n, k, ws.y, ws.tau);
+                       ws.K, n, n, k, ws.y, ws.tau, ws.v);
   }
   KS_LAUNCH_CHECK("tridiagonalisation");
   hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);

@@ -48,6 +48,45 @@ __device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
 // For upper tile (ti, tj) and K split `sp`: S_tile = A_I^H B1_J and, when
 // TWO, H_tile = A_I^H B2_J.  Partials (FP64) go to part[(sp*ntu + t)*4096 +
 // i*64 + j] (row-major within the tile).
+// Loads of one K chunk into registers (EPT points of one column per
+// operand).  Plain functions rather than lambdas: arrays captured by
+// reference in a lambda were kept in private memory.
+template <bool TWO, int EPT, typename T2>
+__device__ __forceinline__ void gram_fetch(T2 (&ra)[EPT], T2 (&rb)[EPT], T2 (&rb2)[TWO ? EPT : 1], const T2* pa,
+                                           const T2* pb, const T2* pb2, int64_t kb, int lk, int64_t k1) {
+  const T2 z = cmake<T2>(decltype(z.x)(0), decltype(z.x)(0));
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int64_t k = kb + lk + q;
+    const bool ok = k < k1;
+    ra[q] = (pa && ok) ? pa[k] : z;
+    rb[q] = (pb && ok) ? pb[k] : z;
+    if constexpr (TWO) rb2[q] = (pb2 && ok) ? pb2[k] : z;
+  }
+}
+
+// FP32 accumulators into the FP64 sums, then cleared.
+template <bool TWO, int WN, typename A>
+__device__ __forceinline__ void gram_flush(A (&sr)[2][WN], A (&si)[2][WN], A (&hr)[2][WN], A (&hi)[2][WN],
+                                           double (&dsr)[2][WN][4], double (&dsi)[2][WN][4],
+                                           double (&dhr)[2][WN][4], double (&dhi)[2][WN][4]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        dsr[a][b][v] += (double)sr[a][b][v];
+        dsi[a][b][v] += (double)si[a][b][v];
+        sr[a][b][v] = si[a][b][v] = 0.0f;
+        if constexpr (TWO) {
+          dhr[a][b][v] += (double)hr[a][b][v];
+          dhi[a][b][v] += (double)hi[a][b][v];
+          hr[a][b][v] = hi[a][b][v] = 0.0f;
+        }
+      }
+}
+
 // Waves per tile in a 2 x WJ grid.  FP32: WJ = 4 (512 threads), a wave owns
 // a 32 x 16 sub-tile, which keeps the accumulators and the FP64 shadow sums
 // small enough for three waves per SIMD.  FP64: WJ = 2 (256 threads), a wave
@@ -113,53 +152,41 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
 #pragma unroll
         for (int v = 0; v < 4; ++v) dsr[a][b][v] = dsi[a][b][v] = dhr[a][b][v] = dhi[a][b][v] = 0.0;
   }
-  auto flush = [&]() {
-    if constexpr (F32) {
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < WN; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            dsr[a][b][v] += (double)sr[a][b][v];
-            dsi[a][b][v] += (double)si[a][b][v];
-            sr[a][b][v] = si[a][b][v] = T(0);
-            if (TWO) {
-              dhr[a][b][v] += (double)hr[a][b][v];
-              dhi[a][b][v] += (double)hi[a][b][v];
-              hr[a][b][v] = hi[a][b][v] = T(0);
-            }
-          }
-    }
-  };
   // FP32: register stage of the next chunk, whose global loads are in flight
   // while the current chunk is multiplied out of LDS.  FP64 loads each chunk
   // just before storing it (measured faster: the FP64 kernel is limited by
   // its accumulator registers, not by load latency).
   constexpr bool PREFETCH = F32;
-  T2 ra[EPT], rb[EPT], rb2[TWO ? EPT : 1];
-  auto fetch = [&](int64_t kb) {
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int64_t k = kb + lk + q;
-      const bool ok = k < k1;
-      ra[q] = (pa && ok) ? pa[k] : z;
-      rb[q] = (pb && ok) ? pb[k] : z;
-      if (TWO) rb2[q] = (pb2 && ok) ? pb2[k] : z;
-    }
-  };
-  if (PREFETCH && k0 < k1) fetch(k0);
+  constexpr int NR = PREFETCH ? EPT : 1;
+  T2 ra[NR], rb[NR], rb2[TWO ? NR : 1];
+  if constexpr (PREFETCH) {
+    if (k0 < k1) gram_fetch<TWO>(ra, rb, rb2, pa, pb, pb2, k0, lk, k1);
+  }
   for (int64_t kb = k0; kb < k1; kb += GKC) {
-    if (!PREFETCH) fetch(kb);
+    if constexpr (PREFETCH) {
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      As[lc][lk + q] = ra[q];
-      Bs[lc][lk + q] = rb[q];
-      if (TWO) B2s[lc][lk + q] = rb2[q];
+      for (int q = 0; q < EPT; ++q) {
+        As[lc][lk + q] = ra[q];
+        Bs[lc][lk + q] = rb[q];
+        if (TWO) B2s[lc][lk + q] = rb2[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int64_t k = kb + lk + q;
+        const bool ok = k < k1;
+        As[lc][lk + q] = (pa && ok) ? pa[k] : z;
+        Bs[lc][lk + q] = (pb && ok) ? pb[k] : z;
+        if (TWO) B2s[lc][lk + q] = (pb2 && ok) ? pb2[k] : z;
+      }
     }
     __syncthreads();
-    if (PREFETCH && kb + GKC < k1) fetch(kb + GKC);
-    if (F32 && kb > k0 && ((kb - k0) % KFLUSH) == 0) flush();
+    if constexpr (PREFETCH) {
+      if (kb + GKC < k1) gram_fetch<TWO>(ra, rb, rb2, pa, pb, pb2, kb + GKC, lk, k1);
+    }
+    if constexpr (F32) {
+      if (kb > k0 && ((kb - k0) % KFLUSH) == 0) gram_flush<TWO>(sr, si, hr, hi, dsr, dsi, dhr, dhi);
+    }
 #pragma unroll
     for (int kk = 0; kk < GKC; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -190,7 +217,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
     }
     __syncthreads();
   }
-  flush();
+  if constexpr (F32) gram_flush<TWO>(sr, si, hr, hi, dsr, dsi, dhr, dhi);
   const int64_t base = ((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE);
 #pragma unroll
   for (int u = 0; u < 2; ++u)
