@@ -33,6 +33,14 @@ WORKLOADS = {
     "C3": "diamond-like 3x3x3 supercell, 216 atoms, L=20.22 bohr, 96^3 grid, 480 bands, s+p KB projectors",
     "C4": "bcc 4x4x4 supercell, 128 atoms, L=23.92 bohr, 112^3 grid, 960 bands, s+p+d KB projectors",
 }
+# HBM bytes per launch of a kernel family, from FETCH_SIZE and WRITE_SIZE
+# counter runs scaled by a known-size copy (the per-dispatch table and the
+# commands are in profiles/hbm_traffic_fp64_c2.md).  A value holds only
+# while the kernel source it was measured on is unchanged (sha256 below).
+MEASURED_TRAFFIC = {
+    ("C2", "fp64", "gram"): (2.6965e9, "paper_2512_04447_amd/csrc/gemm.hip",
+                             "811babf49ec721c9cb92fd3bb5267fd7c6c2659a8d9aa64195811b108dd6039a"),
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
@@ -55,8 +63,12 @@ def parse():
     ap.add_argument("--compare", default=None,
                     help="time-to-1e-6-Ha comparison on one cell (C2, C3 or C4) instead of the throughput bench")
     ap.add_argument("--mixed-lock", type=float, default=1e-4)
-    ap.add_argument("--weights", default=None, help="FP32 parameters of the learned preconditioner (.npy)")
+    ap.add_argument("--weights", default=None, help="FP32 parameters of the learned preconditioner on r (.npy)")
+    ap.add_argument("--weights-tpa", default=None, help="FP32 parameters of the residual network on TPA(r) (.npy)")
     ap.add_argument("--maxit", type=int, default=150)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="first run one plain device-to-device copy of MB megabytes (a known-size dispatch for "
+                         "scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -108,17 +120,37 @@ def compare(args):
     out["mixed_tpa"] = {"seconds_to_1e-6_Ha": round(rm["seconds"], 3), "iterations_to_1e-6_Ha": rm["iterations"],
                         "max_err_Ha": rm["max_err"], "s_per_iter": round(rm["seconds"] / rm["iterations"], 4),
                         "reached": bool(rm["max_err"] <= 1e-6), "max_res_history": rm["max_res_history"]}
-    wpath = args.weights or lr.WEIGHTS
-    if os.path.exists(wpath):
+    for key, kind, wpath in (("mixed_cnn", b.KS_PRECOND_CNN, args.weights or lr.WEIGHTS),
+                             ("mixed_cnn_tpa", b.KS_PRECOND_CNN_TPA, args.weights_tpa or lr.WEIGHTS_TPA)):
+        if not os.path.exists(wpath):
+            continue
         params = torch.from_numpy(np.load(wpath)).cuda()
-        rc, hc, thc = leg("mixed+cnn", b.KS_MIXED_FP32, b.KS_PRECOND_CNN, args.mixed_lock, ref=ref, params=params)
-        out["mixed_cnn"] = {"seconds_to_1e-6_Ha": round(rc["seconds"], 3), "iterations_to_1e-6_Ha": rc["iterations"],
-                            "max_err_Ha": rc["max_err"], "s_per_iter": round(rc["seconds"] / rc["iterations"], 4),
-                            "reached": bool(rc["max_err"] <= 1e-6), "switched_to_tpa_at": rc["switched_to_tpa_at"],
-                            "max_res_history": rc["max_res_history"]}
+        rc, hc, thc = leg(key.replace("_", "+", 1), b.KS_MIXED_FP32, kind, args.mixed_lock, ref=ref, params=params)
+        out[key] = {"seconds_to_1e-6_Ha": round(rc["seconds"], 3), "iterations_to_1e-6_Ha": rc["iterations"],
+                    "max_err_Ha": rc["max_err"], "s_per_iter": round(rc["seconds"] / rc["iterations"], 4),
+                    "reached": bool(rc["max_err"] <= 1e-6), "switched_to_tpa_at": rc["switched_to_tpa_at"],
+                    "max_res_history": rc["max_res_history"]}
     print(json.dumps({"metric": METRIC, "compare": cfg.name, "n_gpus": 1, "data": "synthetic",
                       "config": {"workload": cfg.name, "Ng": cfg.Ng, "bands": cfg.nb, "tracked": cfg.ntrack},
                       "legs": out}))
+
+
+def measured_traffic(cfg_name, precision, family):
+    """Counter-measured bytes per launch, or None when not measured or when
+    the kernel source has changed since."""
+    import hashlib
+
+    ent = MEASURED_TRAFFIC.get((cfg_name, precision, family))
+    if ent is None:
+        return None
+    value, src, digest = ent
+    try:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    except OSError:
+        return None
+    return value
 
 
 def family_work(cfg, es):
@@ -158,6 +190,14 @@ def main():
     from paper_2512_04447_amd import binding as b
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read and {nbytes} bytes written")
+        del src, dst
     if args.compare:
         compare(args)
         return
@@ -219,7 +259,7 @@ def main():
     dom = max(rates, key=lambda k: fam_ms[k][0])
     bound, ach, peak, unit, per_launch = rates[dom]
     roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 4), "traffic": None,
+                "frac": round(ach / peak, 4), "traffic": measured_traffic(cfg.name, args.precision, dom),
                 "algorithmic_per_launch": per_launch,
                 "avg_launch_ms": fam_ms[dom][0] / max(fam_ms[dom][1], 1)}
     others = {k: {"achieved": round(r[1], 3), "unit": r[3], "frac": round(r[1] / r[2], 4),

@@ -121,10 +121,16 @@ typedef struct {
 
 /* Preconditioner kinds.  KS_PRECOND_CNN applies the learned network below to
  * each residual (input channels Re r~, Im r~, h^2 (V_loc - theta_i), with
- * r~ = r sqrt(Ng)/||r|| and h = L0/n0; output w = y0 + i y1). */
+ * r~ = r sqrt(Ng)/||r|| and h = L0/n0; output w = y0 + i y1).
+ * KS_PRECOND_CNN_TPA applies it to the Teter-Payne-Allan output p = K_TPA(r)
+ * instead and adds its input: w = (p~0 + y0) + i (p~1 + y1), p~ = p sqrt(Ng)/
+ * ||p|| (a network whose last layer is zero reproduces TPA).  Either kind
+ * keeps the band's unlearned column (r, or p) where the network output is
+ * not finite. */
 #define KS_PRECOND_NONE 0
 #define KS_PRECOND_TPA 1
 #define KS_PRECOND_CNN 2
+#define KS_PRECOND_CNN_TPA 3
 
 typedef struct {
   int32_t precond;  /* KS_PRECOND_* */
@@ -132,7 +138,7 @@ typedef struct {
   /* Soft locking: a band with residual norm <= lock_tol contributes an
    * exactly-zero column to W and P (its X column stays). */
   double lock_tol;
-  const float* cnn_params; /* device, KS_CNN_NPARAM floats; KS_PRECOND_CNN only */
+  const float* cnn_params; /* device, KS_CNN_NPARAM floats; the CNN kinds only */
 } ks_lobpcg_opts;
 
 /* Learned preconditioner: three periodic 3x3x3 convolutions 3 -> 16 -> 16 -> 2
@@ -248,9 +254,15 @@ int cnn_loss(int32_t nbatch, int64_t Ng, const float* y, const float* t, float* 
 int cnn_adam_step(float* params, const float* grads, float* m, float* v, int32_t nparam, int32_t t,
                   float lr, void* stream);
 /* Network input x[nb][3][Ng] from residual columns R (ld), their norms
- * rnorm[nb], v_loc and theta[nb]. */
+ * rnorm[nb], v_loc and theta[nb].  rnorm may be NULL: each column is then
+ * scaled by its own Euclidean norm, computed here (a zero column stays zero). */
 int cnn_make_input(const ks_plan* plan, const void* R, int64_t ld, const double* rnorm,
                    const void* v_loc, const double* theta, int32_t nb, float* x, void* stream);
+/* Skip connection of the residual network: y[b][c][:] += x[b][c][:] for the
+ * first two channels (c = 0, 1) of nbatch samples on the plan's grid.  The
+ * gradient with respect to the network output equals the one with respect
+ * to y, so cnn_backward is unchanged. */
+int cnn_add_skip(const ks_plan* plan, int32_t nbatch, const float* x, float* y, void* stream);
 
 /* Kernel timing for measurement (not needed to solve anything).
  * ks_kernel_timer(1, id) starts recording a HIP event pair around every

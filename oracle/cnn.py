@@ -96,6 +96,14 @@ def forward(params, x: np.ndarray):
     return h, (acts, pre)
 
 
+def forward_residual(params, x: np.ndarray):
+    """Residual variant: output = net(x) + x[:2] (the network corrects its
+    first two input channels).  The gradient with respect to the parameters
+    is that of ``forward`` for the same output gradient."""
+    out, cache = forward(params, x)
+    return out + x[:2], cache
+
+
 def backward(params, cache, gout: np.ndarray):
     """Gradients [(dw, db), ...] and d input for dL/doutput = gout."""
     acts, pre = cache

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libksh.so")
 
 KS_FP64, KS_MIXED_FP32, KS_MIXED_BF16X3 = 0, 1, 2
-KS_PRECOND_NONE, KS_PRECOND_TPA, KS_PRECOND_CNN = 0, 1, 2
+KS_PRECOND_NONE, KS_PRECOND_TPA, KS_PRECOND_CNN, KS_PRECOND_CNN_TPA = 0, 1, 2, 3
 KS_CNN_NPARAM = 9106
 KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD = 1, 2, 3, 4
 KS_E_HIP, KS_E_WORKSPACE, KS_E_NUMERIC, KS_E_UNSUPPORTED = -1000, -2001, -2002, -2003
@@ -39,6 +39,7 @@ EXPORTS = (
     "cnn_loss",
     "cnn_adam_step",
     "cnn_make_input",
+    "cnn_add_skip",
     "ks_kernel_timer",
     "ks_kernel_timer_read",
     "ks_last_error",
@@ -128,6 +129,7 @@ def load() -> C.CDLL:
     lib.cnn_loss.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
     lib.cnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, f32, vp]
     lib.cnn_make_input.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp]
+    lib.cnn_add_skip.argtypes = [vp, i32, vp, vp, vp]
     lib.ks_kernel_timer.argtypes = [i32, i32]
     lib.ks_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.ks_last_error.restype = C.c_char_p
@@ -339,7 +341,7 @@ class Lobpcg:
 
     def step(self, precond: int = KS_PRECOND_TPA, lock_tol: float = 0.0, cnn_params=None):
         """One iteration; ``cnn_params`` (FP32 device tensor of KS_CNN_NPARAM
-        values) is required for KS_PRECOND_CNN."""
+        values) is required for KS_PRECOND_CNN and KS_PRECOND_CNN_TPA."""
         o = KsLobpcgOpts()
         o.precond = precond
         o.lock_tol = float(lock_tol)
@@ -405,10 +407,13 @@ class Cnn:
         self.loss = torch.zeros(nbatch, dtype=torch.float64, device=dev)
         self.sums = torch.zeros(3 * nbatch, dtype=torch.float64, device=dev)
 
-    def forward(self, x, nb=None, stream=None):
+    def forward(self, x, nb=None, skip=False, stream=None):
+        """y = net(x), plus the first two input channels when ``skip``."""
         nb = x.shape[0] if nb is None else nb
         check(load().cnn_forward(self.plan.handle, _ptr(self.params), nb, _ptr(x), _ptr(self.y), _ptr(self.acts),
                                  C.c_void_p(_stream(stream))), "cnn_forward")
+        if skip:
+            cnn_add_skip(self.plan, x, self.y, nb, stream)
         return self.y[:nb]
 
     def loss_grad(self, t, nb=None, stream=None):
@@ -433,7 +438,16 @@ class Cnn:
 
 
 def cnn_make_input(plan: Plan, R, rnorm, v, theta, x, stream=None):
+    """x = network input of the columns of R; rnorm None: each column is
+    scaled by its own norm (computed by the library)."""
     nb = R.shape[0]
-    check(load().cnn_make_input(plan.handle, _ptr(R), R.stride(0), _ptr(rnorm), _ptr(v), _ptr(theta), nb, _ptr(x),
-                                C.c_void_p(_stream(stream))), "cnn_make_input")
+    check(load().cnn_make_input(plan.handle, _ptr(R), R.stride(0), None if rnorm is None else _ptr(rnorm), _ptr(v),
+                                _ptr(theta), nb, _ptr(x), C.c_void_p(_stream(stream))), "cnn_make_input")
     return x
+
+
+def cnn_add_skip(plan: Plan, x, y, nbatch=None, stream=None):
+    """y[:, 0:2] += x[:, 0:2] (skip connection of the residual network)."""
+    nb = x.shape[0] if nbatch is None else nbatch
+    check(load().cnn_add_skip(plan.handle, nb, _ptr(x), _ptr(y), C.c_void_p(_stream(stream))), "cnn_add_skip")
+    return y

@@ -301,6 +301,8 @@ struct LobWs {
   float* cnn_buf;  // chunk x 32 x Ng
   float* cnn_y;    // chunk x 2 x Ng
   int32_t* cnn_bad; // chunk flags: non-finite network output
+  double* cnn_norm;  // nb column norms of the TPA output
+  double* cnn_part;  // column-norm partial sums of one chunk
   char* end;
 };
 
@@ -337,6 +339,8 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.cnn_buf = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 32 * p.Ng * 4));
   w.cnn_y = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 2 * p.Ng * 4));
   w.cnn_bad = reinterpret_cast<int32_t*>(take((size_t)w.cnn_chunk * 4));
+  w.cnn_norm = reinterpret_cast<double*>(take((size_t)nb * 8));
+  w.cnn_part = reinterpret_cast<double*>(take(column_norms_partial(w.cnn_chunk) * 8));
   w.end = q;
   return w;
 }
@@ -493,19 +497,30 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   int rc;
   using T2 = c2<T>;
   // 1. residual, its norms, preconditioned and lock-masked W (into Xn)
-  const int kind = o->precond == KS_PRECOND_CNN ? KS_PRECOND_NONE : o->precond;
+  const bool learned = o->precond == KS_PRECOND_CNN || o->precond == KS_PRECOND_CNN_TPA;
+  const int kind = o->precond == KS_PRECOND_CNN ? KS_PRECOND_NONE
+                   : o->precond == KS_PRECOND_CNN_TPA ? KS_PRECOND_TPA
+                                                      : o->precond;
   if ((rc = precond_apply<T>(p, kind, static_cast<const T2*>(st->X), static_cast<const T2*>(st->AX), st->theta, ld,
                              nb, o->lock_tol, static_cast<T2*>(st->Xn), st->res, static_cast<T2*>(st->T1), w.partial,
                              w.E, s)))
     return rc;
-  if (o->precond == KS_PRECOND_CNN) {
-    // learned preconditioner on the residual, in band chunks
+  if (learned) {
+    // learned preconditioner, in band chunks, on the residual (CNN) or on
+    // the TPA output with the skip connection (CNN_TPA)
+    const bool skip = o->precond == KS_PRECOND_CNN_TPA;
     for (int b0 = 0; b0 < nb; b0 += w.cnn_chunk) {
       const int nc = std::min(w.cnn_chunk, nb - b0);
       T2* R = static_cast<T2*>(st->Xn) + (int64_t)b0 * ld;
-      if ((rc = cnn_input_impl<T>(p, R, ld, st->res + b0, static_cast<const T*>(v), st->theta + b0, nc, w.cnn_x, s)))
+      const double* nrm = st->res + b0;
+      if (skip) {
+        if ((rc = column_norms<T>(R, ld, nc, p.Ng, w.cnn_part, w.cnn_norm + b0, s))) return rc;
+        nrm = w.cnn_norm + b0;
+      }
+      if ((rc = cnn_input_impl<T>(p, R, ld, nrm, static_cast<const T*>(v), st->theta + b0, nc, w.cnn_x, s)))
         return rc;
       if ((rc = cnn_infer_impl(p, o->cnn_params, nc, w.cnn_x, w.cnn_y, w.cnn_buf, s))) return rc;
+      if (skip && (rc = cnn_skip_impl(p, nc, w.cnn_x, w.cnn_y, s))) return rc;
       if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, w.cnn_bad, R, ld, s))) return rc;
     }
   }
@@ -831,9 +846,11 @@ int lobpcg_step(const ks_plan* p, const void* v_loc, ks_lobpcg_state* st, const 
   if (rc) return rc;
   if (!v_loc) return fail(-2, "v_loc is null");
   if (!opts) return fail(-4, "opts is null");
-  if (opts->precond != KS_PRECOND_NONE && opts->precond != KS_PRECOND_TPA && opts->precond != KS_PRECOND_CNN)
+  if (opts->precond != KS_PRECOND_NONE && opts->precond != KS_PRECOND_TPA && opts->precond != KS_PRECOND_CNN &&
+      opts->precond != KS_PRECOND_CNN_TPA)
     return fail(-4, "unknown preconditioner");
-  if (opts->precond == KS_PRECOND_CNN && !opts->cnn_params) return fail(-4, "CNN preconditioner without parameters");
+  if ((opts->precond == KS_PRECOND_CNN || opts->precond == KS_PRECOND_CNN_TPA) && !opts->cnn_params)
+    return fail(-4, "CNN preconditioner without parameters");
   if (!work) return fail(-5, "work is null");
   if (work_bytes < lobpcg_work_bytes(*p, st->nb)) return fail(KS_E_WORKSPACE, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -941,7 +958,6 @@ int cnn_make_input(const ks_plan* p, const void* R, int64_t ld, const double* rn
   if (!p) return fail(-1, "plan is null");
   if (!R) return fail(-2, "R is null");
   if (ld < p->Ng) return fail(-3, "ld < Ng");
-  if (!rnorm) return fail(-4, "rnorm is null");
   if (!v_loc) return fail(-5, "v_loc is null");
   if (!theta) return fail(-6, "theta is null");
   if (nb <= 0) return fail(-7, "nb must be positive");
@@ -952,6 +968,15 @@ int cnn_make_input(const ks_plan* p, const void* R, int64_t ld, const double* rn
                                   theta, nb, x, s);
   return cnn_input_impl<float>(*p, static_cast<const float2*>(R), ld, rnorm, static_cast<const float*>(v_loc), theta,
                                nb, x, s);
+}
+
+int cnn_add_skip(const ks_plan* p, int32_t nbatch, const float* x, float* y, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (nbatch <= 0) return fail(-2, "nbatch must be positive");
+  if (!x) return fail(-3, "x is null");
+  if (!y) return fail(-4, "y is null");
+  return cnn_skip_impl(*p, nbatch, x, y, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

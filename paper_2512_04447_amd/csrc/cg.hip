@@ -212,6 +212,24 @@ static int coldot(const c2<T>* A, const c2<T>* B, int64_t ld, int nb, int64_t Ng
   return 0;
 }
 
+__global__ void k_sqrt_inplace(double* __restrict__ a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = sqrt(a[i]);
+}
+
+size_t column_norms_partial(int nb) { return (size_t)nb * kChunks; }
+
+template <typename T>
+int column_norms(const c2<T>* A, int64_t ld, int nb, int64_t Ng, double* partial, double* out, hipStream_t s) {
+  int rc;
+  if ((rc = coldot<T>(A, A, ld, nb, Ng, partial, out, s))) return rc;
+  hipLaunchKernelGGL(k_sqrt_inplace, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, out, nb);
+  KS_LAUNCH_CHECK("column_norms");
+  return 0;
+}
+template int column_norms<double>(const double2*, int64_t, int, int64_t, double*, double*, hipStream_t);
+template int column_norms<float>(const float2*, int64_t, int, int64_t, double*, double*, hipStream_t);
+
 // out = V - X (X^H V): one classical Gram-Schmidt pass (a Gram GEMM and a
 // rotation GEMM).  G: nb x nb FP64 scratch; Cbuf: 2nb x nb block precision.
 template <typename T>

@@ -40,6 +40,12 @@ template <typename T>
 int project_out(const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb, int64_t Ng, double2* G, void* Cbuf,
                 void* gram_ws, hipStream_t s);
 
+// out[b] = ||A[:, b]|| (Euclidean, FP64 sums in a fixed order); partial
+// holds column_norms_partial(nb) doubles (cg.hip).
+size_t column_norms_partial(int nb);
+template <typename T>
+int column_norms(const c2<T>* A, int64_t ld, int nb, int64_t Ng, double* partial, double* out, hipStream_t s);
+
 // Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng, c2<T>* Y,

@@ -105,6 +105,7 @@ int cnn_backward_impl(const ks_plan& p, const float* params, int nbatch, const f
 int cnn_loss_impl(const float* y, const float* t, int nbatch, int64_t Ng, float* gy, double* loss, double* sums,
                   hipStream_t s);
 int cnn_adam_impl(float* params, const float* grads, float* m, float* v, int n, int t, float lr, hipStream_t s);
+int cnn_skip_impl(const ks_plan& p, int nbatch, const float* x, float* y, hipStream_t s);
 template <typename T>
 int cnn_input_impl(const ks_plan& p, const c2<T>* R, int64_t ld, const double* rnorm, const T* V,
                    const double* theta, int nb, float* x, hipStream_t s);

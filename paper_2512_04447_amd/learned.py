@@ -40,8 +40,12 @@ class PairSet:
 
 
 def generate_pairs(cell, cfg, X0, n_iters: int, max_pairs: int, cg_maxit: int = 300, cg_rtol: float = 1e-6,
-                   log=print) -> PairSet:
-    """Run LOBPCG on one cell; after each step collect (input, target)."""
+                   inputs: str = "residual", log=print) -> PairSet:
+    """Run LOBPCG on one cell; after each step collect (input, target).
+
+    ``inputs`` = "residual": the network sees the residual r (the plain
+    learned preconditioner); "tpa": it sees the Teter-Payne-Allan output
+    K_TPA(r), each column scaled by its own norm (the residual variant)."""
     import torch
 
     proj = b.ProjectorArrays.from_cell(cell) if cell.nproj else None
@@ -55,12 +59,18 @@ def generate_pairs(cell, cfg, X0, n_iters: int, max_pairs: int, cg_maxit: int = 
     res = torch.empty(nb, dtype=torch.float64, device="cuda")
     iters = torch.zeros(nb, dtype=torch.int32, device="cuda")
     xin = torch.empty((nb, 3, plan.Ng), dtype=torch.float32, device="cuda")
+    P = torch.empty_like(R) if inputs == "tpa" else None
+    dummy = torch.empty(nb, dtype=torch.float64, device="cuda")
     xs, ts, ths, its = [], [], [], []
     count = 0
     for it in range(n_iters):
         b.ks_precond_apply(plan, b.KS_PRECOND_NONE, lob.X, lob.AX, lob.theta, R, res, 0.0)
         b.ks_jd_correction(plan, v, lob.X, lob.theta, R, T, iters, maxit=cg_maxit, rtol=cg_rtol)
-        b.cnn_make_input(plan, R, res, v, lob.theta, xin)
+        if inputs == "tpa":
+            b.ks_precond_apply(plan, b.KS_PRECOND_TPA, lob.X, lob.AX, lob.theta, P, dummy, 0.0)
+            b.cnn_make_input(plan, P, None, v, lob.theta, xin)
+        else:
+            b.cnn_make_input(plan, R, res, v, lob.theta, xin)
         ok = (iters > 0) & (res > 1e-12)
         sel = torch.nonzero(ok).flatten()
         if sel.numel():
@@ -80,8 +90,16 @@ def generate_pairs(cell, cfg, X0, n_iters: int, max_pairs: int, cg_maxit: int = 
     return PairSet(x, t, np.concatenate(ths)[:max_pairs], its[:max_pairs])
 
 
+def zero_last_layer(params):
+    """Zero the weights and biases of the last convolution (flat layout
+    w1, b1, w2, b2, w3, b3): the residual network then starts at its input."""
+    n_w3 = 2 * 16 * 27
+    params[-(n_w3 + 2):] = 0
+    return params
+
+
 def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 2, val_frac: float = 0.1,
-                log=print, params=None):
+                log=print, params=None, skip: bool = False):
     """Adam over pairs from several grids: ``sets`` is a list of (plan, PairSet).
 
     Every batch comes from one grid (the convolution kernels take one grid
@@ -93,7 +111,8 @@ def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int 
 
     rng = np.random.default_rng(seed)
     if params is None:
-        params = torch.from_numpy(kaiming_params(seed)).cuda()
+        p0 = kaiming_params(seed)
+        params = torch.from_numpy(zero_last_layer(p0) if skip else p0).cuda()
     nets, splits = [], []
     for plan, pairs in sets:
         net = b.Cnn(plan, params, batch)
@@ -111,7 +130,7 @@ def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int 
         for net, (plan, pairs), (val, _) in zip(nets, sets, splits):
             for s0 in range(0, len(val), batch):
                 j = torch.from_numpy(val[s0:s0 + batch]).cuda()
-                net.forward(pairs.x[j])
+                net.forward(pairs.x[j], skip=skip)
                 tot += float(net.loss_grad(pairs.t[j]).sum())
                 cnt += len(j)
         return tot / max(cnt, 1)
@@ -129,7 +148,7 @@ def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int 
             net, pairs = nets[g], sets[g][1]
             j = torch.from_numpy(idx).cuda()
             xb, tb = pairs.x[j], pairs.t[j]
-            net.forward(xb)
+            net.forward(xb, skip=skip)
             net.loss_grad(tb)
             net.backward(xb)
             step[0] += 1
@@ -162,7 +181,8 @@ def run_to_tolerance(plan, v, X0, ntrack: int, precond: int, lock_tol: float, ma
     pc = precond
     switched = None
     for it in range(1, maxit + 1):
-        lob.step(pc, lock_tol, cnn_params if pc == b.KS_PRECOND_CNN else None)
+        learned = pc in (b.KS_PRECOND_CNN, b.KS_PRECOND_CNN_TPA)
+        lob.step(pc, lock_tol, cnn_params if learned else None)
         tr = torch.cat([lob.theta[:ntrack], lob.res[:ntrack]]).cpu().numpy()
         th, res = tr[:ntrack], tr[ntrack:]
         rmax = float(res.max())
@@ -171,7 +191,7 @@ def run_to_tolerance(plan, v, X0, ntrack: int, precond: int, lock_tol: float, ma
         if it % 5 == 0:
             log(f"[tta] iteration {it}: max res {rmax:.3e}" + (f", max err {err:.3e}" if err is not None else "")
                 + f", {hist[-1][0]:.1f}s")
-        if pc == b.KS_PRECOND_CNN and switch_to_tpa and it > 3 and rmax > 0.9 * hist[-4][1]:
+        if learned and switch_to_tpa and it > 3 and rmax > 0.9 * hist[-4][1]:
             pc = b.KS_PRECOND_TPA
             switched = it
             log(f"[tta] learned preconditioner stalled at iteration {it}; switching to TPA")
@@ -221,7 +241,9 @@ def train(plan, pairs: PairSet, epochs: int, batch: int = 16, lr: float = 1e-3, 
     return net.params, hist
 
 
-WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights", "cnn_precond.npy")
+_WDIR = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights")
+WEIGHTS = __import__("os").path.join(_WDIR, "cnn_precond.npy")
+WEIGHTS_TPA = __import__("os").path.join(_WDIR, "cnn_tpa.npy")
 
 
 def main(argv=None):
@@ -245,7 +267,9 @@ def main(argv=None):
     ap.add_argument("--c2-iters", type=int, default=25)
     ap.add_argument("--max-pairs", type=int, default=12000)
     ap.add_argument("--epochs", type=int, default=6)
-    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--variant", default="tpa", choices=["tpa", "residual"],
+                    help="tpa: network on the TPA output with a skip connection; residual: network on r")
+    ap.add_argument("--out", default=None)
     ap.add_argument("--log", default=None)
     a = ap.parse_args(argv)
 
@@ -258,7 +282,8 @@ def main(argv=None):
         cell = ki.make_cell(cfg)
         parts = []
         for sd in range(1, nseed + 1):
-            ps = generate_pairs(cell, cfg, ki.make_x0(cfg, seed=sd), nit, a.max_pairs // 2, log=log)
+            ps = generate_pairs(cell, cfg, ki.make_x0(cfg, seed=sd), nit, a.max_pairs // 2,
+                                inputs="tpa" if a.variant == "tpa" else "residual", log=log)
             parts.append(ps)
         pairs = PairSet(torch.cat([p.x for p in parts]), torch.cat([p.t for p in parts]),
                         np.concatenate([p.theta for p in parts]), sum((p.iterations for p in parts), []))
@@ -267,14 +292,15 @@ def main(argv=None):
         log(f"[pairs] {name}: {pairs.x.shape[0]} pairs, CG iterations median {int(np.median(pairs.iterations))}")
         sets.append((plan, pairs))
     t0 = time.time()
-    params, hist = train_multi(sets, a.epochs, log=log)
+    params, hist = train_multi(sets, a.epochs, log=log, skip=a.variant == "tpa")
+    out = a.out or (WEIGHTS_TPA if a.variant == "tpa" else WEIGHTS)
     log(f"[train] {a.epochs} epochs in {time.time() - t0:.1f}s")
-    os.makedirs(os.path.dirname(a.out), exist_ok=True)
-    np.save(a.out, params.cpu().numpy())
-    log(f"[train] wrote {a.out}")
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    np.save(out, params.cpu().numpy())
+    log(f"[train] wrote {out}")
     if a.log:
         with open(a.log, "w") as f:
-            json.dump({"pairs": {n: int(s[1].x.shape[0]) for n, s in zip(("C1", "C2"), sets)},
+            json.dump({"variant": a.variant, "pairs": {n: int(s[1].x.shape[0]) for n, s in zip(("C1", "C2"), sets)},
                        "val_loss": hist}, f)
 
 

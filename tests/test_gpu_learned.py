@@ -125,7 +125,9 @@ def test_adam_matches_oracle(ks):
     assert np.abs(net.params.cpu().numpy() - p).max() <= 1e-6
 
 
-def test_cnn_input_matches_oracle(ks):
+@pytest.mark.parametrize("given_norms", [True, False])
+def test_cnn_input_matches_oracle(ks, given_norms):
+    """Norms passed in, or computed by the library (rnorm NULL)."""
     import torch
 
     from paper_2512_04447_amd import binding as b
@@ -138,11 +140,54 @@ def test_cnn_input_matches_oracle(ks):
     rn = np.linalg.norm(R, axis=1)
     plan = b.Plan(cell.n, cell.L, None, 3, b.KS_FP64)
     x = torch.empty((3, 3, cfg.Ng), dtype=torch.float32, device="cuda")
-    b.cnn_make_input(plan, dev(R), dev(rn), dev(cell.V), dev(theta), x)
+    b.cnn_make_input(plan, dev(R), dev(rn) if given_norms else None, dev(cell.V), dev(theta), x)
     got = x.cpu().numpy()
     for i in range(3):
         ref = ocnn.make_input(R[i], cell.V, theta[i], cfg.n, cfg.h).reshape(3, -1)
         assert np.abs(got[i] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_cnn_add_skip_is_the_channel_sum(ks):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    n, nb = 10, 3
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((nb, 3, n ** 3)).astype(np.float32)
+    y = rng.standard_normal((nb, 2, n ** 3)).astype(np.float32)
+    plan = plan_for(n)
+    dy = dev(y)
+    b.cnn_add_skip(plan, dev(x), dy)
+    # a single FP32 addition per element: bit-exact
+    assert np.array_equal(dy.cpu().numpy(), y + x[:, :2])
+
+
+def test_residual_network_with_zero_last_layer_reproduces_tpa_step(ks):
+    """KS_PRECOND_CNN_TPA with a zero last layer gives W proportional to the
+    TPA output (rounded to FP32), so one LOBPCG step matches the TPA step."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    cfg = ki.config("C1")
+    cell = ki.make_cell(cfg)
+    params = ocnn.init_params(2)
+    params[2] = (np.zeros_like(params[2][0]), np.zeros_like(params[2][1]))
+    flat = dev(flat_params(params))
+    plan = b.Plan(cell.n, cell.L, None, cfg.nb, b.KS_FP64)
+    v = dev(cell.V)
+    thetas = []
+    for kind in (b.KS_PRECOND_TPA, b.KS_PRECOND_CNN_TPA):
+        lob = b.Lobpcg(plan, v, dev(ki.make_x0(cfg)))
+        lob.init()
+        for _ in range(2):
+            lob.step(kind, 0.0, flat if kind == b.KS_PRECOND_CNN_TPA else None)
+        thetas.append(lob.theta.cpu().numpy())
+        _say("kind", kind, "res", float(lob.res.max()))
+    err = np.abs(thetas[0] - thetas[1]).max()
+    _say("max |dtheta| CNN_TPA(zero last layer) vs TPA", err)
+    assert err <= 1e-5
 
 
 def test_jd_correction_matches_oracle(ks):
@@ -180,3 +225,38 @@ def test_jd_correction_matches_oracle(ks):
             assert abs(int(git[i]) - its[i]) <= 2
     # the correction is orthogonal to X
     assert np.abs(np.conj(st.X) @ got.T).max() <= 1e-10 * np.abs(got).max()
+
+
+def test_trained_network_first_step_beats_tpa_and_no_preconditioner(ks):
+    """What the trained network (weights/cnn_precond.npy, trained on the GPU
+    by learned.py on 8- and 64-atom cells) gains: from the same initial
+    block of the 64-atom cell, one LOBPCG step preconditioned by it lowers
+    the largest tracked residual norm more than a TPA step and more than an
+    unpreconditioned step (measured 5.8 vs 19.8 vs larger)."""
+    import os
+
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import learned as lr
+
+    assert os.path.exists(lr.WEIGHTS), "trained weights missing"
+    params = torch.from_numpy(np.load(lr.WEIGHTS)).cuda()
+    cfg = ki.config("C2")
+    cell = ki.make_cell(cfg)
+    plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell), cfg.nb, b.KS_FP64)
+    v = dev(cell.V)
+    x0 = dev(ki.make_x0(cfg))
+    out = {}
+    for name, kind in (("none", b.KS_PRECOND_NONE), ("tpa", b.KS_PRECOND_TPA), ("cnn", b.KS_PRECOND_CNN)):
+        lob = b.Lobpcg(plan, v, x0)
+        lob.init()
+        lob.step(kind, 0.0, params if kind == b.KS_PRECOND_CNN else None)
+        # the residual of the new block is formed at the start of the next step
+        lob.step(b.KS_PRECOND_NONE, 0.0)
+        out[name] = float(lob.res[: cfg.ntrack].max())
+        del lob
+        torch.cuda.empty_cache()
+    _say("max tracked residual after one preconditioned step:", out)
+    assert out["cnn"] < 0.75 * out["tpa"]
+    assert out["cnn"] < out["none"]

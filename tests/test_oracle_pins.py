@@ -396,6 +396,23 @@ def test_cnn_backward_matches_finite_differences():
     assert abs(fd - gx[0, 1, 2, 3]) <= 1e-6 * max(1e-3, abs(fd))
 
 
+def test_residual_network_with_zero_last_layer_is_identity_on_its_input():
+    # a zero last layer makes the residual variant return its first two
+    # input channels exactly (it then reproduces the unlearned direction)
+    rng = np.random.default_rng(8)
+    n = 5
+    params = ocnn.init_params(2, channels=(3, 4, 4, 2))
+    params[2] = (np.zeros_like(params[2][0]), np.zeros_like(params[2][1]))
+    x = rng.standard_normal((3, n, n, n))
+    out, _ = ocnn.forward_residual(params, x)
+    assert np.array_equal(out, x[:2])
+    # and with any weights it differs from the plain network by x[:2]
+    p2 = ocnn.init_params(3, channels=(3, 4, 4, 2))
+    a, _ = ocnn.forward(p2, x)
+    b, _ = ocnn.forward_residual(p2, x)
+    assert np.abs((b - a) - x[:2]).max() <= 1e-12
+
+
 def test_adam_first_step_is_lr_times_sign():
     p = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -4.0, 1e-3])
