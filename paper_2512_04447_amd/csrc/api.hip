@@ -673,8 +673,9 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
     if (n2 % z == 0 && (int64_t)n0 * z <= 16 * kThreads) p->zc = z;
   p->maxe_pencil = 16;
   if ((int64_t)n0 > 16 * kThreads) { delete p; return fail(KS_E_UNSUPPORTED, "x extent too large"); }
-  p->lds_plane = (size_t)plane * es;
-  p->lds_pencil = (size_t)n0 * p->zc * es;
+  // data (planes padded: one pad element per 16) plus the staged twiddle tables
+  p->lds_plane = (size_t)(plane + (plane >> 4) + 1 + n1 + n2) * es;
+  p->lds_pencil = (size_t)(n0 * p->zc + n0) * es;
   int dev = 0, maxlds = 0;
   KS_HIP(hipGetDevice(&dev));
   KS_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

@@ -274,8 +274,16 @@ k_house_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __re
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const double2* x = K + (k + 1) + (int64_t)k * ldk;
+  const double2 zero = make_double2(0.0, 0.0);
+  // loops take 4 loads per lane at a time so that they are in flight together
   double s = 0.0;
-  for (int j = 1 + lane; j < len; j += 64) s += x[j].x * x[j].x + x[j].y * x[j].y;
+  for (int j0 = 1 + lane; j0 < len; j0 += 256) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = j0 + 64 * u < len ? x[j0 + 64 * u] : zero;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += a[u].x * a[u].x + a[u].y * a[u].y;
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   const double2 alpha = x[0];
   double2 t, scale;
@@ -307,14 +315,25 @@ k_house_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __re
   if (row >= len) return;
   const double2* col = K + (k + 1) + (int64_t)(k + 1 + row) * ldk;
   double ar = 0.0, ai = 0.0;
-  for (int j = lane; j < len; j += 64) {
-    const double2 xv = x[j];
-    const double2 v = j == 0 ? make_double2(1.0, 0.0)
-                             : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
-    const double2 a = col[j];
-    // conj(a) v
-    ar += a.x * v.x + a.y * v.y;
-    ai += a.x * v.y - a.y * v.x;
+  for (int j0 = lane; j0 < len; j0 += 256) {
+    double2 xa[4], ca[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 64 * u;
+      xa[u] = j < len ? x[j] : zero;
+      ca[u] = j < len ? col[j] : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 64 * u;
+      const double2 xv = xa[u];
+      const double2 v = j == 0 ? make_double2(1.0, 0.0)
+                               : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+      const double2 a = ca[u];
+      // conj(a) v (zero beyond len)
+      ar += a.x * v.x + a.y * v.y;
+      ai += a.x * v.y - a.y * v.x;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     ar += __shfl_xor(ar, off, 64);
@@ -339,28 +358,49 @@ k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict
     if (i < len) K[(k + 1 + i) + (int64_t)k * ldk] = v[i];
   }
   const double2 t = tau[k];
+  const double2 zero = make_double2(0.0, 0.0);
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  // the tile's entries do not depend on anything below: load them first
+  double2 av[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int i = i0 + (e & 31), j = j0 + (e >> 5);
+    av[u] = (i < len && j < len) ? A[i + (int64_t)j * ldk] : zero;
+  }
+  // the 64 edge entries of v and y this block needs (rows i0.., columns j0..)
+  const int qe = threadIdx.x < 32 ? i0 + threadIdx.x : j0 + (int)threadIdx.x - 32;
+  const bool edge = threadIdx.x < 64 && qe < len;
+  const double2 ve = edge ? v[qe] : zero, ye = edge ? y[qe] : zero;
   double s = 0.0;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) s += v[i].x * y[i].x + v[i].y * y[i].y;  // Re(conj(v) y)
+  for (int q0 = threadIdx.x; q0 < len; q0 += 4 * 256) {
+    double2 va[4], ya[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 256 * u;
+      va[u] = q < len ? v[q] : zero;
+      ya[u] = q < len ? y[q] : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += va[u].x * ya[u].x + va[u].y * ya[u].y;  // Re(conj(v) y)
+  }
   s = block_sum(s, red);
   const double c = -0.5 * (t.x * t.x + t.y * t.y) * s;
-  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
-  if (threadIdx.x < 32) {
-    const int i = i0 + threadIdx.x;
-    if (i < len) {
-      const double2 vi = v[i], yi = y[i];
-      vi_s[threadIdx.x] = vi;
-      wi_s[threadIdx.x] = make_double2(t.x * yi.x - t.y * yi.y + c * vi.x, t.x * yi.y + t.y * yi.x + c * vi.y);
-    }
-  } else if (threadIdx.x < 64) {
-    const int j = j0 + threadIdx.x - 32;
-    if (j < len) {
-      const double2 vj = v[j], yj = y[j];
-      vj_s[threadIdx.x - 32] = vj;
-      wj_s[threadIdx.x - 32] = make_double2(t.x * yj.x - t.y * yj.y + c * vj.x, t.x * yj.y + t.y * yj.x + c * vj.y);
+  if (edge) {
+    const double2 w = make_double2(t.x * ye.x - t.y * ye.y + c * ve.x, t.x * ye.y + t.y * ye.x + c * ve.y);
+    if (threadIdx.x < 32) {
+      vi_s[threadIdx.x] = ve;
+      wi_s[threadIdx.x] = w;
+    } else {
+      vj_s[threadIdx.x - 32] = ve;
+      wj_s[threadIdx.x - 32] = w;
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+  // 4 entries per thread (256 threads, 32 x 32 tile), loaded at the start
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
     const int ii = e & 31, jj = e >> 5;
     const int i = i0 + ii, j = j0 + jj;
     if (i < len && j < len) {
@@ -368,9 +408,7 @@ k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict
       // w_i conj(v_j) + v_i conj(w_j)
       const double re = wi.x * vj.x + wi.y * vj.y + vi.x * wj.x + vi.y * wj.y;
       const double im = wi.y * vj.x - wi.x * vj.y + vi.y * wj.x - vi.x * wj.y;
-      double2* a = A + i + (int64_t)j * ldk;
-      a->x -= re;
-      a->y -= im;
+      A[i + (int64_t)j * ldk] = make_double2(av[u].x - re, av[u].y - im);
     }
   }
 }

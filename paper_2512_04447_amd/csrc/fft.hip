@@ -119,6 +119,14 @@ template <int R, typename T2> struct DftOdd {
 template <typename T2> struct Dft<5, T2> : DftOdd<5, T2> {};
 template <typename T2> struct Dft<7, T2> : DftOdd<7, T2> {};
 
+// LDS layout of a plane or pencil tile: one pad element after every 16, so
+// that accesses with a small power-of-two element stride (the stride-R
+// writes of a first Stockham stage, stride-2 pairs) fall in different banks.
+// The plane passes use it; the x-pencil tiles of pass B (contiguous batches,
+// conflict-free already) do not.
+template <bool PAD = true> __device__ inline int lpad(int i) { return PAD ? i + (i >> 4) : i; }
+__host__ __device__ inline int lpad_size(int n) { return n + (n >> 4) + 1; }
+
 // ---------------------------------------------------------------- Stockham
 // One radix-R stage over `nbatch` transforms of length n stored in LDS with
 // element stride es and batch stride bs.  Ns = product of earlier radices.
@@ -128,7 +136,7 @@ template <typename T2> struct Dft<7, T2> : DftOdd<7, T2> {};
 // transforms when those are the contiguous direction (bs < es), so a wave's
 // LDS accesses stride by bs rather than by es (a large power of two for the
 // y and x transforms, which would put every lane in one bank).
-template <int R, int MAXE, typename T2>
+template <int R, int MAXE, bool PAD, typename T2>
 __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, int Ns,
                                       const T2* __restrict__ tw) {
   constexpr int NBF = (MAXE + R - 1) / R;
@@ -146,10 +154,10 @@ __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, 
       const int b = bfast ? w % nbatch : w / nbf;
       const int j = bfast ? w / nbatch : w - b * nbf;
       const int k = j % Ns;
-      const T2* base = s + b * bs;
+      const int base = b * bs;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        T2 a = base[(j + q * nbf) * es];
+        T2 a = s[lpad<PAD>(base + (j + q * nbf) * es)];
         if (q > 0 && k > 0) a = cmul(a, tw[q * k * tstep]);
         v[u][q] = a;
       }
@@ -162,24 +170,24 @@ __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, 
   for (int u = 0; u < NBF; ++u) {
     if (dst[u] >= 0) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) s[dst[u] + q * Ns * es] = v[u][q];
+      for (int q = 0; q < R; ++q) s[lpad<PAD>(dst[u] + q * Ns * es)] = v[u][q];
     }
   }
   __syncthreads();
 }
 
-template <int MAXE, typename T2>
+template <int MAXE, bool PAD = true, typename T2>
 __device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, int bs,
                                  const T2* __restrict__ tw) {
   int Ns = 1;
   for (int st = 0; st < ap.nst; ++st) {
     const int R = ap.rad[st];
     switch (R) {
-      case 2: stockham_stage<2, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
-      case 3: stockham_stage<3, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
-      case 4: stockham_stage<4, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
-      case 5: stockham_stage<5, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
-      case 7: stockham_stage<7, MAXE>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 2: stockham_stage<2, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 3: stockham_stage<3, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 4: stockham_stage<4, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 5: stockham_stage<5, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 7: stockham_stage<7, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
       default: break;
     }
     Ns *= R;
@@ -206,6 +214,11 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * ld + off;
+  // twiddle tables of the two axes, staged in LDS after the plane
+  T2* st1 = s + lpad_size(plane);
+  T2* st2 = st1 + n1;
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
   double acc = 0.0;
   if (MODE == 1) {
     const T2* in2 = src2 + band * ld + off;  // x
@@ -215,16 +228,16 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
       T2 b = in2[i];
       T2 r = cmake<T2>(a.x - th * b.x, a.y - th * b.y);
       acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-      s[i] = r;
+      s[lpad(i)] = r;
     }
   } else {
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) s[i] = in[i];
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = in[i];
   }
   __syncthreads();
-  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, tw2);  // z rows
-  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, tw1);  // y columns
+  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
+  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
   T2* out = dst + band * ldd + off;
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = s[i];
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = s[lpad(i)];
   if (MODE == 1) {
     double t = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -265,18 +278,21 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   T2* base = buf + band * ld + (int64_t)y * n2 + z0;
   const int64_t xs = (int64_t)n1 * n2;
   const int tile = n0 * zc;
+  T2* st0 = s + tile;  // x-axis twiddles staged in LDS after the tile
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) st0[i] = tw0[i];
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int x = i / zc, z = i - x * zc;
     s[i] = base[x * xs + z];
   }
   __syncthreads();
-  fft_batch<MAXE>(s, zc, f.ax[0], zc, 1, tw0);
+  fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
   if (MODE == 2) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < tile; i += blockDim.x) {
       const int kx = i / zc, z = i - kx * zc;
       const double t = (double)kinetic_of<T>(f, kx, y, z0 + z);
-      acc += t * ((double)s[i].x * s[i].x + (double)s[i].y * s[i].y);
+      const T2 sv = s[i];
+      acc += t * ((double)sv.x * sv.x + (double)sv.y * sv.y);
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -291,7 +307,7 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
     s[i] = cmake<T2>(v.x * fac, -v.y * fac);  // conj for the inverse transform
   }
   __syncthreads();
-  fft_batch<MAXE>(s, zc, f.ax[0], zc, 1, tw0);
+  fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int x = i / zc, z = i - x * zc;
     T2 v = s[i];
@@ -318,16 +334,20 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * lds_ + off;
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) s[i] = cconj(in[i]);
+  T2* st1 = s + lpad_size(plane);  // twiddle tables staged in LDS after the plane
+  T2* st2 = st1 + n1;
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = cconj(in[i]);
   __syncthreads();
-  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, tw1);  // y columns
-  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, tw2);  // z rows
+  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
+  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
   const T scale = T(1.0 / ((double)n0 * (double)n1 * (double)n2));
   T2* out = dst + band * ldd + off;
   if (MODE == 0) {
     const T2* ps = psi + band * ldp + off;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      T2 t = s[i];
+      T2 t = s[lpad(i)];
       T2 p = ps[i];
       const T vr = V[off + i];
       out[i] = cmake<T2>(t.x * scale + vr * p.x, -t.y * scale + vr * p.y);
@@ -335,7 +355,7 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   } else {
     const T m = (res[band] > lock_tol) ? scale : T(0);
     for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      T2 t = s[i];
+      T2 t = s[lpad(i)];
       out[i] = cmake<T2>(t.x * m, -t.y * m);
     }
   }
