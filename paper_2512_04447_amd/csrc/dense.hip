@@ -429,14 +429,15 @@ __device__ inline double pivmin_of(const double* e, int n) {
   return DBL_MIN * m;
 }
 
-// number of eigenvalues of the tridiagonal (d, e) below x (Sturm count)
-__device__ inline int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+// Sturm count with d and e^2 staged in LDS (the recurrence carries q in a
+// register; the loads do not depend on it).
+__device__ inline int sturm_count_lds(const double* sd, const double* se2, int n, double x, double pivmin) {
   int cnt = 0;
-  double q = d[0] - x;
+  double q = sd[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = sd[i] - x - se2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
   }
@@ -446,13 +447,22 @@ __device__ inline int sturm_count(const double* d, const double* e, int n, doubl
 // Eigenvalue idx = blockIdx.x by multisection: each of the 64 lanes takes a
 // Sturm count at one of 64 interior points of [lo, hi], and the interval
 // shrinks to the sub-interval where the count passes idx (65x per round).
+// Dynamic LDS: 2n doubles (d and e^2).
 __global__ void __launch_bounds__(64)
 k_bisect(const double* __restrict__ d, const double* __restrict__ e, int n, int nev, double* __restrict__ w,
          double* __restrict__ tnorm_out) {
   __shared__ int cnt[64];
   __shared__ double red[2];
+  extern __shared__ __align__(16) unsigned char bis_raw[];
+  double* sd = reinterpret_cast<double*>(bis_raw);
+  double* se2 = sd + n;
   const int idx = blockIdx.x;
   const int t = threadIdx.x;
+  for (int i = t; i < n; i += 64) {
+    sd[i] = d[i];
+    se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
   double gl = DBL_MAX, gu = -DBL_MAX, em = 1.0;
   for (int i = t; i < n; i += 64) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
@@ -472,7 +482,7 @@ k_bisect(const double* __restrict__ d, const double* __restrict__ e, int n, int 
   for (int round = 0; round < 40; ++round) {
     if (hi - lo <= fmax(4.0 * DBL_EPSILON * tnorm, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) + pivmin) break;
     const double x = lo + (hi - lo) * (double)(t + 1) / 65.0;
-    cnt[t] = sturm_count(d, e, n, x, pivmin);
+    cnt[t] = sturm_count_lds(sd, se2, n, x, pivmin);
     __syncthreads();
     if (t == 0) {
       // first point whose count exceeds idx: the eigenvalue lies below it
@@ -515,25 +525,31 @@ __global__ void k_clusters(const double* __restrict__ w, int nev, const double* 
 // Inverse iteration for the eigenvalues of one cluster (one block per
 // cluster; blocks past the cluster count exit).  Solves (T - lambda I) x = b
 // by Gaussian elimination with partial pivoting on the tridiagonal matrix
-// (thread 0), re-orthogonalises against the earlier vectors of the cluster
-// (modified Gram-Schmidt, all threads) and normalises; three sweeps.
+// (thread 0; the recurrences carry their running values in registers and
+// store the factors in LDS), re-orthogonalises against the earlier vectors
+// of the cluster (modified Gram-Schmidt, all threads) and normalises; three
+// sweeps.  Dynamic LDS: 5n doubles (the factor U0 (as its reciprocal), U1,
+// U2, the multipliers and x) and n ints (pivots).
 __global__ void __launch_bounds__(256)
 k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, int n, const double* __restrict__ w,
                     const double* __restrict__ tnorm_p, const int32_t* __restrict__ cl,
-                    const int32_t* __restrict__ ncl, double* __restrict__ Z, int ldz, double* __restrict__ scratch) {
+                    const int32_t* __restrict__ ncl, double* __restrict__ Z, int ldz) {
   __shared__ double red[4];
   __shared__ double lam_prev;
+  extern __shared__ __align__(16) unsigned char ii_raw[];
+  double* ru0 = reinterpret_cast<double*>(ii_raw);  // 1 / U0
+  double* u1 = ru0 + n;
+  double* u2 = u1 + n;
+  double* lm = u2 + n;
+  double* x = lm + n;
+  int* piv = reinterpret_cast<int*>(x + n);
   const int c = blockIdx.x;
   if (c >= *ncl) return;
   const int j0 = cl[c], j1 = cl[c + 1];
-  double* u0 = scratch + (size_t)c * 5 * n;
-  double* u1 = u0 + n;
-  double* u2 = u1 + n;
-  double* lm = u2 + n;
-  int* piv = reinterpret_cast<int*>(lm + n);
   const double tnorm = *tnorm_p;
   const double eps = DBL_EPSILON;
   const double pertol = 10.0 * eps * fmax(tnorm, DBL_MIN);
+  const double small = eps * fmax(tnorm, DBL_MIN);
   for (int j = j0; j < j1; ++j) {
     double lam = w[j];
     if (threadIdx.x == 0) {
@@ -542,60 +558,71 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
     }
     __syncthreads();
     lam = lam_prev;
-    double* x = Z + (int64_t)j * ldz;
-    // LU factorisation of T - lam I with partial pivoting (thread 0)
     if (threadIdx.x == 0) {
-      const double small = eps * fmax(tnorm, DBL_MIN);
-      for (int i = 0; i < n; ++i) {
-        u0[i] = d[i] - lam;
-        u1[i] = (i + 1 < n) ? e[i] : 0.0;
-        u2[i] = 0.0;
-      }
+      // LU of T - lam I with partial pivoting; (c0, c1) are the diagonal and
+      // superdiagonal of row i as modified by the previous elimination step
+      double c0 = d[0] - lam, c1 = n > 1 ? e[0] : 0.0;
       for (int i = 0; i + 1 < n; ++i) {
         const double b = e[i];
-        if (fabs(u0[i]) >= fabs(b)) {
-          const double piv0 = (u0[i] == 0.0) ? small : u0[i];
-          u0[i] = piv0;
-          const double l = b / piv0;
+        const double n0 = d[i + 1] - lam, n1 = i + 2 < n ? e[i + 1] : 0.0;
+        if (fabs(c0) >= fabs(b)) {
+          const double p0 = c0 == 0.0 ? small : c0;
+          const double l = b / p0;
+          ru0[i] = 1.0 / p0;
+          u1[i] = c1;
+          u2[i] = 0.0;
           lm[i] = l;
           piv[i] = 0;
-          u0[i + 1] -= l * u1[i];
+          c0 = n0 - l * c1;
+          c1 = n1;
         } else {
-          const double l = u0[i] / b;
+          const double l = c0 / b;
+          ru0[i] = 1.0 / b;
+          u1[i] = n0;
+          u2[i] = n1;
           lm[i] = l;
           piv[i] = 1;
-          const double a1 = u0[i + 1], c1 = u1[i + 1];
-          const double old_u1 = u1[i];
-          u0[i] = b;
-          u1[i] = a1;
-          u2[i] = c1;
-          u0[i + 1] = old_u1 - l * a1;
-          u1[i + 1] = -l * c1;
+          c0 = c1 - l * n0;
+          c1 = -l * n1;
         }
       }
-      if (u0[n - 1] == 0.0) u0[n - 1] = small;
-      // deterministic start vector
-      for (int i = 0; i < n; ++i) {
-        unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)(j * 40503u + 12345u);
-        h ^= h >> 13; h *= 0x5bd1e995u; h ^= h >> 15;
-        x[i] = 0.5 + (double)(h & 0xffff) / 65536.0;
-      }
+      ru0[n - 1] = 1.0 / (c0 == 0.0 ? small : c0);
+      u1[n - 1] = 0.0;
+      u2[n - 1] = 0.0;
+    }
+    // deterministic start vector
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)(j * 40503u + 12345u);
+      h ^= h >> 13; h *= 0x5bd1e995u; h ^= h >> 15;
+      x[i] = 0.5 + (double)(h & 0xffff) / 65536.0;
     }
     __syncthreads();
+    double* zj = Z + (int64_t)j * ldz;
     for (int sweep = 0; sweep < 3; ++sweep) {
       if (threadIdx.x == 0) {
+        // forward: apply the row exchanges and multipliers (cur = x[i])
+        double cur = x[0];
         for (int i = 0; i + 1 < n; ++i) {
+          const double nx = x[i + 1], l = lm[i];
           if (piv[i] == 0) {
-            x[i + 1] -= lm[i] * x[i];
+            x[i] = cur;
+            cur = nx - l * cur;
           } else {
-            const double t0 = x[i], t1 = x[i + 1];
-            x[i] = t1;
-            x[i + 1] = t0 - lm[i] * t1;
+            x[i] = nx;
+            cur = cur - l * nx;
           }
         }
-        x[n - 1] = x[n - 1] / u0[n - 1];
-        if (n > 1) x[n - 2] = (x[n - 2] - u1[n - 2] * x[n - 1]) / u0[n - 2];
-        for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / u0[i];
+        x[n - 1] = cur;
+        // back substitution with U (three diagonals)
+        double xa = x[n - 1] * ru0[n - 1];  // x[i+1]
+        double xb = 0.0;                    // x[i+2]
+        x[n - 1] = xa;
+        for (int i = n - 2; i >= 0; --i) {
+          const double xi = (x[i] - u1[i] * xa - u2[i] * xb) * ru0[i];
+          x[i] = xi;
+          xb = xa;
+          xa = xi;
+        }
       }
       __syncthreads();
       // scale to avoid growth, then MGS against earlier vectors of the cluster
@@ -624,44 +651,61 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
       for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= inv;
       __syncthreads();
     }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) zj[i] = x[i];
+    __syncthreads();
   }
 }
 
 // C[:, j] = Q Z_T[:, j], Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H.
-__global__ void __launch_bounds__(256)
+// One wave per eigenvector (64-thread blocks), z in LDS: the reflector
+// dot products reduce by shuffles, and the wave executes its LDS accesses in
+// order, so no block barrier is needed between reflectors.
+__global__ void __launch_bounds__(64)
 k_backtransform(const double2* __restrict__ K, int ldk, int n, const double2* __restrict__ tau,
                 const double* __restrict__ Z, int ldz, double2* __restrict__ C, int ldc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2* z = reinterpret_cast<double2*>(smem_raw);
-  __shared__ double red[4];
   const int j = blockIdx.x;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) z[i] = make_double2(Z[i + (int64_t)j * ldz], 0.0);
+  const int lane = threadIdx.x;
+  for (int i = lane; i < n; i += 64) z[i] = make_double2(Z[i + (int64_t)j * ldz], 0.0);
   __syncthreads();
+  const double2 zero = make_double2(0.0, 0.0);
   for (int k = n - 2; k >= 0; --k) {
     const double2 t = tau[k];
-    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
+    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the wave
     const double2* v = K + (k + 1) + (int64_t)k * ldk;
+    double2* zk = z + k + 1;
     const int len = n - k - 1;
     double sr = 0.0, si = 0.0;
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-      const double2 a = v[i], b = z[k + 1 + i];
-      sr += a.x * b.x + a.y * b.y;  // conj(v) z
-      si += a.x * b.y - a.y * b.x;
+    for (int i0 = lane; i0 < len; i0 += 256) {
+      double2 va[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) va[u] = i0 + 64 * u < len ? v[i0 + 64 * u] : zero;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + 64 * u < len) {
+          const double2 b = zk[i0 + 64 * u];
+          sr += va[u].x * b.x + va[u].y * b.y;  // conj(v) z
+          si += va[u].x * b.y - va[u].y * b.x;
+        }
+      }
     }
-    sr = block_sum(sr, red);
-    si = block_sum(si, red);
+    for (int off = 32; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
     // f = tau * (v^H z)
     const double fr = t.x * sr - t.y * si, fi = t.x * si + t.y * sr;
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    for (int i = lane; i < len; i += 64) {
       const double2 a = v[i];
-      double2 b = z[k + 1 + i];
+      double2 b = zk[i];
       b.x -= fr * a.x - fi * a.y;
       b.y -= fr * a.y + fi * a.x;
-      z[k + 1 + i] = b;
+      zk[i] = b;
     }
-    __syncthreads();
+    __syncthreads();  // a single wave: orders this reflector's LDS writes before the next reads
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) C[i + (int64_t)j * ldc] = z[i];
+  for (int i = lane; i < n; i += 64) C[i + (int64_t)j * ldc] = z[i];
 }
 
 // ---------------------------------------------------------------- hegv
@@ -677,7 +721,6 @@ struct HegvWs {
   int32_t* cl;
   int32_t* ncl;
   double* Z;
-  double* scratch;
   double2* tmp;
 };
 
@@ -695,15 +738,13 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   w.cl = reinterpret_cast<int32_t*>(p); p += al((size_t)(nev + 1) * 4);
   w.ncl = reinterpret_cast<int32_t*>(p); p += 256;
   w.Z = reinterpret_cast<double*>(p); p += al((size_t)n * nev * 8);
-  w.scratch = reinterpret_cast<double*>(p); p += al((size_t)nev * 5 * n * 8);
   w.tmp = reinterpret_cast<double2*>(p); p += al((size_t)NB * n * sizeof(double2));
   return w;
 }
 
 size_t hegv_work(int n, int nev) {
   return al(potrf_work(n)) + al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
-         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)nev * 5 * n * 8) +
-         al((size_t)NB * n * 16);
+         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16);
 }
 
 int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, double2* C, int ldc, void* work,
@@ -732,12 +773,13 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   }
   KS_LAUNCH_CHECK("tridiagonalisation");
   hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
-  hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), 0, s, ws.d, ws.e, n, nev, w, ws.tnorm);
+  hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), (size_t)2 * n * sizeof(double), s, ws.d, ws.e, n, nev, w,
+                     ws.tnorm);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, w, nev, ws.tnorm, ws.cl, ws.ncl);
-  hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), 0, s, ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl,
-                     ws.Z, n, ws.scratch);
+  hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), (size_t)n * (5 * sizeof(double) + sizeof(int)), s,
+                     ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl, ws.Z, n);
   KS_LAUNCH_CHECK("bisection / inverse iteration");
-  hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(256), (size_t)n * sizeof(double2), s, ws.K, n, n, ws.tau,
+  hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(64), (size_t)n * sizeof(double2), s, ws.K, n, n, ws.tau,
                      ws.Z, n, C, ldc);
   KS_LAUNCH_CHECK("backtransform");
   // C = L^-H Z
