@@ -58,8 +58,9 @@ extern "C" {
  *   FP32 with FP32 accumulation inside each K chunk and FP64 summation of
  *   the chunks; Cholesky, triangular solves, eigensolve and the X
  *   re-orthonormalisation factor in FP64; rotation in FP32.
- * KS_MIXED_BF16X3: as KS_MIXED_FP32 but the H Gram uses three bf16 products
- *   (hi*hi + hi*lo + lo*hi) per real product; S stays FP32. */
+ * KS_MIXED_BF16X3: reserved for an H Gram from three bf16 products
+ *   (hi*hi + hi*lo + lo*hi) per real product; not built: ks_plan_create
+ *   returns KS_E_UNSUPPORTED for it. */
 typedef enum { KS_FP64 = 0, KS_MIXED_FP32 = 1, KS_MIXED_BF16X3 = 2 } ks_precision;
 
 typedef struct {

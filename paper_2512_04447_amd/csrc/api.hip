@@ -97,13 +97,11 @@ static int upload_vec(const std::vector<T>& h, T** out) {
 template <typename T>
 static int upload_proj(ks_plan* p, const ks_projset* ps) {
   const int na = ps->n_atoms;
-  std::vector<int32_t> sp(ps->atom_supp_ptr, ps->atom_supp_ptr + na + 1);
-  std::vector<int32_t> si(ps->supp_idx, ps->supp_idx + ps->n_supp);
-  std::vector<int32_t> pp(ps->atom_proj_ptr, ps->atom_proj_ptr + na + 1);
-  std::vector<int64_t> bp(ps->beta_ptr, ps->beta_ptr + na + 1);
-  const int64_t nbeta = bp[na];
-  std::vector<T> beta(nbeta), D(ps->n_proj);
-  for (int64_t i = 0; i < nbeta; ++i) beta[i] = (T)ps->beta[i];
+  const int32_t* sp = ps->atom_supp_ptr;
+  const int32_t* si = ps->supp_idx;
+  const int32_t* pp = ps->atom_proj_ptr;
+  const int64_t* bp = ps->beta_ptr;
+  std::vector<T> D(ps->n_proj);
   for (int i = 0; i < ps->n_proj; ++i) D[i] = (T)ps->D[i];
   // inverse table by grid point: entries (projector, value), projectors ascending
   std::vector<int32_t> cnt(p->Ng + 1, 0);
@@ -116,20 +114,22 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
   if (nnz > INT32_MAX) return fail(KS_E_UNSUPPORTED, "projector table too large");
   std::vector<int32_t> pt_proj(nnz);
   std::vector<T> pt_beta(nnz);
-  std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
-  for (int a = 0; a < na; ++a) {
-    const int ns = sp[a + 1] - sp[a];
-    for (int j = 0; j < pp[a + 1] - pp[a]; ++j) {
-      for (int s = 0; s < ns; ++s) {
-        const int r = si[sp[a] + s];
-        const int32_t slot = fillp[r]++;
-        pt_proj[slot] = pp[a] + j;
-        pt_beta[slot] = (T)ps->beta[bp[a] + (int64_t)j * ns + s];
+  {
+    std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
+    for (int a = 0; a < na; ++a) {
+      const int ns = sp[a + 1] - sp[a];
+      for (int j = 0; j < pp[a + 1] - pp[a]; ++j) {
+        for (int s = 0; s < ns; ++s) {
+          const int r = si[sp[a] + s];
+          const int32_t slot = fillp[r]++;
+          pt_proj[slot] = pp[a] + j;
+          pt_beta[slot] = (T)ps->beta[bp[a] + (int64_t)j * ns + s];
+        }
       }
     }
   }
-  // per block of kScatterPts points: the projectors its entries touch, and
-  // the entries' projector ids rewritten as indices into that list
+  // per block of kScatterPts points: the projectors its entries touch (its
+  // rows), and the entries' projector ids rewritten as row-local indices
   const int64_t nblk = (p->Ng + kScatterPts - 1) / kScatterPts;
   std::vector<int32_t> blk_ptr(nblk + 1, 0), blk_proj;
   std::vector<int32_t> local(ps->n_proj, -1);
@@ -149,33 +149,59 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
     blk_ptr[k + 1] = (int32_t)blk_proj.size();
     maxl = std::max(maxl, (int)(blk_proj.size() - first));
   }
+  if (maxl > 65535) return fail(KS_E_UNSUPPORTED, "too many projectors touch one block of grid points");
+  // scatter: ELL slots per block
+  std::vector<int32_t> ell_ptr(nblk + 1, 0);
+  for (int64_t k = 0; k < nblk; ++k) {
+    int wmax = 0;
+    for (int64_t r = k * kScatterPts; r < std::min<int64_t>(p->Ng, (k + 1) * kScatterPts); ++r)
+      wmax = std::max(wmax, cnt[r + 1] - cnt[r]);
+    ell_ptr[k + 1] = ell_ptr[k] + wmax;
+  }
+  const int64_t nell = (int64_t)ell_ptr[nblk] * kScatterPts;
+  std::vector<uint16_t> ell_lp(std::max<int64_t>(nell, 1), 0);
+  std::vector<T> ell_beta(std::max<int64_t>(nell, 1), T(0));
+  for (int64_t r = 0; r < p->Ng; ++r) {
+    const int64_t k = r / kScatterPts, t = r - k * kScatterPts;
+    for (int32_t e = cnt[r]; e < cnt[r + 1]; ++e) {
+      const int64_t idx = ((int64_t)ell_ptr[k] + (e - cnt[r])) * kScatterPts + t;
+      ell_lp[idx] = (uint16_t)pt_proj[e];
+      ell_beta[idx] = pt_beta[e];
+    }
+  }
   if (blk_proj.empty()) blk_proj.push_back(0);
-  int maxp = 0;
-  for (int a = 0; a < na; ++a) maxp = std::max(maxp, pp[a + 1] - pp[a]);
   p->natoms = na;
   p->nproj = ps->n_proj;
-  p->maxp = maxp;
-  p->nsupp = ps->n_supp;
   p->nnz = nnz;
+  p->nblk = nblk;
   p->maxl = maxl;
+  int maxp = 0;
+  for (int a = 0; a < na; ++a) maxp = std::max(maxp, pp[a + 1] - pp[a]);
+  p->maxp = maxp;
   int rc;
   if ((rc = upload_vec(blk_ptr, &p->blk_ptr))) return rc;
   if ((rc = upload_vec(blk_proj, &p->blk_proj))) return rc;
-  if ((rc = upload_vec(sp, &p->supp_ptr))) return rc;
-  if ((rc = upload_vec(si, &p->supp_idx))) return rc;
-  if ((rc = upload_vec(pp, &p->proj_ptr))) return rc;
-  if ((rc = upload_vec(bp, &p->beta_ptr))) return rc;
-  T* b = nullptr;
-  if ((rc = upload_vec(beta, &b))) return rc;
-  p->beta = b;
+  if ((rc = upload_vec(ell_ptr, &p->ell_ptr))) return rc;
+  if ((rc = upload_vec(ell_lp, &p->ell_lp))) return rc;
+  {
+    std::vector<int32_t> spv(sp, sp + na + 1), siv(si, si + ps->n_supp), ppv(pp, pp + na + 1);
+    std::vector<int64_t> bpv(bp, bp + na + 1);
+    std::vector<T> bv(bp[na]);
+    for (int64_t i = 0; i < bp[na]; ++i) bv[i] = (T)ps->beta[i];
+    if ((rc = upload_vec(spv, &p->supp_ptr))) return rc;
+    if ((rc = upload_vec(siv, &p->supp_idx))) return rc;
+    if ((rc = upload_vec(ppv, &p->proj_ptr))) return rc;
+    if ((rc = upload_vec(bpv, &p->beta_ptr))) return rc;
+    T* b = nullptr;
+    if ((rc = upload_vec(bv, &b))) return rc;
+    p->beta = b;
+  }
   T* d = nullptr;
   if ((rc = upload_vec(D, &d))) return rc;
   p->Dcoef = d;
-  if ((rc = upload_vec(cnt, &p->pt_ptr))) return rc;
-  if ((rc = upload_vec(pt_proj, &p->pt_proj))) return rc;
-  T* pb = nullptr;
-  if ((rc = upload_vec(pt_beta, &pb))) return rc;
-  p->pt_beta = pb;
+  T* eb = nullptr;
+  if ((rc = upload_vec(ell_beta, &eb))) return rc;
+  p->ell_beta = eb;
   return 0;
 }
 
@@ -643,6 +669,7 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   if (!grid) return fail(-2, "grid is null");
   if (nb_max <= 0) return fail(-4, "nb_max must be positive");
   if (precision < KS_FP64 || precision > KS_MIXED_BF16X3) return fail(-5, "unknown precision");
+  if (precision == KS_MIXED_BF16X3) return fail(KS_E_UNSUPPORTED, "the bf16x3 Gram split is not built");
   ks_plan* p = new ks_plan();
   p->grid = *grid;
   p->nb_max = nb_max;
@@ -714,8 +741,8 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
 int ks_plan_destroy(ks_plan* p) {
   if (!p) return 0;
   for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
-  void* bufs[] = {p->supp_ptr, p->supp_idx, p->proj_ptr, p->beta_ptr, p->beta, p->Dcoef, p->pt_ptr, p->pt_proj, p->pt_beta,
-                  p->blk_ptr, p->blk_proj};
+  void* bufs[] = {p->Dcoef,   p->blk_ptr,  p->blk_proj, p->ell_ptr,  p->ell_lp, p->ell_beta,
+                  p->supp_ptr, p->supp_idx, p->proj_ptr, p->beta_ptr, p->beta};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;

@@ -362,6 +362,8 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
 }
 
 // ---------------------------------------------------------------- nonlocal
+// Deterministic (no atomics, fixed summation orders).
+
 // Projection c[band][p] = sum_{s in S_a} beta_p(s) psi_band(s), scaled by D_p.
 // One block per (atom, tile of NBT bands); the support list is streamed
 // once per tile and every psi value feeds all projectors of the atom.
@@ -430,45 +432,57 @@ k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* _
   }
 }
 
-// Nonlocal scatter: hpsi[b][r] += sum_{e in row r} beta_e dc[proj_e][b] through
-// the per-point inverse table (no atomics; fixed order).  A block owns
-// kScatterPts consecutive grid points and NBS bands; the dc rows of the
-// projectors its points touch are staged in LDS first (rows padded by one
-// element so that lanes reading different rows fall in different banks),
-// and each table entry indexes that list.  dc is [projector][band].
+// Nonlocal scatter: hpsi[b][r] += sum over the entries of point r of
+// beta * dc[proj][b].  A block owns kScatterPts consecutive points and NBS
+// bands; the dc rows of its projectors are staged in LDS (rows padded by one
+// element so that lanes reading different rows fall in different banks), and
+// the entries come from the ELL table (slot-major, so a wave's loads of one
+// slot are contiguous; unused slots have value 0).  dc is [projector][band].
 template <typename T, int NBS>
 __global__ void __launch_bounds__(kScatterPts)
-k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int32_t* __restrict__ pt_ptr,
-             const int32_t* __restrict__ pt_lproj, const T* __restrict__ pt_beta,
+k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int32_t* __restrict__ ell_ptr,
+             const uint16_t* __restrict__ ell_lp, const T* __restrict__ ell_beta,
              const int32_t* __restrict__ blk_ptr, const int32_t* __restrict__ blk_proj,
              const c2<T>* __restrict__ dc) {
   using T2 = c2<T>;
   constexpr int ROW = NBS + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* sdc = reinterpret_cast<T2*>(smem_raw);
+  const int64_t k = blockIdx.x;
   const int b0 = blockIdx.y * NBS;
   const int nbl = min(NBS, nb - b0);
-  const int l0 = blk_ptr[blockIdx.x];
-  const int nl = blk_ptr[blockIdx.x + 1] - l0;
+  const int l0 = blk_ptr[k];
+  const int nl = blk_ptr[k + 1] - l0;
   for (int i = threadIdx.x; i < nl * NBS; i += blockDim.x) {
     const int l = i / NBS, b = i - l * NBS;
     sdc[l * ROW + b] = b < nbl ? dc[(int64_t)blk_proj[l0 + l] * nb + b0 + b] : cmake<T2>(T(0), T(0));
   }
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * kScatterPts + threadIdx.x;
+  const int64_t r = k * kScatterPts + threadIdx.x;
   if (r >= Ng) return;
   T ax[NBS], ay[NBS];
 #pragma unroll
   for (int b = 0; b < NBS; ++b) ax[b] = ay[b] = T(0);
-  const int e0 = pt_ptr[r], e1 = pt_ptr[r + 1];
-  for (int e = e0; e < e1; ++e) {
-    const T be = pt_beta[e];
-    const T2* c = sdc + pt_lproj[e] * ROW;
+  const int w = ell_ptr[k + 1] - ell_ptr[k];
+  const int64_t base = (int64_t)ell_ptr[k] * kScatterPts + threadIdx.x;
+  for (int s0 = 0; s0 < w; s0 += 4) {
+    int lp[4];
+    T be[4];
 #pragma unroll
-    for (int b = 0; b < NBS; ++b) {
-      const T2 v = c[b];
-      ax[b] += be * v.x;
-      ay[b] += be * v.y;
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = s0 + u < w;
+      lp[u] = ok ? (int)ell_lp[base + (int64_t)(s0 + u) * kScatterPts] : 0;
+      be[u] = ok ? ell_beta[base + (int64_t)(s0 + u) * kScatterPts] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T2* c = sdc + lp[u] * ROW;
+#pragma unroll
+      for (int b = 0; b < NBS; ++b) {
+        const T2 v = c[b];
+        ax[b] += be[u] * v.x;
+        ay[b] += be[u] * v.y;
+      }
     }
   }
 #pragma unroll
@@ -620,18 +634,21 @@ static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2
 template <typename T, int NBS>
 static void launch_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
   const size_t lds = (size_t)p.maxl * (NBS + 1) * sizeof(c2<T>);
-  dim3 grid((unsigned)ceil_div(p.Ng, kScatterPts), (unsigned)ceil_div(nb, NBS));
-  hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(kScatterPts), lds, s, hpsi, ldh, nb, p.Ng, p.pt_ptr,
-                     p.pt_proj, static_cast<const T*>(p.pt_beta), p.blk_ptr, p.blk_proj, dc);
+  dim3 grid((unsigned)p.nblk, (unsigned)ceil_div(nb, NBS));
+  hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(kScatterPts), lds, s, hpsi, ldh, nb, p.Ng, p.ell_ptr,
+                     p.ell_lp, static_cast<const T*>(p.ell_beta), p.blk_ptr, p.blk_proj, dc);
 }
 
-// The widest band group whose staged projector rows fit in 64 KB of LDS.
+// The widest band group (32 bands in FP32, 16 in FP64) whose staged
+// projector rows fit in 64 KB of LDS.
 template <typename T>
 static int nl_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
   TimerScope ts(KF_NL_PROJECT, s);
   const size_t row = (size_t)p.maxl * sizeof(c2<T>);
   constexpr size_t kMax = 64 * 1024;
-  if (row * 17 <= kMax)
+  if (sizeof(T) == 4 && row * 33 <= kMax)
+    launch_scatter<T, 32>(p, hpsi, ldh, nb, dc, s);
+  else if (row * 17 <= kMax)
     launch_scatter<T, 16>(p, hpsi, ldh, nb, dc, s);
   else if (row * 9 <= kMax)
     launch_scatter<T, 8>(p, hpsi, ldh, nb, dc, s);

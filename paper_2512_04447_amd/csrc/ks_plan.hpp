@@ -42,25 +42,30 @@ struct ks_plan {
   int zc;          // z extent of one x-pencil tile
   size_t lds_plane;
   size_t lds_pencil;
-  // projectors
+  // projectors, organised by blocks of kScatterPts consecutive grid points
   int32_t natoms = 0;
   int32_t nproj = 0;
-  int32_t maxp = 0;  // max projectors per atom
-  int64_t nsupp = 0;
-  int64_t nnz = 0;   // entries of the per-point inverse table
+  int32_t maxp = 0;             // max projectors per atom
+  int64_t nnz = 0;              // (point, projector) pairs with a support value
+  int64_t nblk = 0;             // point blocks
+  void* Dcoef = nullptr;        // nproj couplings, plan precision
+  // projection tables, atom-major: support points of atom a at
+  // supp_idx[supp_ptr[a]..], its projectors proj_ptr[a].., values beta
+  // (atom, then projector, then point) from beta_ptr[a]
   int32_t* supp_ptr = nullptr;
   int32_t* supp_idx = nullptr;
   int32_t* proj_ptr = nullptr;
   int64_t* beta_ptr = nullptr;
-  void* beta = nullptr;      // plan precision
-  void* Dcoef = nullptr;     // plan precision
-  int32_t* pt_ptr = nullptr; // Ng + 1
-  int32_t* pt_proj = nullptr; // projector of each entry, local to its block of kScatterPts points
-  void* pt_beta = nullptr;   // plan precision
-  // projectors touched by each block of kScatterPts consecutive points
-  int32_t* blk_ptr = nullptr;   // nblk + 1
+  void* beta = nullptr;         // plan precision
+  int32_t* blk_ptr = nullptr;   // nblk + 1: projectors blk_ptr[k].. touch block k
   int32_t* blk_proj = nullptr;  // global projector ids, ascending within a block
   int32_t maxl = 0;             // largest per-block projector count
+  // scatter table, ELL by block: slot s of point t of block k at
+  // (ell_ptr[k] + s) * kScatterPts + t holds (block-local projector, value);
+  // unused slots hold (0, 0)
+  int32_t* ell_ptr = nullptr;   // nblk + 1
+  uint16_t* ell_lp = nullptr;
+  void* ell_beta = nullptr;     // plan precision
 };
 
 namespace ks {

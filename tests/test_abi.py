@@ -49,6 +49,13 @@ def test_host_validation_rejects_bad_arguments_without_a_gpu():
     assert lib.ks_plan_create(None, None, None, 1, 0, None) == -1
     msg = lib.ks_last_error().decode()
     assert "null" in msg
+    # the bf16x3 Gram split is declared but not built: refused before any GPU call
+    g = binding.KsGrid()
+    g.n[0] = g.n[1] = g.n[2] = 8
+    g.L[0] = g.L[1] = g.L[2] = 5.0
+    out = C.c_void_p()
+    assert lib.ks_plan_create(C.byref(out), C.byref(g), None, 4, binding.KS_MIXED_BF16X3, None) == -2003
+    assert "bf16" in lib.ks_last_error().decode()
 
 
 def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
