@@ -63,7 +63,8 @@ static bool radix_plan(int n, AxisPlan& ap) {
   ap.n = n;
   ap.nst = 0;
   int m = n;
-  const int order[5] = {4, 2, 3, 5, 7};
+  // largest radices first: fewer LDS passes per transform
+  const int order[8] = {16, 8, 7, 6, 5, 4, 3, 2};
   for (int r : order) {
     while (m % r == 0 && m > 1) {
       if (ap.nst >= kMaxStages) return false;

@@ -11,7 +11,7 @@
 //   pass C: per (band, x-plane): inverse y- and z-transforms, 1/Ng, and an
 //           epilogue (local potential and nonlocal scatter for H, lock mask
 //           for the preconditioner).
-// Each 1D transform is a mixed-radix (2, 3, 4, 5, 7) Stockham autosort FFT
+// Each 1D transform is a mixed-radix (16, 8, 7, 6, 5, 4, 3, 2) Stockham autosort FFT
 // done in place in LDS: a stage reads its butterfly inputs into registers,
 // barriers, then writes the outputs to their autosorted positions.  The
 // inverse transform is conj(FFT(conj(.))).
@@ -119,6 +119,68 @@ template <int R, typename T2> struct DftOdd {
 template <typename T2> struct Dft<5, T2> : DftOdd<5, T2> {};
 template <typename T2> struct Dft<7, T2> : DftOdd<7, T2> {};
 
+// exp(-2 pi i m / N) = (c[m], -s[m]) for the composite radices below, from
+// the closed forms of the angles (multiples of pi/3 and pi/8).
+template <int N> struct TwN;
+#define KS_R2 0.70710678118654752440
+#define KS_R3 0.86602540378443864676
+#define KS_C8 0.92387953251128675613
+#define KS_S8 0.38268343236508977173
+template <> struct TwN<6> {
+  static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+  static constexpr double s[6] = {0.0, KS_R3, KS_R3, 0.0, -KS_R3, -KS_R3};
+};
+template <> struct TwN<8> {
+  static constexpr double c[8] = {1.0, KS_R2, 0.0, -KS_R2, -1.0, -KS_R2, 0.0, KS_R2};
+  static constexpr double s[8] = {0.0, KS_R2, 1.0, KS_R2, 0.0, -KS_R2, -1.0, -KS_R2};
+};
+template <> struct TwN<16> {
+  static constexpr double c[16] = {1.0, KS_C8, KS_R2, KS_S8, 0.0, -KS_S8, -KS_R2, -KS_C8,
+                                   -1.0, -KS_C8, -KS_R2, -KS_S8, 0.0, KS_S8, KS_R2, KS_C8};
+  static constexpr double s[16] = {0.0, KS_S8, KS_R2, KS_C8, 1.0, KS_C8, KS_R2, KS_S8,
+                                   0.0, -KS_S8, -KS_R2, -KS_C8, -1.0, -KS_C8, -KS_R2, -KS_S8};
+};
+#undef KS_R2
+#undef KS_R3
+#undef KS_C8
+#undef KS_S8
+
+// Composite radix N = N1 N2 in registers (two-factor Cooley-Tukey): with
+// j = j1 + N1 j2 and k = k1 + N2 k2, X[k] = sum_j1 W_N1^(j1 k2) W_N^(j1 k1)
+// sum_j2 a[j1 + N1 j2] W_N2^(j2 k1): inner size-N2 transforms, constant
+// twiddles, outer size-N1 transforms.  Radix 16 = 4 x 4, 8 = 4 x 2,
+// 6 = 3 x 2.
+template <int N1, int N2, typename T2> struct DftComp {
+  __device__ static void run(T2* a) {
+    using T = decltype(a[0].x);
+    constexpr int N = N1 * N2;
+    T2 B[N1][N2];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) {
+#pragma unroll
+      for (int j2 = 0; j2 < N2; ++j2) B[j1][j2] = a[j1 + N1 * j2];
+      Dft<N2, T2>::run(B[j1]);
+#pragma unroll
+      for (int k1 = 1; k1 < N2; ++k1) {
+        const int m = (j1 * k1) % N;
+        if (j1 > 0) B[j1][k1] = cmul(B[j1][k1], cmake<T2>(T(TwN<N>::c[m]), T(-TwN<N>::s[m])));
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < N2; ++k1) {
+      T2 t[N1];
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) t[j1] = B[j1][k1];
+      Dft<N1, T2>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < N1; ++k2) a[k1 + N2 * k2] = t[k2];
+    }
+  }
+};
+template <typename T2> struct Dft<6, T2> : DftComp<3, 2, T2> {};
+template <typename T2> struct Dft<8, T2> : DftComp<4, 2, T2> {};
+template <typename T2> struct Dft<16, T2> : DftComp<4, 4, T2> {};
+
 // LDS layout of a plane or pencil tile: one pad element after every 16, so
 // that accesses with a small power-of-two element stride (the stride-R
 // writes of a first Stockham stage, stride-2 pairs) fall in different banks.
@@ -188,6 +250,9 @@ __device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, 
       case 4: stockham_stage<4, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
       case 5: stockham_stage<5, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
       case 7: stockham_stage<7, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 6: stockham_stage<6, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 8: stockham_stage<8, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
+      case 16: stockham_stage<16, MAXE, PAD>(s, nbatch, ap.n, es, bs, Ns, tw); break;
       default: break;
     }
     Ns *= R;
