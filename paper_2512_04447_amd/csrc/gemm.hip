@@ -93,9 +93,11 @@ __device__ __forceinline__ void gram_flush(A (&sr)[2][WN], A (&si)[2][WN], A (&h
 // owns 32 x 32 (measured faster for FP64 at both cell sizes).
 template <typename T> constexpr int gram_wj() { return sizeof(T) == 4 ? 4 : 2; }
 template <typename T> constexpr int gram_threads() { return 128 * gram_wj<T>(); }
+// FP64: ask for two resident blocks per CU (two waves per SIMD)
+template <typename T> constexpr int gram_min_blocks() { return sizeof(T) == 8 ? 2 : 1; }
 
 template <typename T, bool TWO>
-__global__ void __launch_bounds__(gram_threads<T>())
+__global__ void __launch_bounds__(gram_threads<T>(), gram_min_blocks<T>())
 k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int64_t K, int64_t kper,
        int ntile, int ntu, int full, double2* __restrict__ partS, double2* __restrict__ partH) {
   using T2 = c2<T>;
