@@ -38,8 +38,8 @@ WORKLOADS = {
 # commands are in profiles/hbm_traffic_fp64_c2.md).  A value holds only
 # while the kernel source it was measured on is unchanged (sha256 below).
 MEASURED_TRAFFIC = {
-    ("C2", "fp64", "gram"): (2.6965e9, "paper_2512_04447_amd/csrc/gemm.hip",
-                             "811babf49ec721c9cb92fd3bb5267fd7c6c2659a8d9aa64195811b108dd6039a"),
+    ("C2", "fp64", "gram"): (2.7275e9, "paper_2512_04447_amd/csrc/gemm.hip",
+                             "5667a84d09377d5cce0cc2b54d2c311c31e51ca744b823f82d803b7950981e98"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
@@ -210,7 +210,8 @@ def main():
                   b.KS_MIXED_FP32 if mixed else b.KS_FP64)
     v = torch.from_numpy(cell.V).cuda()
     x0 = torch.from_numpy(X0).cuda()
-    del X0
+    if cfg.name not in ("C1", "C2"):
+        del X0  # large cells: the host copy is not needed again
     if mixed:
         v, x0 = v.float(), x0.to(torch.complex64)
     lob = b.Lobpcg(plan, v, x0)
@@ -289,7 +290,8 @@ def main():
         log(f"[bench] time to 1e-6 Ha: {tta}")
 
     cpu = None
-    if not args.no_cpu_baseline and not mixed:
+    # the oracle step is timed on the FP64 workloads small enough for it
+    if not args.no_cpu_baseline and not mixed and cfg.name in ("C1", "C2"):
         from oracle import hamiltonian as oh
         from oracle import lobpcg as olob
 
