@@ -387,28 +387,42 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
   const int vi = threadIdx.x >> 4, vr = (threadIdx.x & 15) * 4;  // V: column vi, rows vr..vr+3
   const int cb = threadIdx.x >> 2, ci = (threadIdx.x & 3) * 4;   // C: band cb, i ci..ci+3
   const int npass = Yp ? 2 : 1;
+  // register stage of the next chunk (its loads overlap this chunk's MFMAs);
+  // eight named values rather than arrays, which stay in registers
+  T2 v0, v1, v2, v3, q0, q1, q2, q3;
+  const int band_l = b0 + cb;
+  const bool band_ok = band_l < ncol;
+  const int64_t rr = r0 + vr;
+#define KS_ROT_FETCH(C0)                                                                    \
+  do {                                                                                      \
+    const int c_ = (C0) + vi;                                                               \
+    const T2* col_ = (c_ < hi) ? seg_col(V, c_) : nullptr;                                  \
+    v0 = (col_ && rr + 0 < Ng) ? col_[rr + 0] : z;                                          \
+    v1 = (col_ && rr + 1 < Ng) ? col_[rr + 1] : z;                                          \
+    v2 = (col_ && rr + 2 < Ng) ? col_[rr + 2] : z;                                          \
+    v3 = (col_ && rr + 3 < Ng) ? col_[rr + 3] : z;                                          \
+    const int i_ = (C0) + ci;                                                               \
+    const T2* cc_ = C + (int64_t)band_l * ldc;                                              \
+    q0 = (band_ok && i_ + 0 < hi) ? cc_[i_ + 0] : z;                                        \
+    q1 = (band_ok && i_ + 1 < hi) ? cc_[i_ + 1] : z;                                        \
+    q2 = (band_ok && i_ + 2 < hi) ? cc_[i_ + 2] : z;                                        \
+    q3 = (band_ok && i_ + 3 < hi) ? cc_[i_ + 3] : z;                                        \
+  } while (0)
   for (int pass = 0; pass < npass; ++pass) {
     const int lo = (Yp && pass == 0) ? pstart : 0;
     const int hi = (Yp && pass == 0) ? m : (Yp ? pstart : m);
+    if (lo < hi) KS_ROT_FETCH(lo);
     for (int c0 = lo; c0 < hi; c0 += KC) {
-      {
-        const int c = c0 + vi;
-        const T2* col = (c < hi) ? seg_col(V, c) : nullptr;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t r = r0 + vr + q;
-          Vs[vi][vr + q] = (col && r < Ng) ? col[r] : z;
-        }
-      }
-      {
-        const int band = b0 + cb;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = c0 + ci + q;
-          Cs[cb][ci + q] = (band < ncol && i < hi) ? C[i + (int64_t)band * ldc] : z;
-        }
-      }
+      Vs[vi][vr + 0] = v0;
+      Vs[vi][vr + 1] = v1;
+      Vs[vi][vr + 2] = v2;
+      Vs[vi][vr + 3] = v3;
+      Cs[cb][ci + 0] = q0;
+      Cs[cb][ci + 1] = q1;
+      Cs[cb][ci + 2] = q2;
+      Cs[cb][ci + 3] = q3;
       __syncthreads();
+      if (c0 + KC < hi) KS_ROT_FETCH(c0 + KC);
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -444,6 +458,8 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
         }
   }
 }
+
+#undef KS_ROT_FETCH
 
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng,
