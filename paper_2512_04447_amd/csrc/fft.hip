@@ -259,12 +259,72 @@ __device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, 
   }
 }
 
+// ---------------------------------------------------------------- fixed sizes
+// The same Stockham stage with every size a compile-time constant (length N,
+// NBATCH transforms, element and batch strides ES and BS, previous radix
+// product NS, NT threads): the index arithmetic folds to shifts and constant
+// multiplies and the work per thread is exact.  Used for cubic grids of
+// 16, 48, 96 and 112 points per axis (the benchmarked cells); other grids
+// take the run-time path above.
+template <int R, int N, int NBATCH, int ES, int BS, int NS, int NT, bool PAD, typename T2>
+__device__ inline void stockham_stage_ct(T2* s, const T2* __restrict__ tw) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NBATCH * NBF;
+  constexpr int NIT = (TOTAL + NT - 1) / NT;
+  constexpr int TSTEP = N / (NS * R);
+  constexpr bool BFAST = BS < ES;
+  T2 v[NIT][R];
+  int dst[NIT];
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int w = (int)threadIdx.x + u * NT;
+    dst[u] = -1;
+    if (TOTAL % NT == 0 || w < TOTAL) {
+      const int b = BFAST ? w % NBATCH : w / NBF;
+      const int j = BFAST ? w / NBATCH : w - b * NBF;
+      const int k = j % NS;
+      const int base = b * BS;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        T2 a = s[lpad<PAD>(base + (j + q * NBF) * ES)];
+        if (q > 0 && NS > 1 && k > 0) a = cmul(a, tw[q * k * TSTEP]);
+        v[u][q] = a;
+      }
+      Dft<R, T2>::run(v[u]);
+      dst[u] = b * BS + ((j / NS) * NS * R + k) * ES;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    if (TOTAL % NT == 0 || dst[u] >= 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) s[lpad<PAD>(dst[u] + q * NS * ES)] = v[u][q];
+    }
+  }
+  __syncthreads();
+}
+
+// radix pairs of the fixed sizes: N = R1 * R2 (R2 = 1: a single stage)
+template <int N> struct CtRad;
+template <> struct CtRad<16> { static constexpr int R1 = 16, R2 = 1; };
+template <> struct CtRad<48> { static constexpr int R1 = 16, R2 = 3; };
+template <> struct CtRad<96> { static constexpr int R1 = 16, R2 = 6; };
+template <> struct CtRad<112> { static constexpr int R1 = 16, R2 = 7; };
+
+template <int N, int NBATCH, int ES, int BS, int NT, bool PAD, typename T2>
+__device__ inline void fft_ct(T2* s, const T2* __restrict__ tw) {
+  constexpr int R1 = CtRad<N>::R1, R2 = CtRad<N>::R2;
+  stockham_stage_ct<R1, N, NBATCH, ES, BS, 1, NT, PAD>(s, tw);
+  if constexpr (R2 > 1) stockham_stage_ct<R2, N, NBATCH, ES, BS, R1, NT, PAD>(s, tw);
+}
+
 __device__ inline int wrap_m(int k, int n) { return (2 * k < n) ? k : k - n; }
 
 // ---------------------------------------------------------------- pass A
 // MODE 0: load psi.  MODE 1: load r = ax - theta x and write per-plane
 // partial sums of |r|^2 to partial[band*n0 + x].
-template <typename T, int MAXE, int MODE, int NT>
+template <typename T, int MAXE, int MODE, int NT, int CN = 0>
 __global__ void __launch_bounds__(NT)
 k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
          const double* __restrict__ theta, int64_t ld, c2<T>* __restrict__ dst, int64_t ldd,
@@ -299,8 +359,13 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
     for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = in[i];
   }
   __syncthreads();
-  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
-  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
+  if constexpr (CN > 0) {
+    fft_ct<CN, CN, 1, CN, NT, true>(s, st2);  // z rows
+    fft_ct<CN, CN, CN, 1, NT, true>(s, st1);  // y columns
+  } else {
+    fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
+    fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
+  }
   T2* out = dst + band * ldd + off;
   for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = s[lpad(i)];
   if (MODE == 1) {
@@ -325,7 +390,7 @@ template <typename T> __device__ inline T tpa_factor(T x) {
   return num / (num + T(16) * x * x * x * x);
 }
 
-template <typename T, int MAXE, int MODE>
+template <typename T, int MAXE, int MODE, int CN = 0, int CZC = 0>
 __global__ void __launch_bounds__(kThreads)
 k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __restrict__ tw0,
          const double* __restrict__ E, double* __restrict__ partial) {
@@ -350,7 +415,10 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
     s[i] = base[x * xs + z];
   }
   __syncthreads();
-  fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
+  if constexpr (CN > 0)
+    fft_ct<CN, CZC, CZC, 1, kThreads, false>(s, st0);
+  else
+    fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
   if (MODE == 2) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < tile; i += blockDim.x) {
@@ -372,7 +440,10 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
     s[i] = cmake<T2>(v.x * fac, -v.y * fac);  // conj for the inverse transform
   }
   __syncthreads();
-  fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
+  if constexpr (CN > 0)
+    fft_ct<CN, CZC, CZC, 1, kThreads, false>(s, st0);
+  else
+    fft_batch<MAXE, false>(s, zc, f.ax[0], zc, 1, st0);
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int x = i / zc, z = i - x * zc;
     T2 v = s[i];
@@ -385,7 +456,7 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
 // conj(FFT(conj(.))) / Ng.
 // MODE 0 (H): out = Tpsi + V psi.
 // MODE 1 (preconditioner): out = mask[band] * IFFT(.), mask from res > lock_tol.
-template <typename T, int MAXE, int MODE, int NT>
+template <typename T, int MAXE, int MODE, int NT, int CN = 0>
 __global__ void __launch_bounds__(NT)
 k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict__ dst, int64_t ldd,
          const c2<T>* __restrict__ tw1, const c2<T>* __restrict__ tw2, const T* __restrict__ V,
@@ -405,8 +476,13 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
   for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = cconj(in[i]);
   __syncthreads();
-  fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
-  fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
+  if constexpr (CN > 0) {
+    fft_ct<CN, CN, CN, 1, NT, true>(s, st1);  // y columns
+    fft_ct<CN, CN, 1, CN, NT, true>(s, st2);  // z rows
+  } else {
+    fft_batch<MAXE>(s, n2, f.ax[1], n2, 1, st1);  // y columns
+    fft_batch<MAXE>(s, n1, f.ax[2], 1, n2, st2);  // z rows
+  }
   const T scale = T(1.0 / ((double)n0 * (double)n1 * (double)n2));
   T2* out = dst + band * ldd + off;
   if (MODE == 0) {
@@ -575,7 +651,7 @@ __global__ void k_row_sum(const double* __restrict__ partial, int cnt, int nb, d
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename T, int MAXE, int NT>
+template <typename T, int MAXE, int NT, int CN = 0>
 static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2,
                           const double* theta, int64_t ld, c2<T>* dst, int64_t ldd, int nb,
                           double* partial, hipStream_t s) {
@@ -584,18 +660,37 @@ static int launch_plane_a(const ks_plan& p, int mode, const c2<T>* src, const c2
   dim3 grid(nb * p.fft.ax[0].n);
   TimerScope ts(KF_PASS_A, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_pass_a<T, MAXE, 0, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 0, NT, CN>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
                        theta, ld, dst, ldd, tw1, tw2, partial);
   else
-    hipLaunchKernelGGL((k_pass_a<T, MAXE, 1, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
+    hipLaunchKernelGGL((k_pass_a<T, MAXE, 1, NT, CN>), grid, dim3(NT), p.lds_plane, s, p.fft, src, src2,
                        theta, ld, dst, ldd, tw1, tw2, partial);
   KS_LAUNCH_CHECK("pass A");
+  return 0;
+}
+
+// Fixed-size path: cubic grids of 16, 48, 96 or 112 points per axis whose
+// plan chose the block shapes the compile-time kernels assume (else 0).
+static int fixed_n(const ks_plan& p) {
+  const int n = p.fft.ax[0].n;
+  if (p.fft.ax[1].n != n || p.fft.ax[2].n != n) return 0;
+  if (n == 16 && p.plane_threads == kThreads && p.maxe_plane == 4 && p.zc == 16) return 16;
+  if (n == 48 && p.plane_threads == kThreads && p.maxe_plane == 16 && p.zc == 48) return 48;
+  if (n == 96 && p.plane_threads == 1024 && p.maxe_plane == 12 && p.zc == 32) return 96;
+  if (n == 112 && p.plane_threads == 1024 && p.maxe_plane == 16 && p.zc == 28) return 112;
   return 0;
 }
 
 template <typename T>
 static int pass_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2, const double* theta,
                   int64_t ld, c2<T>* dst, int64_t ldd, int nb, double* partial, hipStream_t s) {
+  switch (fixed_n(p)) {
+    case 16: return launch_plane_a<T, 4, kThreads, 16>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 48: return launch_plane_a<T, 16, kThreads, 48>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 96: return launch_plane_a<T, 12, 1024, 96>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    case 112: return launch_plane_a<T, 16, 1024, 112>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
+    default: break;
+  }
   if (p.plane_threads == 1024) {
     if (p.maxe_plane == 12) return launch_plane_a<T, 12, 1024>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
     if (p.maxe_plane == 16) return launch_plane_a<T, 16, 1024>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
@@ -610,7 +705,7 @@ static int pass_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src
   }
 }
 
-template <typename T, int MAXE, int NT>
+template <typename T, int MAXE, int NT, int CN = 0>
 static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst,
                           int64_t ldd, int nb, const T* V, const c2<T>* psi, int64_t ldp,
                           const c2<T>* dc, const double* res, double lock_tol, hipStream_t s) {
@@ -619,10 +714,10 @@ static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t 
   dim3 grid(nb * p.fft.ax[0].n);
   TimerScope ts(KF_PASS_C, s);
   if (mode == 0)
-    hipLaunchKernelGGL((k_pass_c<T, MAXE, 0, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 0, NT, CN>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
                        dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   else
-    hipLaunchKernelGGL((k_pass_c<T, MAXE, 1, NT>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
+    hipLaunchKernelGGL((k_pass_c<T, MAXE, 1, NT, CN>), grid, dim3(NT), p.lds_plane, s, p.fft, src, lds_,
                        dst, ldd, tw1, tw2, V, psi, ldp, res, lock_tol);
   KS_LAUNCH_CHECK("pass C");
   return 0;
@@ -632,6 +727,13 @@ template <typename T>
 static int pass_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst, int64_t ldd,
                   int nb, const T* V, const c2<T>* psi, int64_t ldp, const c2<T>* dc,
                   const double* res, double lock_tol, hipStream_t s) {
+  switch (fixed_n(p)) {
+    case 16: return launch_plane_c<T, 4, kThreads, 16>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 48: return launch_plane_c<T, 16, kThreads, 48>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 96: return launch_plane_c<T, 12, 1024, 96>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    case 112: return launch_plane_c<T, 16, 1024, 112>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
+    default: break;
+  }
   if (p.plane_threads == 1024) {
     if (p.maxe_plane == 12)
       return launch_plane_c<T, 12, 1024>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
@@ -648,6 +750,25 @@ static int pass_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2
   }
 }
 
+template <typename T, int CN, int CZC>
+static void launch_pencil(const ks_plan& p, int mode, dim3 grid, c2<T>* buf, int64_t ld, const c2<T>* tw0,
+                          const double* E, double* partial, hipStream_t s) {
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 0, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 1, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 2, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
+  }
+}
+
 template <typename T>
 static int pass_b(const ks_plan& p, int mode, c2<T>* buf, int64_t ld, int nb, const double* E,
                   double* partial, hipStream_t s) {
@@ -656,19 +777,12 @@ static int pass_b(const ks_plan& p, int mode, c2<T>* buf, int64_t ld, int nb, co
   dim3 grid(nb * n1 * (n2 / p.zc));
   TimerScope ts(KF_PASS_B, s);
   if (p.maxe_pencil != 16) return fail(KS_E_UNSUPPORTED, "pencil tile size");
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((k_pass_b<T, 16, 0>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
-                         tw0, E, partial);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_pass_b<T, 16, 1>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
-                         tw0, E, partial);
-      break;
-    default:
-      hipLaunchKernelGGL((k_pass_b<T, 16, 2>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
-                         tw0, E, partial);
-      break;
+  switch (fixed_n(p)) {
+    case 16: launch_pencil<T, 16, 16>(p, mode, grid, buf, ld, tw0, E, partial, s); break;
+    case 48: launch_pencil<T, 48, 48>(p, mode, grid, buf, ld, tw0, E, partial, s); break;
+    case 96: launch_pencil<T, 96, 32>(p, mode, grid, buf, ld, tw0, E, partial, s); break;
+    case 112: launch_pencil<T, 112, 28>(p, mode, grid, buf, ld, tw0, E, partial, s); break;
+    default: launch_pencil<T, 0, 0>(p, mode, grid, buf, ld, tw0, E, partial, s); break;
   }
   KS_LAUNCH_CHECK("pass B");
   return 0;
