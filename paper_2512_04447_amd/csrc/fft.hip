@@ -399,6 +399,8 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   T2* s = reinterpret_cast<T2*>(smem_raw);
   __shared__ double red[kThreads / kWave];
   const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  // fixed-size path: the z-chunk width is a compile-time constant
+  if constexpr (CZC > 0) zc = CZC;
   const int nzc = n2 / zc;
   int bid = blockIdx.x;
   const int zt = bid % nzc; bid /= nzc;
