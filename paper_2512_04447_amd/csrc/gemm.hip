@@ -290,27 +290,66 @@ k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, 
   }
 }
 
-GramShape gram_shape(int m, int64_t K, bool full) {
+// K splits: each workgroup sums one tile over one K range into FP64
+// partials, reduced afterwards.  The split count makes the number of
+// workgroups fill whole rounds of the device's resident slots (workgroups
+// are of equal length, so a last round that is nearly empty costs as much
+// as a full one): the count minimises rounds / splits, a smaller count
+// winning ties within 2%, with at least 512 points per split and partials
+// under GRAM_PART_BYTES.
+constexpr int64_t GRAM_PART_BYTES = 1ll << 30;
+
+GramShape gram_shape(int ntile, int64_t K, bool full, int slots) {
   GramShape g;
-  g.ntile = (int)ceil_div(m, TILE);
-  g.ntu = full ? g.ntile * g.ntile : g.ntile * (g.ntile + 1) / 2;
-  int64_t ns = ceil_div(1024, g.ntu);
-  const int64_t kmax_split = std::max<int64_t>(1, K / 512);
-  ns = std::min<int64_t>(ns, kmax_split);
-  // keep partials (two matrices) under 256 MB
-  const int64_t cap = std::max<int64_t>(1, (int64_t)(256ll << 20) / ((int64_t)g.ntu * TILE * TILE * 16 * 2));
-  ns = std::max<int64_t>(1, std::min(ns, cap));
-  g.kper = ceil_div(ceil_div(K, ns), 32) * 32;  // a multiple of either Gram chunk
+  g.ntile = ntile;
+  g.ntu = full ? ntile * ntile : ntile * (ntile + 1) / 2;
+  if (slots <= 0) slots = 1024;
+  const int64_t ns_k = std::max<int64_t>(1, K / 512);
+  const int64_t ns_mem = std::max<int64_t>(1, GRAM_PART_BYTES / ((int64_t)g.ntu * TILE * TILE * 16 * 2));
+  const int64_t nsmax = std::min<int64_t>(std::min(ns_k, ns_mem), 4096);
+  int64_t best = 1;
+  double bestc = 1e300;
+  for (int64_t ns = 1; ns <= nsmax; ++ns) {
+    const double rounds = (double)ceil_div((int64_t)g.ntu * ns, slots);
+    const double cost = rounds / (double)ns;
+    if (cost < 0.98 * bestc) {
+      bestc = cost;
+      best = ns;
+    }
+  }
+  g.kper = ceil_div(ceil_div(K, best), 32) * 32;  // a multiple of either Gram chunk
   g.nsplit = (int)ceil_div(K, g.kper);
   return g;
 }
 
-size_t gram_work_bytes(int m, int64_t K) {
-  size_t mx = 0;
-  for (int f = 0; f < 2; ++f) {
-    GramShape g = gram_shape(m, K, f == 1);
-    mx = std::max(mx, (size_t)g.nsplit * g.ntu * TILE * TILE * sizeof(double2) * 2);
+// Resident workgroups of one Gram kernel on the current device.
+template <typename T, bool TWO> static int gram_slots() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] > 0) return cache[dev];
+  int per = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_gram<T, TWO>),
+                                                   gram_threads<T>(), 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
   }
+  cache[dev] = std::max(1, per) * std::max(1, cus);
+  return cache[dev];
+}
+
+size_t gram_work_bytes(int m, int64_t K) {
+  const int slots[4] = {gram_slots<double, true>(), gram_slots<double, false>(), gram_slots<float, true>(),
+                        gram_slots<float, false>()};
+  size_t mx = 0;
+  const int nt = (int)ceil_div(std::max(m, 1), TILE);
+  for (int t = 1; t <= nt; ++t)
+    for (int f = 0; f < 2; ++f)
+      for (int v = 0; v < 4; ++v) {
+        const GramShape g = gram_shape(t, K, f == 1, slots[v]);
+        mx = std::max(mx, (size_t)g.nsplit * g.ntu * TILE * TILE * sizeof(double2) * 2);
+      }
   return mx;
 }
 
@@ -318,7 +357,7 @@ template <typename T>
 static int gram_impl(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B1, const BlockList<c2<T>>* B2, int m,
                      int64_t K, bool full, double2* S, int lds_, double2* H, int ldh, void* work, hipStream_t s) {
   if (m <= 0) return 0;
-  GramShape g = gram_shape(m, K, full);
+  const GramShape g = gram_shape((int)ceil_div(m, TILE), K, full, B2 ? gram_slots<T, true>() : gram_slots<T, false>());
   double2* partS = static_cast<double2*>(work);
   double2* partH = partS + (size_t)g.nsplit * g.ntu * TILE * TILE;
   dim3 grid(g.ntu, g.nsplit);

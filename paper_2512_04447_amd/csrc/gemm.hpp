@@ -20,7 +20,10 @@ struct GramShape {
   int ntile, ntu, nsplit;
   int64_t kper;
 };
-GramShape gram_shape(int m, int64_t K, bool full);
+// Launch shape for ntile x ntile tiles (upper triangle unless full) on a
+// device with `slots` resident Gram workgroups.
+GramShape gram_shape(int ntile, int64_t K, bool full, int slots);
+// Partial-sum workspace for every Gram of at most m columns.
 size_t gram_work_bytes(int m, int64_t K);
 
 // S = A^H B1 (and H = A^H B2 when B2 != null) for the first m columns of the
