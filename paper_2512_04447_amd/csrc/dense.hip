@@ -422,6 +422,314 @@ __global__ void k_tridiag_tail(const double2* __restrict__ K, int ldk, int n, do
   }
 }
 
+// ---------------------------------------------------------------- resident tridiagonalisation
+// Steps k0..n-2 of the same reduction in one cooperative launch.  The
+// trailing columns k0+1..n-1 are dealt cyclically to the G workgroups and
+// stay in LDS for the whole reduction: workgroup b owns the columns
+// j = k0+1 + b + q G (q < c), rows k0+1..n-1.  Step k's rank-2 update is
+// not applied in step k; step k+1 applies it to each owned column just
+// before that column's product with v_{k+1}, so one grid barrier per step
+// suffices.  Phase k:
+//  1. scalars of the pending update (step k-1): s = Re(v^H y) and
+//     w = tau y - |tau|^2 s v / 2, computed by every workgroup from the same
+//     data in the same order (identical in all of them);
+//  2. column k of the updated matrix: its owner published it in phase k-1
+//     (before the update of step k-1); the update is applied on the fly;
+//  3. beta, tau_k and v_k from it, with the formulas of k_house_hemv;
+//  4. every owned column j > k: pending update (rows > k), then
+//     y_j = sum_i conj(A[i][j]) v_k[i]; the owner of column k+1 publishes it;
+//  5. grid barrier.
+// Workgroup 0 stores d, e, tau and (one phase later) v_k in column k of K,
+// where the back-transform expects it.  Published vectors alternate
+// between two buffers by the parity of k.
+constexpr int TRI_THREADS = 256;
+constexpr int TRI_RMAX = 8;  // rows per thread: trailing size <= 2048
+constexpr int TRI_CMAX = 8;  // columns per workgroup
+constexpr unsigned TRI_SPIN_LIMIT = 1u << 21;
+
+// Grid barrier of a cooperative launch.  Arrivals count in two levels:
+// workgroup b adds to the counter of its group b % TRI_GROUPS, and the last
+// arrival of a group adds to the top counter; everyone waits for the top
+// counter to reach (phase) * (number of groups).  All counters only grow
+// (zeroed before the launch), so `phase` (1, 2, ...) names the wait.  The
+// wait is bounded: after TRI_SPIN_LIMIT polls (well over a second) it raises
+// the failure flag, and every later wait sees the flag and returns, so every
+// wave reaches the end.  Layout: bar[0] top, bar[1] flag, group g's counter
+// at bar[64 (g + 1)] (256 bytes apart).
+constexpr int TRI_GROUPS = 8;
+constexpr int TRI_BAR_WORDS = 64 * (TRI_GROUPS + 1);
+
+__device__ bool tri_grid_barrier(unsigned* bar, unsigned phase) {
+  __shared__ int ok_s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned G = gridDim.x, g = blockIdx.x % TRI_GROUPS;
+    const unsigned ng = G < (unsigned)TRI_GROUPS ? G : (unsigned)TRI_GROUPS;
+    const unsigned gsize = (G - g + TRI_GROUPS - 1) / TRI_GROUPS;
+    int* fail = reinterpret_cast<int*>(bar + 1);
+    __threadfence();
+    const unsigned old =
+        __hip_atomic_fetch_add(bar + 64 * (g + 1), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == phase * gsize) {
+      __threadfence();
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    const unsigned target = phase * ng;
+    for (unsigned spins = 0;; ++spins) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (spins >= TRI_SPIN_LIMIT || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// relaxed agent-scope load: never served by a cache that another
+// workgroup's writes bypassed
+__device__ inline double2 load_agent(const double2* p) {
+  double* q = reinterpret_cast<double*>(const_cast<double2*>(p));
+  return make_double2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ inline double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a conj(b)
+__device__ inline double2 zmulc2(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// bar: TRI_BAR_WORDS words, zero at launch.  On a barrier failure *info
+// is set to -1.  Dynamic LDS: c m double2,
+// m = n - k0 - 1.
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tridiag_resident(double2* __restrict__ K, int ldk, int n, int k0, int c, double2* __restrict__ tau,
+                   double* __restrict__ d, double* __restrict__ e, double2* __restrict__ ybuf,
+                   double2* __restrict__ xbuf, unsigned* __restrict__ bar, int32_t* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char tri_raw[];
+  double2* Aq = reinterpret_cast<double2*>(tri_raw);  // column q at Aq + q m
+  __shared__ double red_s[TRI_THREADS / 64], red_n[TRI_THREADS / 64];
+  __shared__ double2 red_y[TRI_CMAX][TRI_THREADS / 64];
+  __shared__ double2 alpha_s, yk_s, xk_s, wq_s[TRI_CMAX], vq_s[TRI_CMAX];
+  const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wid = t >> 6;
+  const int m = n - k0 - 1;
+  const int base = k0 + 1;  // global index of local row / column 0
+  const double2 zero = make_double2(0.0, 0.0);
+  for (int q = 0; q < c; ++q) {
+    const int jr = b + q * G;
+    if (jr >= m) break;
+    const double2* src = K + base + (int64_t)(base + jr) * ldk;
+    // thread t owns rows t + 256 u: only it reads them back, no barrier needed
+    for (int r = t; r < m; r += TRI_THREADS) Aq[q * m + r] = src[r];
+  }
+  double2 vp[TRI_RMAX];  // v of the pending step (zero above its head)
+#pragma unroll
+  for (int u = 0; u < TRI_RMAX; ++u) vp[u] = zero;
+  double2 tp = zero;  // tau of the pending step
+  for (int k = k0; k < n - 1; ++k) {
+    const int a = k - k0;  // local index of row k+1
+    const bool pend = k > k0;
+    const int pin = (k - 1) & 1, pout = k & 1;
+    // 1. loads: y of the pending step (rows >= k) and column k (rows > k)
+    // (row k is local row a-1; its values reach the other threads through
+    // LDS, written by the thread that owns the row)
+    double2 y[TRI_RMAX], x[TRI_RMAX];
+    if (pend) {
+      const double2* yb = ybuf + (int64_t)pin * n + base;
+      const double2* xb = xbuf + (int64_t)pout * n + base;
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) {
+        const int r = t + TRI_THREADS * u;
+        y[u] = (r >= a - 1 && r < m) ? yb[r] : zero;
+        x[u] = (r >= a && r < m) ? xb[r] : zero;
+        if (r == a - 1) {
+          yk_s = y[u];
+          xk_s = xb[r];
+        }
+      }
+    } else {
+      const double2* col = K + (int64_t)k * ldk;
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) {
+        const int r = t + TRI_THREADS * u;
+        y[u] = zero;
+        x[u] = (r >= a && r < m) ? col[base + r] : zero;
+      }
+      if (t == 0) xk_s = col[k];
+    }
+    // 2. the pending update: w = tau y - (1/2)|tau|^2 s v, s = Re(v^H y)
+    double2 w[TRI_RMAX];
+    double2 wk = zero;
+    if (pend) {
+      double sp = 0.0;
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) sp += vp[u].x * y[u].x + vp[u].y * y[u].y;
+      sp = wave_sum(sp);
+      if (lane == 0) red_s[wid] = sp;
+      __syncthreads();
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < TRI_THREADS / 64; ++i) s += red_s[i];
+      const double c0 = -0.5 * (tp.x * tp.x + tp.y * tp.y) * s;
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) {
+        const double2 ty = zmul(tp, y[u]);
+        w[u] = make_double2(ty.x + c0 * vp[u].x, ty.y + c0 * vp[u].y);
+      }
+      // v of the pending step is exactly 1 at its head, row k
+      const double2 ty = zmul(tp, yk_s);
+      wk = make_double2(ty.x + c0, ty.y);
+    } else {
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) w[u] = zero;
+    }
+    // 3. column k after the pending update: x_i - w_i - v_i conj(w_k), then
+    //    the reflector of step k
+    double sn = 0.0;
+#pragma unroll
+    for (int u = 0; u < TRI_RMAX; ++u) {
+      const int r = t + TRI_THREADS * u;
+      if (r >= a && r < m) {
+        const double2 vw = zmulc2(vp[u], wk);
+        x[u] = make_double2(x[u].x - w[u].x - vw.x, x[u].y - w[u].y - vw.y);
+        if (r == a) alpha_s = x[u];
+        else sn += x[u].x * x[u].x + x[u].y * x[u].y;
+      }
+      // the pending update's values at the rows of owned columns
+      if (pend && r >= a && r < m && r >= b && (r - b) % G == 0) {
+        const int q = (r - b) / G;
+        wq_s[q] = w[u];
+        vq_s[q] = vp[u];
+      }
+    }
+    sn = wave_sum(sn);
+    if (lane == 0) red_n[wid] = sn;
+    __syncthreads();
+    sn = 0.0;
+#pragma unroll
+    for (int i = 0; i < TRI_THREADS / 64; ++i) sn += red_n[i];
+    const double2 alpha = alpha_s;
+    const double dk = xk_s.x - 2.0 * wk.x;  // Re A[k][k] after the pending update
+    double2 tn, scale;
+    double beta;
+    if (sn == 0.0 && alpha.y == 0.0) {
+      tn = zero;
+      beta = alpha.x;
+      scale = zero;
+    } else {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sn);
+      beta = alpha.x >= 0.0 ? -nrm : nrm;
+      tn = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      const double ar = alpha.x - beta, ai = alpha.y;
+      const double den = ar * ar + ai * ai;
+      scale = make_double2(ar / den, -ai / den);
+    }
+    double2 vn[TRI_RMAX];
+#pragma unroll
+    for (int u = 0; u < TRI_RMAX; ++u) {
+      const int r = t + TRI_THREADS * u;
+      vn[u] = r == a ? make_double2(1.0, 0.0) : (r > a && r < m) ? zmul(x[u], scale) : zero;
+    }
+    if (b == 0) {
+      if (t == 0) {
+        tau[k] = tn;
+        d[k] = dk;
+        e[k] = beta;
+      }
+      // v of the pending step into column k-1 of K (rows >= k); every
+      // workgroup read that column before the previous barrier
+      if (pend) {
+        double2* vcol = K + base + (int64_t)(k - 1) * ldk;
+#pragma unroll
+        for (int u = 0; u < TRI_RMAX; ++u) {
+          const int r = t + TRI_THREADS * u;
+          if (r >= a - 1 && r < m) vcol[r] = vp[u];
+        }
+      }
+    }
+    // 4. owned columns j > k: pending update, then the product with v_k
+    double2 acc[TRI_CMAX];
+#pragma unroll
+    for (int q = 0; q < TRI_CMAX; ++q) {
+      acc[q] = zero;
+      const int jr = b + q * G;
+      if (q >= c || jr < a || jr >= m) continue;
+      const double2 wj = pend ? wq_s[q] : zero, vj = pend ? vq_s[q] : zero;
+      double2* col = Aq + q * m;
+      double2* pub = xbuf + (int64_t)((k + 1) & 1) * n + base;
+#pragma unroll
+      for (int u = 0; u < TRI_RMAX; ++u) {
+        const int r = t + TRI_THREADS * u;
+        if (r >= a && r < m) {
+          double2 A = col[r];
+          if (pend) {
+            const double2 p1 = zmulc2(w[u], vj), p2 = zmulc2(vp[u], wj);
+            A = make_double2(A.x - p1.x - p2.x, A.y - p1.y - p2.y);
+            col[r] = A;
+          }
+          if (jr == a) pub[r] = A;
+          // conj(A) v
+          acc[q].x += A.x * vn[u].x + A.y * vn[u].y;
+          acc[q].y += A.x * vn[u].y - A.y * vn[u].x;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TRI_CMAX; ++q) {
+      if (q >= c) break;
+      const double ax = wave_sum(acc[q].x), ay = wave_sum(acc[q].y);
+      if (lane == 0) red_y[q][wid] = make_double2(ax, ay);
+    }
+    __syncthreads();
+    if (t < c) {
+      const int jr = b + t * G;
+      if (jr >= a && jr < m) {
+        double2 sy = zero;
+#pragma unroll
+        for (int i = 0; i < TRI_THREADS / 64; ++i) {
+          sy.x += red_y[t][i].x;
+          sy.y += red_y[t][i].y;
+        }
+        ybuf[(int64_t)pout * n + base + jr] = sy;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TRI_RMAX; ++u) vp[u] = vn[u];
+    tp = tn;
+    // 5. all of step k published
+    if (!tri_grid_barrier(bar, (unsigned)(a + 1))) {
+      if (t == 0) info[0] = -1;
+      return;
+    }
+  }
+  // the last diagonal entry after the update of step n-2 (v = 1 at row n-1)
+  if (b == 0 && t == 0) {
+    const int p = (n - 2) & 1;
+    const double2 yl = load_agent(ybuf + (int64_t)p * n + (n - 1));
+    const double2 xl = load_agent(xbuf + (int64_t)((n - 1) & 1) * n + (n - 1));
+    const double c0 = -0.5 * (tp.x * tp.x + tp.y * tp.y) * yl.x;
+    const double2 ty = zmul(tp, yl);
+    d[n - 1] = xl.x - 2.0 * (ty.x + c0);
+    e[n - 1] = 0.0;
+    tau[n - 1] = zero;
+    K[(n - 1) + (int64_t)(n - 2) * ldk] = make_double2(1.0, 0.0);
+  }
+}
+
+__global__ void k_tri_reset(unsigned* bar) {
+  for (int i = threadIdx.x; i < TRI_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
+}
+
 // ---------------------------------------------------------------- bisection
 __device__ inline double pivmin_of(const double* e, int n) {
   double m = 1.0;
@@ -722,6 +1030,9 @@ struct HegvWs {
   int32_t* ncl;
   double* Z;
   double2* tmp;
+  double2* ybuf;  // 2 n: products published by the resident tridiagonalisation
+  double2* xbuf;  // 2 n: columns published by it
+  unsigned* bar;  // its grid-barrier counters
 };
 
 static HegvWs hegv_ws(void* work, int n, int nev) {
@@ -739,12 +1050,59 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   w.ncl = reinterpret_cast<int32_t*>(p); p += 256;
   w.Z = reinterpret_cast<double*>(p); p += al((size_t)n * nev * 8);
   w.tmp = reinterpret_cast<double2*>(p); p += al((size_t)NB * n * sizeof(double2));
+  w.ybuf = reinterpret_cast<double2*>(p); p += al((size_t)2 * n * sizeof(double2));
+  w.xbuf = reinterpret_cast<double2*>(p); p += al((size_t)2 * n * sizeof(double2));
+  w.bar = reinterpret_cast<unsigned*>(p); p += al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
   return w;
 }
 
 size_t hegv_work(int n, int nev) {
   return al(potrf_work(n)) + al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
-         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16);
+         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16) +
+         2 * al((size_t)2 * n * 16) + al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
+}
+
+// Launch shape of the resident tridiagonalisation: it takes the last m
+// steps, m as large as the LDS of the device's compute units holds
+// (c m double2 per workgroup, at most one workgroup per CU), aiming at
+// TRI_CTARGET columns per workgroup; steps before n-1-m run one column per
+// launch.  A step of the resident kernel costs about as much as the two
+// launches of a step below n = TRI_MIN_N (grid barrier and the round trips
+// of the published vectors; measured on MI355X: slower at n = 480, 11%
+// faster at n = 1440), so smaller problems keep one column per launch.
+// k0 < 0: not used.
+struct TriPlan {
+  int k0 = -1, G = 0, c = 0;
+  size_t lds = 0;
+};
+constexpr int TRI_CTARGET = 8;
+constexpr int TRI_MIN_N = 1024;
+
+static TriPlan tri_plan(int n) {
+  TriPlan p;
+  if (n < TRI_MIN_N) return p;
+  int dev = 0, cus = 0, lds = 0, coop = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return p;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess)
+    return p;
+  if (!coop || cus <= 0 || lds <= 4096) return p;
+  const size_t budget = (size_t)lds - 4096;  // static LDS of the kernel stays below 4 KB
+  for (int m = std::min(n - 1, TRI_THREADS * TRI_RMAX); m >= 1; --m) {
+    const int cfit = (int)std::min<size_t>(TRI_CMAX, budget / ((size_t)m * sizeof(double2)));
+    if (cfit < 1) continue;
+    int G = (int)ceil_div(m, std::min(cfit, TRI_CTARGET));
+    if (G > cus) G = cus;
+    const int c = (int)ceil_div(m, G);
+    if (c > cfit) continue;
+    p.k0 = n - 1 - m;
+    p.G = G;
+    p.c = c;
+    p.lds = (size_t)c * m * sizeof(double2);
+    return p;
+  }
+  return p;
 }
 
 int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, double2* C, int ldc, void* work,
@@ -763,16 +1121,49 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   hipLaunchKernelGGL(k_hermitise, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)), dim3(256),
                      0, s, ws.K, n, n);
   KS_LAUNCH_CHECK("hermitise");
-  // Householder tridiagonalisation, one column per step
-  for (int k = 0; k + 1 < n; ++k) {
-    const int len = n - k - 1;
-    hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau, ws.d,
-                       ws.e, ws.v, ws.y);
-    hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
-                       ws.K, n, n, k, ws.y, ws.tau, ws.v);
-  }
+  // Householder tridiagonalisation: one column per launch while the
+  // trailing matrix is larger than the LDS of the device holds, then the
+  // resident kernel for the remaining steps
+  const TriPlan tp = tri_plan(n);
+  const int kres = tp.k0 >= 0 ? tp.k0 : n - 1;
+  auto column_steps = [&](int kbeg, int kend) {
+    for (int k = kbeg; k < kend; ++k) {
+      const int len = n - k - 1;
+      hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau,
+                         ws.d, ws.e, ws.v, ws.y);
+      hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
+                         ws.K, n, n, k, ws.y, ws.tau, ws.v);
+    }
+  };
+  column_steps(0, kres);
   KS_LAUNCH_CHECK("tridiagonalisation");
-  hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
+  bool resident = false;
+  if (tp.k0 >= 0) {
+    hipLaunchKernelGGL(k_tri_reset, dim3(1), dim3(256), 0, s, ws.bar);
+    KS_LAUNCH_CHECK("tridiagonalisation reset");
+    double2* Kp = ws.K;
+    int ldk = n, nn = n, k0 = tp.k0, c = tp.c;
+    double2* taup = ws.tau;
+    double* dp = ws.d;
+    double* ep = ws.e;
+    double2* yb = ws.ybuf;
+    double2* xb = ws.xbuf;
+    unsigned* bar = ws.bar;
+    void* args[] = {&Kp, &ldk, &nn, &k0, &c, &taup, &dp, &ep, &yb, &xb, &bar, &info};
+    const hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_tridiag_resident),
+                                                     dim3((unsigned)tp.G), dim3(TRI_THREADS), args,
+                                                     (unsigned)tp.lds, s);
+    if (le == hipSuccess) {
+      resident = true;
+    } else {
+      (void)hipGetLastError();  // not enqueued: continue one column per launch
+    }
+  }
+  if (!resident) {
+    column_steps(kres, n - 1);
+    KS_LAUNCH_CHECK("tridiagonalisation");
+    hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
+  }
   hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), (size_t)2 * n * sizeof(double), s, ws.d, ws.e, n, nev, w,
                      ws.tnorm);
   hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, w, nev, ws.tnorm, ws.cl, ws.ncl);

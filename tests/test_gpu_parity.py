@@ -136,7 +136,10 @@ def colmajor(A):
     return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().T
 
 
-@pytest.mark.parametrize("n,nev", [(1, 1), (5, 3), (33, 11), (48, 16), (100, 40), (480, 160)])
+# 1440: the subspace of the 216-atom cell (trailing matrix resident in LDS
+# from the first step); 1800: one column per launch first, then resident
+@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (33, 11), (48, 16), (100, 40), (480, 160), (1440, 480),
+                                   (1800, 600)])
 def test_hegv_reduce_solve_matches_oracle(ks, n, nev):
     import torch
 
