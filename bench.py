@@ -38,8 +38,8 @@ WORKLOADS = {
 # commands are in profiles/hbm_traffic_fp64_c2.md).  A value holds only
 # while the kernel source it was measured on is unchanged (sha256 below).
 MEASURED_TRAFFIC = {
-    ("C2", "fp64", "gram"): (2.7275e9, "paper_2512_04447_amd/csrc/gemm.hip",
-                             "5667a84d09377d5cce0cc2b54d2c311c31e51ca744b823f82d803b7950981e98"),
+    ("C2", "fp64", "gram"): (2.7566e9, "paper_2512_04447_amd/csrc/gemm.hip",
+                             "8e195cd5a6a82ce27cef8fa10d7be8c0cdad2525fb7eaca23d43b1f2a1947834"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
