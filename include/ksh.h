@@ -195,7 +195,10 @@ int ks_precond_apply(const ks_plan* plan, int32_t kind, const void* X, const voi
  * On return w[0..nev) ascending, C (n x nev, ldc) with C^H S C = I, S holds
  * L in its lower triangle and H is overwritten.  info_dev (device int32):
  * 0 ok; n + k if the leading minor k of S is not positive definite (pivot
- * <= 1e-14 * max diag(S)), then w and C are not written.  n <= 8192. */
+ * <= 1e-14 * max diag(S)), then w and C are not written; -1 if the grid
+ * barrier of the resident tridiagonalisation (n >= 1024, one cooperative
+ * launch, co-residency guaranteed by the runtime) gave up after its bounded
+ * wait, then w and C are not valid.  n <= 8192. */
 int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds,
                       double* w, void* C, int32_t ldc, void* work, size_t work_bytes,
                       int32_t* info_dev, void* stream);

@@ -449,6 +449,12 @@ static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B,
   } else {
     hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.S0, nb, nb);
     if ((rc = hegv(nb, nb, w.H0, nb, w.S0, nb, w.lam, w.C, nb, w.hegv, w.info + 2, s))) return rc;
+    // S0 = I: only the tridiagonalisation's barrier can fail here
+    if (nb >= hegv_resident_min_n()) {
+      int32_t sinfo = 0;
+      if ((rc = read_info(w.info + 2, &sinfo, s))) return rc;
+      if (sinfo != 0) return fail(KS_E_NUMERIC, "SVQB eigensolve failed");
+    }
     const double tol = p.prec == KS_FP64 ? 1e-12 : 1e-6;
     hipLaunchKernelGGL((k_svqb_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.C, nb, nb, w.lam,
                        w.dvec, tol, static_cast<c2<T>*>(w.M), nb);
@@ -588,6 +594,7 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   if ((rc = hegv(m, nb, w.H, mfull, w.S, mfull, w.wnew, w.C, m, w.hegv, w.info, s))) return rc;
   int32_t hinfo = 0;
   if ((rc = read_info(w.info, &hinfo, s))) return rc;
+  if (hinfo < 0) return fail(KS_E_NUMERIC, "subspace eigensolve: tridiagonalisation grid barrier timed out");
   if (hinfo != 0 && st->has_p) {
     st->dropped_p += 1;
     m = 2 * nb;
@@ -597,6 +604,7 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
                        mfull, mfull);
     if ((rc = hegv(m, nb, w.H, mfull, w.S, mfull, w.wnew, w.C, m, w.hegv, w.info, s))) return rc;
     if ((rc = read_info(w.info, &hinfo, s))) return rc;
+    if (hinfo < 0) return fail(KS_E_NUMERIC, "subspace eigensolve: tridiagonalisation grid barrier timed out");
   }
   st->last_info = hinfo;
   if (hinfo != 0) return fail(KS_E_NUMERIC, "subspace overlap is not positive definite");

@@ -1077,6 +1077,7 @@ struct TriPlan {
 };
 constexpr int TRI_CTARGET = 8;
 constexpr int TRI_MIN_N = 1024;
+int hegv_resident_min_n() { return TRI_MIN_N; }
 
 static TriPlan tri_plan(int n) {
   TriPlan p;

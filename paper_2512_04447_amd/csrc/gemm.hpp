@@ -59,6 +59,9 @@ int zgemm(char ta, char tb, int M, int N, int K, double alpha, const double2* A,
 
 // ---- dense FP64 solver (dense.hip) ----
 size_t hegv_work(int n, int nev);
+// Smallest n whose tridiagonalisation uses the resident (cooperative) kernel;
+// only that kernel can report info = -1.
+int hegv_resident_min_n();
 int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds, double* w, double2* C, int ldc, void* work,
          int32_t* info, hipStream_t s);
 // Cholesky S = L L^H in place (lower), info as for hegv (k, not n + k).
