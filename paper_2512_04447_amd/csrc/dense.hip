@@ -2,7 +2,10 @@
 // problem H X = lambda S X (the paragraph before Eq. 1), by the paper's
 // reduction: S = L L^H, K = L^-1 H L^-H (Eq. 1) formed with two triangular
 // solves instead of a HEGST-type reduction (the paragraph after Eq. 1), a
-// Hermitian eigensolve of K, and X = L^-H Z.
+// Hermitian eigensolve of K, and X = L^-H Z.  The triangular solves are
+// products with L^-1, itself one blocked triangular solve on the identity:
+// on the GPU the blocked solve is bound by its launches (three per 32-row
+// block), so solving once and multiplying three times is the cheaper order.
 //
 // The paper calls vendor (P)ZHEEVD; here the Hermitian eigensolve is
 // Householder tridiagonalisation (one column per step), bisection with
@@ -219,23 +222,12 @@ int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ld
 }
 
 // ---------------------------------------------------------------- small ops
-// dst = src^H (n x n)
-__global__ void k_conj_transpose(const double2* __restrict__ src, int lds_, double2* __restrict__ dst, int ldd,
-                                 int n) {
-  __shared__ double2 t[32][33];
-  const int bi = blockIdx.x * 32, bj = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
-  for (int r = ty; r < 32; r += 8) {
-    const int i = bi + tx, j = bj + r;
-    if (i < n && j < n) t[r][tx] = src[i + (int64_t)j * lds_];
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int i = bj + tx, j = bi + r;  // dst(i, j) = conj(src(j, i))
-    if (i < n && j < n) {
-      double2 v = t[tx][r];
-      dst[i + (int64_t)j * ldd] = make_double2(v.x, -v.y);
-    }
+// A <- I (n x n)
+__global__ void k_set_identity(double2* __restrict__ A, int lda, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    A[i + (int64_t)j * lda] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
 }
 
@@ -1019,6 +1011,7 @@ k_backtransform(const double2* __restrict__ K, int ldk, int n, const double2* __
 // ---------------------------------------------------------------- hegv
 struct HegvWs {
   void* potrf;
+  double2* X;  // L^-1
   double2* K;
   double2* y;
   double2* v;
@@ -1039,6 +1032,7 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   char* p = static_cast<char*>(work);
   HegvWs w;
   w.potrf = p; p += al(potrf_work(n));
+  w.X = reinterpret_cast<double2*>(p); p += al((size_t)n * n * sizeof(double2));
   w.K = reinterpret_cast<double2*>(p); p += al((size_t)n * n * sizeof(double2));
   w.y = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
   w.v = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
@@ -1057,7 +1051,7 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
 }
 
 size_t hegv_work(int n, int nev) {
-  return al(potrf_work(n)) + al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
+  return al(potrf_work(n)) + 2 * al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
          al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16) +
          2 * al((size_t)2 * n * 16) + al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
 }
@@ -1112,13 +1106,19 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   TimerScope ts(KF_HEGV, s);
   int rc;
   if ((rc = potrf_impl(n, S, lds_, ws.potrf, info, n, s))) return rc;
-  // Y = L^-1 H (in H)
-  if ((rc = trsm('N', n, n, S, lds_, H, ldh, ws.potrf, ws.tmp, info, s))) return rc;
-  // K = L^-1 Y^H
-  dim3 tg((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32));
-  hipLaunchKernelGGL(k_conj_transpose, tg, dim3(256), 0, s, H, ldh, ws.K, n, n);
-  KS_LAUNCH_CHECK("conj_transpose");
-  if ((rc = trsm('N', n, n, S, lds_, ws.K, n, ws.potrf, ws.tmp, info, s))) return rc;
+  // The two triangular solves of the reduction, Y = L^-1 H and
+  // K = L^-1 Y^H, and the final C = L^-H Z go through X = L^-1: the blocked
+  // solve runs once, on the identity (its result is exactly zero above the
+  // diagonal), and each solve becomes one product, three launches instead
+  // of three blocked solves of about 3n/32 launches each.
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)),
+                     dim3(256), 0, s, ws.X, n, n);
+  KS_LAUNCH_CHECK("identity");
+  if ((rc = trsm('N', n, n, S, lds_, ws.X, n, ws.potrf, ws.tmp, info, s))) return rc;
+  // Y = X H (in K's buffer), K = Y X^H (in H), then K <- (K + K^H)/2
+  if ((rc = zgemm('N', 'N', n, n, n, 1.0, ws.X, n, H, ldh, 0.0, ws.K, n, s))) return rc;
+  if ((rc = zgemm('N', 'C', n, n, n, 1.0, ws.K, n, ws.X, n, 0.0, H, ldh, s))) return rc;
+  if ((rc = copy_block(H, ldh, ws.K, n, n, n, s))) return rc;
   hipLaunchKernelGGL(k_hermitise, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)), dim3(256),
                      0, s, ws.K, n, n);
   KS_LAUNCH_CHECK("hermitise");
@@ -1171,11 +1171,11 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), (size_t)n * (5 * sizeof(double) + sizeof(int)), s,
                      ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl, ws.Z, n);
   KS_LAUNCH_CHECK("bisection / inverse iteration");
+  // Q Z_T into H (no longer needed), then C = L^-H (Q Z_T) = X^H (Q Z_T)
   hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(64), (size_t)n * sizeof(double2), s, ws.K, n, n, ws.tau,
-                     ws.Z, n, C, ldc);
+                     ws.Z, n, H, ldh);
   KS_LAUNCH_CHECK("backtransform");
-  // C = L^-H Z
-  return trsm('C', n, nev, S, lds_, C, ldc, ws.potrf, ws.tmp, info, s);
+  return zgemm('C', 'N', n, nev, n, 1.0, ws.X, n, H, ldh, 0.0, C, ldc, s);
 }
 
 }  // namespace ks
