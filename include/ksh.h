@@ -267,6 +267,21 @@ int cnn_make_input(const ks_plan* plan, const void* R, int64_t ld, const double*
  * gradient with respect to the network output equals the one with respect
  * to y, so cnn_backward is unchanged. */
 int cnn_add_skip(const ks_plan* plan, int32_t nbatch, const float* x, float* y, void* stream);
+/* Inference of the network as lobpcg_step applies it (KS_PRECOND_CNN and
+ * KS_PRECOND_CNN_TPA): y[nbatch][2][Ng] = net(x[nbatch][3][Ng]) with the
+ * 16 -> 16 layer computed by cnn_conv16_bf16 (bfloat16 products) and the two
+ * other layers in FP32.  buf: 32 * nbatch * Ng floats of scratch (the
+ * act_floats of cnn_workspace_size suffice). */
+int cnn_infer(const ks_plan* plan, const float* params, int32_t nbatch, const float* x, float* y,
+              float* buf, void* stream);
+/* One periodic 3x3x3 convolution 16 -> 16 channels on the bfloat16 matrix
+ * cores: y[b][o][r] = bias[o] + sum_{i, d} w[o][i][d] x[b][i][r + d] (w as
+ * in the parameter vector, [o][i][dx][dy][dz]; d in {-1, 0, 1}^3), with x
+ * and w rounded to the nearest bfloat16 (ties to even), products and sums in
+ * FP32, then SiLU when silu != 0.  x, y: nbatch x 16 x Ng floats, no
+ * aliasing. */
+int cnn_conv16_bf16(const ks_plan* plan, int32_t nbatch, const float* x, const float* w,
+                    const float* b, int32_t silu, float* y, void* stream);
 
 /* Kernel timing for measurement (not needed to solve anything).
  * ks_kernel_timer(1, id) starts recording a HIP event pair around every

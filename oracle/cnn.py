@@ -83,13 +83,33 @@ def init_params(seed: int = 2, channels=CHANNELS):
     return params
 
 
-def forward(params, x: np.ndarray):
-    """Returns (output, cache) for one sample x (3, n, n, n)."""
+def round_bf16(a) -> np.ndarray:
+    """Nearest bfloat16 of each value, ties to even, returned as float64.
+
+    bfloat16 is the upper half of an IEEE binary32 (sign, 8 exponent bits,
+    7 fraction bits): the value is first rounded to binary32, then its lower
+    16 bits are rounded away (round half to even on bit 16).  NaN stays NaN.
+    """
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
+    nan = (u & 0x7FFFFFFF) > 0x7F800000
+    r = np.where(nan, ((u >> 16) | 0x40) & 0xFFFF, r)
+    return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def forward(params, x: np.ndarray, bf16_layer2: bool = False):
+    """Returns (output, cache) for one sample x (3, n, n, n).  With
+    ``bf16_layer2`` the second layer's input and weights are rounded to
+    bfloat16 first (the products and sums stay exact here)."""
     acts = [x]
     pre = []
     h = x
     for k, (w, b) in enumerate(params):
-        z = conv3d(h, w, b)
+        if bf16_layer2 and k == 1:
+            z = conv3d(round_bf16(h), round_bf16(w), b)
+        else:
+            z = conv3d(h, w, b)
         pre.append(z)
         h = silu(z) if k < len(params) - 1 else z
         acts.append(h)

@@ -40,6 +40,8 @@ EXPORTS = (
     "cnn_adam_step",
     "cnn_make_input",
     "cnn_add_skip",
+    "cnn_infer",
+    "cnn_conv16_bf16",
     "ks_kernel_timer",
     "ks_kernel_timer_read",
     "ks_last_error",
@@ -130,6 +132,8 @@ def load() -> C.CDLL:
     lib.cnn_adam_step.argtypes = [vp, vp, vp, vp, i32, i32, f32, vp]
     lib.cnn_make_input.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp]
     lib.cnn_add_skip.argtypes = [vp, i32, vp, vp, vp]
+    lib.cnn_infer.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.cnn_conv16_bf16.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
     lib.ks_kernel_timer.argtypes = [i32, i32]
     lib.ks_kernel_timer_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.ks_last_error.restype = C.c_char_p
@@ -416,6 +420,14 @@ class Cnn:
             cnn_add_skip(self.plan, x, self.y, nb, stream)
         return self.y[:nb]
 
+    def infer(self, x, nb=None, stream=None):
+        """y = net(x) as lobpcg_step applies it (16 -> 16 layer on bfloat16
+        MFMA); uses the activation buffer as scratch."""
+        nb = x.shape[0] if nb is None else nb
+        check(load().cnn_infer(self.plan.handle, _ptr(self.params), nb, _ptr(x), _ptr(self.y), _ptr(self.acts),
+                               C.c_void_p(_stream(stream))), "cnn_infer")
+        return self.y[:nb]
+
     def loss_grad(self, t, nb=None, stream=None):
         nb = t.shape[0] if nb is None else nb
         check(load().cnn_loss(nb, self.plan.Ng, _ptr(self.y), _ptr(t), _ptr(self.gy), _ptr(self.loss), _ptr(self.sums),
@@ -444,6 +456,14 @@ def cnn_make_input(plan: Plan, R, rnorm, v, theta, x, stream=None):
     check(load().cnn_make_input(plan.handle, _ptr(R), R.stride(0), None if rnorm is None else _ptr(rnorm), _ptr(v),
                                 _ptr(theta), nb, _ptr(x), C.c_void_p(_stream(stream))), "cnn_make_input")
     return x
+
+
+def cnn_conv16_bf16(plan: Plan, x, w, b, y, silu=True, nbatch=None, stream=None):
+    """y = conv(x; w, b) (16 -> 16 channels, periodic 3x3x3) with bfloat16
+    products, then SiLU when ``silu``; x, y: (nbatch, 16, Ng) float32."""
+    nb = x.shape[0] if nbatch is None else nbatch
+    check(load().cnn_conv16_bf16(plan.handle, nb, _ptr(x), _ptr(w), _ptr(b), 1 if silu else 0, _ptr(y),
+                                 C.c_void_p(_stream(stream))), "cnn_conv16_bf16")
 
 
 def cnn_add_skip(plan: Plan, x, y, nbatch=None, stream=None):

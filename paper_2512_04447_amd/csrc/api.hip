@@ -1007,6 +1007,31 @@ int cnn_make_input(const ks_plan* p, const void* R, int64_t ld, const double* rn
                                nb, x, s);
 }
 
+int cnn_infer(const ks_plan* p, const float* params, int32_t nbatch, const float* x, float* y, float* buf,
+              void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!params) return fail(-2, "params is null");
+  if (nbatch <= 0) return fail(-3, "nbatch must be positive");
+  if (!x) return fail(-4, "x is null");
+  if (!y) return fail(-5, "y is null");
+  if (!buf) return fail(-6, "buf is null");
+  return cnn_infer_impl(*p, params, nbatch, x, y, buf, static_cast<hipStream_t>(stream));
+}
+
+int cnn_conv16_bf16(const ks_plan* p, int32_t nbatch, const float* x, const float* w, const float* b, int32_t silu,
+                    float* y, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (nbatch <= 0) return fail(-2, "nbatch must be positive");
+  if (!x) return fail(-3, "x is null");
+  if (!w) return fail(-4, "w is null");
+  if (!b) return fail(-5, "b is null");
+  if (!y) return fail(-7, "y is null");
+  if (x == y) return fail(-7, "y must not alias x");
+  return cnn_conv16_bf16_impl(*p, nbatch, x, w, b, silu != 0, y, static_cast<hipStream_t>(stream));
+}
+
 int cnn_add_skip(const ks_plan* p, int32_t nbatch, const float* x, float* y, void* stream) {
   g_last_error.clear();
   if (!p) return fail(-1, "plan is null");

@@ -111,6 +111,8 @@ int cnn_loss_impl(const float* y, const float* t, int nbatch, int64_t Ng, float*
                   hipStream_t s);
 int cnn_adam_impl(float* params, const float* grads, float* m, float* v, int n, int t, float lr, hipStream_t s);
 int cnn_skip_impl(const ks_plan& p, int nbatch, const float* x, float* y, hipStream_t s);
+int cnn_conv16_bf16_impl(const ks_plan& p, int nbatch, const float* x, const float* w, const float* b, bool silu,
+                         float* y, hipStream_t s);
 template <typename T>
 int cnn_input_impl(const ks_plan& p, const c2<T>* R, int64_t ld, const double* rnorm, const T* V,
                    const double* theta, int nb, float* x, hipStream_t s);

@@ -65,6 +65,72 @@ def test_cnn_forward_matches_oracle(ks, n, nbatch):
     assert err <= 2e-5
 
 
+@pytest.mark.parametrize("n,nbatch,silu", [(10, 2, True), (16, 2, False), (48, 1, True)])
+def test_conv16_bf16_matches_oracle(ks, n, nbatch, silu):
+    """The 16 -> 16 layer on bfloat16 MFMA.  Inputs are bfloat16 values
+    already, so both sides round only the weights (from the same FP32
+    values).  bfloat16 products are exact in FP32, so the only error is the
+    FP32 summation of 27 x 16 terms: |y - ref| <= 432 u S per element, S the
+    sum of |terms| and u = 2^-24, times 1.1 (the slope of SiLU), plus the
+    FP32 bias and SiLU evaluation."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    _say("conv16 bf16", n, nbatch, silu)
+    rng = np.random.default_rng(31 + n)
+    w = rng.uniform(-0.12, 0.12, (16, 16, 3, 3, 3))
+    bias = 0.1 * rng.standard_normal(16)
+    x = ocnn.round_bf16(rng.standard_normal((nbatch, 16, n, n, n)))
+    wb = ocnn.round_bf16(w)
+    w32 = w.astype(np.float32)
+    ref, bound = [], []
+    for s_ in range(nbatch):
+        z = ocnn.conv3d(x[s_], wb, bias)
+        S = ocnn.conv3d(np.abs(x[s_]), np.abs(wb), np.abs(bias))
+        ref.append(ocnn.silu(z) if silu else z)
+        bound.append(1.1 * 432 * 2.0 ** -24 * S + 1e-6 * (np.abs(z) + 1.0))
+    ref = np.stack(ref)
+    bound = np.stack(bound)
+    plan = plan_for(n)
+    xd = dev(x.reshape(nbatch, 16, -1), torch.float32)
+    y = torch.empty_like(xd)
+    b.cnn_conv16_bf16(plan, xd, dev(w32.ravel()), dev(bias, torch.float32), y, silu=silu)
+    got = y.cpu().numpy().reshape(ref.shape)
+    err = np.abs(got - ref)
+    _say("  max err", err.max(), "max err / bound", (err / bound).max())
+    assert np.all(err <= bound)
+
+
+def test_cnn_infer_matches_oracle_with_bf16_second_layer(ks):
+    """The network as lobpcg_step applies it against the oracle with the
+    second layer's input and weights rounded to bfloat16.  The two sides
+    round that input from activations computed in FP32 (GPU) and FP64
+    (oracle): an activation within the FP32 error of a rounding midpoint can
+    round to neighbouring bfloat16 values (one bfloat16 ulp, 2^-8 relative),
+    which moves nearby outputs by about 1e-4 of their scale; elsewhere the
+    difference is FP32 summation error."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    n, nbatch = 16, 2
+    params = rand_params(4)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((nbatch, 3, n, n, n))
+    ref = np.stack([ocnn.forward(params, x[s_], bf16_layer2=True)[0] for s_ in range(nbatch)])
+    plain = np.stack([ocnn.forward(params, x[s_])[0] for s_ in range(nbatch)])
+    plan = plan_for(n)
+    net = b.Cnn(plan, dev(flat_params(params)), nbatch)
+    got = net.infer(dev(x.reshape(nbatch, 3, -1), torch.float32)).cpu().numpy().reshape(ref.shape)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    _say("cnn infer: max err", err.max() / scale, "median", np.median(err) / scale,
+         "bf16 vs fp64 network", np.abs(plain - ref).max() / scale)
+    assert err.max() <= 2e-3 * scale
+    assert np.median(err) <= 2e-5 * scale
+
+
 @pytest.mark.parametrize("n,nbatch", [(10, 2), (16, 2)])
 def test_cnn_backward_matches_oracle(ks, n, nbatch):
     import torch

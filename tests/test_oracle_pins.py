@@ -440,3 +440,27 @@ def test_projected_cg_matches_lstsq(tiny):
     ref = P @ ref
     assert ok
     assert np.linalg.norm(t - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_bfloat16_rounding_matches_torch_conversion():
+    """The oracle's nearest-bfloat16 rounding (ties to even) against torch's
+    float32 -> bfloat16 conversion: random magnitudes, exact ties of both
+    parities and signs, subnormals, overflow to infinity, zeros and
+    infinities; NaN stays NaN."""
+    import torch
+
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal(50000) * 10.0 ** rng.integers(-38, 38, 50000)).astype(np.float32)
+    hi = rng.integers(0, 1 << 16, 4000, dtype=np.uint64)
+    ties = ((hi << 16) | 0x8000).astype(np.uint32).view(np.float32)  # exactly half-way
+    tiny = (rng.integers(1, 1 << 23, 2000, dtype=np.uint64)).astype(np.uint32).view(np.float32)  # subnormals
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.finfo(np.float32).max, -np.finfo(np.float32).max,
+                        np.float32(1.0) + np.float32(2.0 ** -8), 3.0, -7.5e-39], dtype=np.float32)
+    allv = np.concatenate([x, ties, -ties, tiny, special])
+    allv = allv[np.isfinite(allv) | np.isinf(allv)]
+    ref = torch.from_numpy(allv).to(torch.bfloat16).to(torch.float64).numpy()
+    got = ocnn.round_bf16(allv)
+    assert np.array_equal(got, ref)
+    # representable: the low 16 bits of the binary32 pattern are zero
+    assert np.all((got.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+    assert np.isnan(ocnn.round_bf16(np.array([np.nan], dtype=np.float32))[0])
