@@ -324,6 +324,17 @@ __device__ inline int wrap_m(int k, int n) { return (2 * k < n) ? k : k - n; }
 // ---------------------------------------------------------------- pass A
 // MODE 0: load psi.  MODE 1: load r = ax - theta x and write per-plane
 // partial sums of |r|^2 to partial[band*n0 + x].
+// Loads per thread in flight in the global-memory loops of the passes: a
+// loop that stores each loaded value before the next load keeps one load
+// per thread in flight, and the passes were then bound by memory latency
+// (about 16 KB in flight per CU) rather than by bandwidth.  The loads of a
+// batch are unconditional, from an index clamped into range, and so are the
+// stores that consume them (a guarded use draws its load into the guarded
+// block, one load in flight again): an index past the end rewrites the last
+// element with its own value.  Four for FP64 in 1024-thread blocks (128
+// registers per thread there).
+template <typename T, int NT> constexpr int load_batch() { return (sizeof(T) == 8 && NT > 256) ? 4 : 8; }
+
 template <typename T, int MAXE, int MODE, int NT, int CN = 0>
 __global__ void __launch_bounds__(NT)
 k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
@@ -334,11 +345,12 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
   T2* s = reinterpret_cast<T2*>(smem_raw);
   __shared__ double red[NT / kWave];
   const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
-  const int plane = n1 * n2;
+  const int plane = CN > 0 ? CN * CN : n1 * n2;
   const int band = blockIdx.x / n0;
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * ld + off;
+  constexpr int BATCH = load_batch<T, NT>();
   // twiddle tables of the two axes, staged in LDS after the plane
   T2* st1 = s + lpad_size(plane);
   T2* st2 = st1 + n1;
@@ -348,15 +360,31 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
   if (MODE == 1) {
     const T2* in2 = src2 + band * ld + off;  // x
     const T th = T(theta[band]);
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      T2 a = in[i];
-      T2 b = in2[i];
-      T2 r = cmake<T2>(a.x - th * b.x, a.y - th * b.y);
-      acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-      s[lpad(i)] = r;
+    for (int i0 = threadIdx.x; i0 < plane; i0 += NT * BATCH) {
+      T2 a[BATCH], b[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * NT, plane - 1);
+        a[u] = in[i];
+        b[u] = in2[i];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = i0 + u * NT;
+        const T2 r = cmake<T2>(a[u].x - th * b[u].x, a[u].y - th * b[u].y);
+        const double r2 = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+        acc += i < plane ? r2 : 0.0;
+        s[lpad(min(i, plane - 1))] = r;
+      }
     }
   } else {
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = in[i];
+    for (int i0 = threadIdx.x; i0 < plane; i0 += NT * BATCH) {
+      T2 a[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) a[u] = in[min(i0 + u * NT, plane - 1)];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) s[lpad(min(i0 + u * NT, plane - 1))] = a[u];
+    }
   }
   __syncthreads();
   if constexpr (CN > 0) {
@@ -409,12 +437,20 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   const int z0 = zt * zc;
   T2* base = buf + band * ld + (int64_t)y * n2 + z0;
   const int64_t xs = (int64_t)n1 * n2;
-  const int tile = n0 * zc;
+  const int tile = (CN > 0 ? CN : n0) * zc;
+  constexpr int BATCH = load_batch<T, kThreads>();
   T2* st0 = s + tile;  // x-axis twiddles staged in LDS after the tile
   for (int i = threadIdx.x; i < n0; i += blockDim.x) st0[i] = tw0[i];
-  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int x = i / zc, z = i - x * zc;
-    s[i] = base[x * xs + z];
+  for (int i0 = threadIdx.x; i0 < tile; i0 += kThreads * BATCH) {
+    T2 a[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int i = min(i0 + u * kThreads, tile - 1);
+      const int x = i / zc, z = i - x * zc;
+      a[u] = base[x * xs + z];
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) s[min(i0 + u * kThreads, tile - 1)] = a[u];
   }
   __syncthreads();
   if constexpr (CN > 0)
@@ -467,16 +503,23 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* s = reinterpret_cast<T2*>(smem_raw);
   const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
-  const int plane = n1 * n2;
+  const int plane = CN > 0 ? CN * CN : n1 * n2;
   const int band = blockIdx.x / n0;
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * lds_ + off;
+  constexpr int BATCH = load_batch<T, NT>();
   T2* st1 = s + lpad_size(plane);  // twiddle tables staged in LDS after the plane
   T2* st2 = st1 + n1;
   for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
   for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) s[lpad(i)] = cconj(in[i]);
+  for (int i0 = threadIdx.x; i0 < plane; i0 += NT * BATCH) {
+    T2 a[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) a[u] = in[min(i0 + u * NT, plane - 1)];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) s[lpad(min(i0 + u * NT, plane - 1))] = cconj(a[u]);
+  }
   __syncthreads();
   if constexpr (CN > 0) {
     fft_ct<CN, CN, CN, 1, NT, true>(s, st1);  // y columns
@@ -489,11 +532,21 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   T2* out = dst + band * ldd + off;
   if (MODE == 0) {
     const T2* ps = psi + band * ldp + off;
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      T2 t = s[lpad(i)];
-      T2 p = ps[i];
-      const T vr = V[off + i];
-      out[i] = cmake<T2>(t.x * scale + vr * p.x, -t.y * scale + vr * p.y);
+    for (int i0 = threadIdx.x; i0 < plane; i0 += NT * BATCH) {
+      T2 p[BATCH];
+      T vr[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * NT, plane - 1);
+        p[u] = ps[i];
+        vr[u] = V[off + i];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * NT, plane - 1);
+        const T2 t = s[lpad(i)];
+        out[i] = cmake<T2>(t.x * scale + vr[u] * p[u].x, -t.y * scale + vr[u] * p[u].y);
+      }
     }
   } else {
     const T m = (res[band] > lock_tol) ? scale : T(0);
