@@ -45,6 +45,13 @@ __device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
 }
 
 // ---------------------------------------------------------------- Gram
+// v when c, else zero, selected per component (a select between two
+// vector structs was lowered through scratch memory)
+template <typename T2> __device__ __forceinline__ T2 keep_if(bool c, T2 v) {
+  using S = decltype(v.x);
+  return cmake<T2>(c ? v.x : S(0), c ? v.y : S(0));
+}
+
 // For upper tile (ti, tj) and K split `sp`: S_tile = A_I^H B1_J and, when
 // TWO, H_tile = A_I^H B2_J.  Partials (FP64) go to part[(sp*ntu + t)*4096 +
 // i*64 + j] (row-major within the tile).
@@ -142,6 +149,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   const T2* pb = cb < m ? seg_col(B1, cb) : nullptr;
   const T2* pb2 = (TWO && cb < m) ? seg_col(B2, cb) : nullptr;
   const T2 z = cmake<T2>(T(0), T(0));
+  const T2* pb0 = seg_col(A, 0);  // a valid column for loads that are discarded
   // FP32 products accumulate in FP32 over KFLUSH points, then in FP64.
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int KFLUSH = 256;
@@ -173,13 +181,41 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
         if (TWO) B2s[lc][lk + q] = rb2[q];
       }
     } else {
-#pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int64_t k = kb + lk + q;
-        const bool ok = k < k1;
-        As[lc][lk + q] = (pa && ok) ? pa[k] : z;
-        Bs[lc][lk + q] = (pb && ok) ? pb[k] : z;
-        if (TWO) B2s[lc][lk + q] = (pb2 && ok) ? pb2[k] : z;
+      // FP64: all loads of the chunk issued before the first is used.
+      // Unconditional loads from valid addresses (column 0 for a column past
+      // m, point k1 - 1 past k1) into named values, the zero selected on the
+      // value: a select between addresses, a guarded load or an array the
+      // compiler keeps in scratch each made the loads go one group at a time.
+      static_assert(EPT == 4, "FP64 chunk loads are written for 4 points per thread");
+      const T2* qa = pa ? pa : pb0;
+      const T2* qb = pb ? pb : pb0;
+      const T2* qb2 = pb2 ? pb2 : pb0;
+      const int64_t kq = kb + lk;
+      const int64_t e0 = min(kq, k1 - 1), e1 = min(kq + 1, k1 - 1), e2 = min(kq + 2, k1 - 1), e3 = min(kq + 3, k1 - 1);
+      const T2 a0 = qa[e0], a1 = qa[e1], a2 = qa[e2], a3 = qa[e3];
+      const T2 b0 = qb[e0], b1 = qb[e1], b2 = qb[e2], b3 = qb[e3];
+      T2 c0 = z, c1 = z, c2 = z, c3 = z;
+      if constexpr (TWO) {
+        c0 = qb2[e0];
+        c1 = qb2[e1];
+        c2 = qb2[e2];
+        c3 = qb2[e3];
+      }
+      const bool va = pa != nullptr, vb = pb != nullptr;
+      const bool o0 = kq < k1, o1 = kq + 1 < k1, o2 = kq + 2 < k1, o3 = kq + 3 < k1;
+      As[lc][lk + 0] = keep_if(va && o0, a0);
+      As[lc][lk + 1] = keep_if(va && o1, a1);
+      As[lc][lk + 2] = keep_if(va && o2, a2);
+      As[lc][lk + 3] = keep_if(va && o3, a3);
+      Bs[lc][lk + 0] = keep_if(vb && o0, b0);
+      Bs[lc][lk + 1] = keep_if(vb && o1, b1);
+      Bs[lc][lk + 2] = keep_if(vb && o2, b2);
+      Bs[lc][lk + 3] = keep_if(vb && o3, b3);
+      if constexpr (TWO) {
+        B2s[lc][lk + 0] = keep_if(vb && o0, c0);
+        B2s[lc][lk + 1] = keep_if(vb && o1, c1);
+        B2s[lc][lk + 2] = keep_if(vb && o2, c2);
+        B2s[lc][lk + 3] = keep_if(vb && o3, c3);
       }
     }
     __syncthreads();
