@@ -584,20 +584,38 @@ k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* _
   for (int j = 0; j < MAXP; ++j)
 #pragma unroll
     for (int b = 0; b < NBT; ++b) acc[j][b][0] = acc[j][b][1] = 0.0;
-  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-    const int idx = supp_idx[s0 + s];
-    T2 pv[NBT];
+  // SB support points per thread per step, all their loads issued before
+  // any is used: unconditional, from indices clamped into range (band nb - 1,
+  // projector np - 1, point ns - 1); the terms of a point past ns or a
+  // projector past np get a zero coefficient, and bands past nb are never
+  // written.  The per-thread summation order is that of one point at a time.
+  constexpr int SB = 2;
+  for (int sb = threadIdx.x; sb < ns; sb += blockDim.x * SB) {
+    int sp[SB], idx[SB];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b)
-      pv[b] = (b0 + b < nb) ? psi[(int64_t)(b0 + b) * ld + idx] : cmake<T2>(T(0), T(0));
+    for (int u = 0; u < SB; ++u) sp[u] = min(sb + u * (int)blockDim.x, ns - 1);
 #pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
-      if (j < np) {
-        const double bv = (double)bet[(int64_t)j * ns + s];
+    for (int u = 0; u < SB; ++u) idx[u] = supp_idx[s0 + sp[u]];
+    T bv[SB][MAXP];
+#pragma unroll
+    for (int u = 0; u < SB; ++u)
+#pragma unroll
+      for (int j = 0; j < MAXP; ++j) bv[u][j] = bet[(int64_t)min(j, np - 1) * ns + sp[u]];
+    T2 pv[SB][NBT];
+#pragma unroll
+    for (int u = 0; u < SB; ++u)
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) pv[u][b] = psi[(int64_t)min(b0 + b, nb - 1) * ld + idx[u]];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const bool valid = sb + u * (int)blockDim.x < ns;
+#pragma unroll
+      for (int j = 0; j < MAXP; ++j) {
+        const double c = (valid && j < np) ? (double)bv[u][j] : 0.0;
 #pragma unroll
         for (int b = 0; b < NBT; ++b) {
-          acc[j][b][0] += bv * (double)pv[b].x;
-          acc[j][b][1] += bv * (double)pv[b].y;
+          acc[j][b][0] += c * (double)pv[u][b].x;
+          acc[j][b][1] += c * (double)pv[u][b].y;
         }
       }
     }
@@ -649,9 +667,27 @@ k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int
   const int nbl = min(NBS, nb - b0);
   const int l0 = blk_ptr[k];
   const int nl = blk_ptr[k + 1] - l0;
-  for (int i = threadIdx.x; i < nl * NBS; i += blockDim.x) {
-    const int l = i / NBS, b = i - l * NBS;
-    sdc[l * ROW + b] = b < nbl ? dc[(int64_t)blk_proj[l0 + l] * nb + b0 + b] : cmake<T2>(T(0), T(0));
+  // Loads below are unconditional where they can be (indices clamped into
+  // range, unwanted values zeroed after loading): a guarded load is issued
+  // only when the one before it has returned.  A full band tile (nbl = NBS,
+  // the usual case) takes the read-modify-write of hpsi without guards.
+  for (int i0 = threadIdx.x; i0 < nl * NBS; i0 += blockDim.x * 4) {
+    int pj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pj[u] = blk_proj[l0 + min(i0 + u * (int)blockDim.x, nl * NBS - 1) / NBS];
+    T2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u * (int)blockDim.x, nl * NBS - 1);
+      const int b = i % NBS;
+      v[u] = dc[(int64_t)pj[u] * nb + b0 + min(b, nbl - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u * (int)blockDim.x, nl * NBS - 1);
+      const int l = i / NBS, b = i - l * NBS;
+      sdc[l * ROW + b] = b < nbl ? v[u] : cmake<T2>(T(0), T(0));
+    }
   }
   __syncthreads();
   const int64_t r = k * kScatterPts + threadIdx.x;
@@ -666,9 +702,15 @@ k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int
     T be[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      const int64_t e = base + (int64_t)min(s0 + u, w - 1) * kScatterPts;
+      lp[u] = (int)ell_lp[e];
+      be[u] = ell_beta[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       const bool ok = s0 + u < w;
-      lp[u] = ok ? (int)ell_lp[base + (int64_t)(s0 + u) * kScatterPts] : 0;
-      be[u] = ok ? ell_beta[base + (int64_t)(s0 + u) * kScatterPts] : T(0);
+      lp[u] = ok ? lp[u] : 0;
+      be[u] = ok ? be[u] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -681,14 +723,27 @@ k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int
       }
     }
   }
+  if (nbl == NBS) {
+    constexpr int G = NBS < 8 ? NBS : 8;  // bands per group of loads in flight
 #pragma unroll
-  for (int b = 0; b < NBS; ++b) {
-    if (b < nbl) {
-      T2* o = hpsi + (int64_t)(b0 + b) * ld + r;
-      T2 v = *o;
-      v.x += ax[b];
-      v.y += ay[b];
-      *o = v;
+    for (int g = 0; g < NBS; g += G) {
+      T2 v[G];
+#pragma unroll
+      for (int b = 0; b < G; ++b) v[b] = hpsi[(int64_t)(b0 + g + b) * ld + r];
+#pragma unroll
+      for (int b = 0; b < G; ++b)
+        hpsi[(int64_t)(b0 + g + b) * ld + r] = cmake<T2>(v[b].x + ax[g + b], v[b].y + ay[g + b]);
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < NBS; ++b) {
+      if (b < nbl) {
+        T2* o = hpsi + (int64_t)(b0 + b) * ld + r;
+        T2 v = *o;
+        v.x += ax[b];
+        v.y += ay[b];
+        *o = v;
+      }
     }
   }
 }
