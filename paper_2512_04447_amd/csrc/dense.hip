@@ -352,29 +352,40 @@ k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict
   const double2 t = tau[k];
   const double2 zero = make_double2(0.0, 0.0);
   const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
-  // the tile's entries do not depend on anything below: load them first
+  // the tile's entries do not depend on anything below: load them first.
+  // Loads are unconditional from indices clamped into range, the unwanted
+  // values zeroed afterwards per component (selects between addresses
+  // became flat loads issued one after another).
   double2 av[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + 256 * u;
     const int i = i0 + (e & 31), j = j0 + (e >> 5);
-    av[u] = (i < len && j < len) ? A[i + (int64_t)j * ldk] : zero;
+    av[u] = A[min(i, len - 1) + (int64_t)min(j, len - 1) * ldk];
+    const bool in = i < len && j < len;
+    av[u] = make_double2(in ? av[u].x : 0.0, in ? av[u].y : 0.0);
   }
   // the 64 edge entries of v and y this block needs (rows i0.., columns j0..)
   const int qe = threadIdx.x < 32 ? i0 + threadIdx.x : j0 + (int)threadIdx.x - 32;
   const bool edge = threadIdx.x < 64 && qe < len;
-  const double2 ve = edge ? v[qe] : zero, ye = edge ? y[qe] : zero;
+  const int qc = min(qe, len - 1);
+  double2 ve = v[qc], ye = y[qc];
+  ve = make_double2(edge ? ve.x : 0.0, edge ? ve.y : 0.0);
+  ye = make_double2(edge ? ye.x : 0.0, edge ? ye.y : 0.0);
   double s = 0.0;
   for (int q0 = threadIdx.x; q0 < len; q0 += 4 * 256) {
     double2 va[4], ya[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int q = q0 + 256 * u;
-      va[u] = q < len ? v[q] : zero;
-      ya[u] = q < len ? y[q] : zero;
+      const int q = min(q0 + 256 * u, len - 1);
+      va[u] = v[q];
+      ya[u] = y[q];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s += va[u].x * ya[u].x + va[u].y * ya[u].y;  // Re(conj(v) y)
+    for (int u = 0; u < 4; ++u) {
+      const double t = va[u].x * ya[u].x + va[u].y * ya[u].y;  // Re(conj(v) y)
+      s += q0 + 256 * u < len ? t : 0.0;
+    }
   }
   s = block_sum(s, red);
   const double c = -0.5 * (t.x * t.x + t.y * t.y) * s;

@@ -199,7 +199,7 @@ __host__ __device__ inline int lpad_size(int n) { return n + (n >> 4) + 1; }
 // LDS accesses stride by bs rather than by es (a large power of two for the
 // y and x transforms, which would put every lane in one bank).
 template <int R, int MAXE, bool PAD, typename T2>
-__device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, int Ns,
+__device__ __forceinline__ void stockham_stage(T2* s, int nbatch, int n, int es, int bs, int Ns,
                                       const T2* __restrict__ tw) {
   constexpr int NBF = (MAXE + R - 1) / R;
   const int nbf = n / R;
@@ -239,7 +239,7 @@ __device__ inline void stockham_stage(T2* s, int nbatch, int n, int es, int bs, 
 }
 
 template <int MAXE, bool PAD = true, typename T2>
-__device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, int bs,
+__device__ __forceinline__ void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, int bs,
                                  const T2* __restrict__ tw) {
   int Ns = 1;
   for (int st = 0; st < ap.nst; ++st) {
@@ -267,7 +267,7 @@ __device__ inline void fft_batch(T2* s, int nbatch, const AxisPlan& ap, int es, 
 // 16, 48, 96 and 112 points per axis (the benchmarked cells); other grids
 // take the run-time path above.
 template <int R, int N, int NBATCH, int ES, int BS, int NS, int NT, bool PAD, typename T2>
-__device__ inline void stockham_stage_ct(T2* s, const T2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage_ct(T2* s, const T2* __restrict__ tw) {
   constexpr int NBF = N / R;
   constexpr int TOTAL = NBATCH * NBF;
   constexpr int NIT = (TOTAL + NT - 1) / NT;
@@ -313,7 +313,7 @@ template <> struct CtRad<96> { static constexpr int R1 = 16, R2 = 6; };
 template <> struct CtRad<112> { static constexpr int R1 = 16, R2 = 7; };
 
 template <int N, int NBATCH, int ES, int BS, int NT, bool PAD, typename T2>
-__device__ inline void fft_ct(T2* s, const T2* __restrict__ tw) {
+__device__ __forceinline__ void fft_ct(T2* s, const T2* __restrict__ tw) {
   constexpr int R1 = CtRad<N>::R1, R2 = CtRad<N>::R2;
   stockham_stage_ct<R1, N, NBATCH, ES, BS, 1, NT, PAD>(s, tw);
   if constexpr (R2 > 1) stockham_stage_ct<R2, N, NBATCH, ES, BS, R1, NT, PAD>(s, tw);
