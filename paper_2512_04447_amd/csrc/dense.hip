@@ -1019,6 +1019,76 @@ k_backtransform(const double2* __restrict__ K, int ldk, int n, const double2* __
   for (int i = lane; i < n; i += 64) C[i + (int64_t)j * ldc] = z[i];
 }
 
+// The same product with the reflectors in registers: lane l holds the
+// entries l + 64 r (r < R) of the current reflector, uses them for both the
+// dot product and the update, and loads the next reflector (k - 1) while
+// the current one is applied, so that a reflector costs no dependent global
+// round trip.  Loads are unconditional from indices clamped into range,
+// zeroed afterwards.  Same arithmetic and summation order as
+// k_backtransform.  n - 1 <= 64 R.
+template <int R>
+__global__ void __launch_bounds__(64)
+k_backtransform_reg(const double2* __restrict__ K, int ldk, int n, const double2* __restrict__ tau,
+                    const double* __restrict__ Z, int ldz, double2* __restrict__ C, int ldc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* z = reinterpret_cast<double2*>(smem_raw);
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < n; i += 64) z[i] = make_double2(Z[i + (int64_t)j * ldz], 0.0);
+  __syncthreads();
+  double2 vc[R], vn[R];
+  // reflector k: v[i'] = K[(k + 1 + i') + k ldk], i' < n - k - 1
+#define KS_BT_LOAD(V, KK)                                                                      \
+  do {                                                                                         \
+    const int len_ = n - (KK) - 1;                                                             \
+    const double2* col_ = K + ((KK) + 1) + (int64_t)(KK) * ldk;                                \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) V[r] = col_[min(lane + 64 * r, len_ - 1)]; \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) {                                            \
+      const bool in_ = lane + 64 * r < len_;                                                   \
+      V[r] = make_double2(in_ ? V[r].x : 0.0, in_ ? V[r].y : 0.0);                             \
+    }                                                                                          \
+  } while (0)
+  if (n >= 2) KS_BT_LOAD(vc, n - 2);
+  for (int k = n - 2; k >= 0; --k) {
+    if (k > 0) KS_BT_LOAD(vn, k - 1);
+    const double2 t = tau[k];
+    if (t.x != 0.0 || t.y != 0.0) {  // uniform across the wave
+      const int len = n - k - 1;
+      double2* zk = z + k + 1;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        if (i < len) {
+          const double2 b = zk[i];
+          sr += vc[r].x * b.x + vc[r].y * b.y;  // conj(v) z
+          si += vc[r].x * b.y - vc[r].y * b.x;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+      }
+      const double fr = t.x * sr - t.y * si, fi = t.x * si + t.y * sr;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        if (i < len) {
+          double2 b = zk[i];
+          b.x -= fr * vc[r].x - fi * vc[r].y;
+          b.y -= fr * vc[r].y + fi * vc[r].x;
+          zk[i] = b;
+        }
+      }
+      __syncthreads();  // a single wave: orders this reflector's LDS writes before the next reads
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) vc[r] = vn[r];
+  }
+#undef KS_BT_LOAD
+  for (int i = lane; i < n; i += 64) C[i + (int64_t)j * ldc] = z[i];
+}
+
 // ---------------------------------------------------------------- hegv
 struct HegvWs {
   void* potrf;
@@ -1183,9 +1253,21 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
                      ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl, ws.Z, n);
   KS_LAUNCH_CHECK("bisection / inverse iteration");
   // Q Z_T into H (no longer needed), then C = L^-H (Q Z_T) = X^H (Q Z_T)
-  hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(64), (size_t)n * sizeof(double2), s, ws.K, n, n, ws.tau,
-                     ws.Z, n, H, ldh);
-  KS_LAUNCH_CHECK("backtransform");
+  {
+    const size_t lds = (size_t)n * sizeof(double2);
+    const int need = (int)ceil_div(std::max(n - 1, 1), 64);  // reflector entries per lane
+    if (need <= 8)
+      hipLaunchKernelGGL(k_backtransform_reg<8>, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
+    else if (need <= 16)
+      hipLaunchKernelGGL(k_backtransform_reg<16>, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
+    else if (need <= 24)
+      hipLaunchKernelGGL(k_backtransform_reg<24>, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
+    else if (need <= 48)
+      hipLaunchKernelGGL(k_backtransform_reg<48>, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
+    else
+      hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
+    KS_LAUNCH_CHECK("backtransform");
+  }
   return zgemm('C', 'N', n, nev, n, 1.0, ws.X, n, H, ldh, 0.0, C, ldc, s);
 }
 

@@ -56,6 +56,11 @@ def test_host_validation_rejects_bad_arguments_without_a_gpu():
     out = C.c_void_p()
     assert lib.ks_plan_create(C.byref(out), C.byref(g), None, 4, binding.KS_MIXED_BF16X3, None) == -2003
     assert "bf16" in lib.ks_last_error().decode()
+    # the network's inference and its bfloat16 layer validate before any launch
+    fake = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert lib.cnn_infer(None, fake, 1, fake, fake, fake, None) == -1
+    assert lib.cnn_conv16_bf16(None, 1, fake, fake, fake, 1, fake, None) == -1
+    assert "plan" in lib.ks_last_error().decode()
 
 
 def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
