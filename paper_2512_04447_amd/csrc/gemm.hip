@@ -133,6 +133,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   const int64_t k1 = min(K, k0 + kper);
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
   const int wi = wave / WJ, wj = wave % WJ;
+  const bool wact = ti * TILE + wi * 32 < m && tj * TILE + wj * WN * 16 < m;
   typename M::acc sr[2][WN], si[2][WN], hr[2][WN], hi[2][WN];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -225,6 +226,10 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
     if constexpr (F32) {
       if (kb > k0 && ((kb - k0) % KFLUSH) == 0) gram_flush<TWO>(sr, si, hr, hi, dsr, dsi, dhr, dhi);
     }
+    // a wave whose rows or columns all lie past m has only padding to
+    // compute: it loads and waits with the others but issues no MFMA, and
+    // the co-resident workgroup's wave on its SIMD takes the matrix core
+    if (wact)
 #pragma unroll
     for (int kk = 0; kk < GKC; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -450,6 +455,7 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
   const int b0 = blockIdx.y * TILE;
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
   const int wb = wave >> 1, wr = wave & 1;  // wave's band half, row half
+  const bool wact = b0 + wb * 32 < ncol;
   typename M::acc dr[2][2], di[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -498,6 +504,8 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
       Cs[cb][ci + 3] = q3;
       __syncthreads();
       if (c0 + KC < hi) KS_ROT_FETCH(c0 + KC);
+      // a wave whose 32 bands all lie past ncol issues no MFMA (padding)
+      if (wact)
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
         const int kr = kk + (lane >> 4);
