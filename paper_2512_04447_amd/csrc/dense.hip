@@ -50,12 +50,24 @@ __global__ void __launch_bounds__(256)
 k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restrict__ dmax,
         int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv) {
   __shared__ double2 a[NB][NB + 1];
-  __shared__ double2 x[NB][NB + 1];
   if (*info != 0) return;
   const double tol = CHOL_TOL * (*dmax);
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+  // the block: unconditional loads (indices clamped into the block), padding
+  // zeroed afterwards, four in flight per thread
+  static_assert(NB * NB == 4 * 256, "four entries per thread");
+  double2 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
     const int i = e % NB, j = e / NB;
-    a[i][j] = (i < kb && j < kb) ? S[(k0 + i) + (int64_t)(k0 + j) * lds] : make_double2(0.0, 0.0);
+    v[u] = S[(k0 + min(i, kb - 1)) + (int64_t)(k0 + min(j, kb - 1)) * lds];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int i = e % NB, j = e / NB;
+    const bool in = i < kb && j < kb;
+    a[i][j] = make_double2(in ? v[u].x : 0.0, in ? v[u].y : 0.0);
   }
   __syncthreads();
   for (int j = 0; j < kb; ++j) {
@@ -67,12 +79,14 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     // column j-1 was scaled in the previous phase by other threads: no
     // thread reads it here.  Update a[i][p] -= a[i][j] conj(a[p][j]) / d.
     const double rd = 1.0 / d;
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-      const int i = e % kb, p = e / kb;
-      if (p > j && i >= p) {
-        const double2 u = a[i][j], v = a[p][j];
-        a[i][p].x -= (u.x * v.x + u.y * v.y) * rd;
-        a[i][p].y -= (u.y * v.x - u.x * v.y) * rd;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int i = e % NB, p = e / NB;
+      if (p > j && i >= p && i < kb) {
+        const double2 x = a[i][j], y = a[p][j];
+        a[i][p].x -= (x.x * y.x + x.y * y.y) * rd;
+        a[i][p].y -= (x.y * y.x - x.x * y.y) * rd;
       }
     }
     // scale column j (entries i > j are read above only by this step)
@@ -88,34 +102,30 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     const int i = e % kb, j = e / kb;
     if (i >= j) S[(k0 + i) + (int64_t)(k0 + j) * lds] = a[i][j];
   }
-  // inverse X = L^-1 by rows: X[i][c] = (delta_ic - sum_{c<=p<i} L[i][p] X[p][c]) / L[i][i];
-  // 8 threads per column c split the sum over p and combine by shuffles
-  const int c = threadIdx.x >> 3, part = threadIdx.x & 7;
-  for (int i = 0; i < NB; ++i) {
-    double2 acc = make_double2(0.0, 0.0);
-    if (c < kb && i < kb && c < i)
-      for (int p = c + part; p < i; p += 8) {
-        const double2 l = a[i][p], y = x[p][c];
-        acc.x += l.x * y.x - l.y * y.y;
-        acc.y += l.x * y.y + l.y * y.x;
+  // inverse X = L^-1, column c by lane c of the first wave: forward
+  // substitution X[i][c] = (delta_ic - sum_{c<=p<i} L[i][p] X[p][c]) / L[i][i]
+  // in registers, L read from LDS (the same entry for every lane), no
+  // barriers
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    double2 xc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double accr = 0.0, acci = 0.0;
+#pragma unroll
+      for (int p = 0; p < i; ++p) {
+        const double2 l = a[i][p];
+        const double2 y = xc[p];  // zero for p < c
+        accr += l.x * y.x - l.y * y.y;
+        acci += l.x * y.y + l.y * y.x;
       }
-    for (int off = 4; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off, 8);
-      acc.y += __shfl_xor(acc.y, off, 8);
+      const bool live = c <= i && i < kb && c < kb;
+      const double inv = 1.0 / a[i][i].x;
+      const double dr = ((i == c ? 1.0 : 0.0) - accr) * inv, di = -acci * inv;
+      xc[i] = make_double2(live ? dr : 0.0, live ? di : 0.0);
     }
-    if (part == 0 && c < NB) {
-      double2 v = make_double2(0.0, 0.0);
-      if (c < kb && i < kb && c <= i) {
-        const double inv = 1.0 / a[i][i].x;
-        v = make_double2(((i == c ? 1.0 : 0.0) - acc.x) * inv, -acc.y * inv);
-      }
-      x[i][c] = v;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, j = e / NB;
-    linv[i + (int64_t)j * NB] = x[i][j];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) linv[i + (int64_t)c * NB] = xc[i];
   }
 }
 

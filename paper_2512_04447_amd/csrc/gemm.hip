@@ -578,27 +578,35 @@ k_zgemm(int M, int N, int K, double alpha, const double2* __restrict__ A, int ld
       for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0.0;
   const double2 z = make_double2(0.0, 0.0);
   for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * TILE; e += 256) {
-      // A tile: op(A)[i][k]
+    // the A tile op(A)[i][k] and the B tile op(B)[k][j], four elements of
+    // each per thread with all eight loads in flight: unconditional, from
+    // indices clamped into range, zeroed afterwards (guarded loads went one
+    // at a time)
+    static_assert(KC * TILE == 4 * 256, "four elements of each tile per thread");
+    double2 av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
       int i, k;
       if (!CA) { i = e % TILE; k = e / TILE; } else { k = e % KC; i = e / KC; }
-      const int gi = i0 + i, gk = k0 + k;
-      double2 v = z;
-      if (gi < M && gk < K) {
-        if (!CA) v = A[gi + (int64_t)gk * lda];
-        else { v = A[gk + (int64_t)gi * lda]; v.y = -v.y; }
-      }
-      As[k][i] = v;
-      // B tile: op(B)[k][j]
+      const int gi = min(i0 + i, M - 1), gk = min(k0 + k, K - 1);
+      av[u] = !CA ? A[gi + (int64_t)gk * lda] : A[gk + (int64_t)gi * lda];
       int j, kb;
       if (!CB) { kb = e % KC; j = e / KC; } else { j = e % TILE; kb = e / TILE; }
-      const int gj = j0 + j, gkb = k0 + kb;
-      double2 w = z;
-      if (gj < N && gkb < K) {
-        if (!CB) w = B[gkb + (int64_t)gj * ldb];
-        else { w = B[gj + (int64_t)gkb * ldb]; w.y = -w.y; }
-      }
-      Bs[j][kb] = w;
+      const int gj = min(j0 + j, N - 1), gkb = min(k0 + kb, K - 1);
+      bv[u] = !CB ? B[gkb + (int64_t)gj * ldb] : B[gj + (int64_t)gkb * ldb];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      int i, k;
+      if (!CA) { i = e % TILE; k = e / TILE; } else { k = e % KC; i = e / KC; }
+      const bool oka = i0 + i < M && k0 + k < K;
+      As[k][i] = make_double2(oka ? av[u].x : 0.0, oka ? (CA ? -av[u].y : av[u].y) : 0.0);
+      int j, kb;
+      if (!CB) { kb = e % KC; j = e / KC; } else { j = e % TILE; kb = e / TILE; }
+      const bool okb = j0 + j < N && k0 + kb < K;
+      Bs[j][kb] = make_double2(okb ? bv[u].x : 0.0, okb ? (CB ? -bv[u].y : bv[u].y) : 0.0);
     }
     __syncthreads();
 #pragma unroll
