@@ -344,6 +344,80 @@ k_house_hemv(const double2* __restrict__ K, int ldk, int n, int k, double2* __re
   if (lane == 0) y[row] = make_double2(ar, ai);
 }
 
+// The same step for len <= 64 R with every load issued at the start: x and
+// the wave's column of A22 in registers (unconditional loads from indices
+// clamped into range, zeroed afterwards), so that the column does not wait
+// for the norm.  Same formulas; the norm and the product are summed in
+// another order.
+template <int R>
+__global__ void __launch_bounds__(256)
+k_house_hemv_reg(const double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ tau,
+                 double* __restrict__ d, double* __restrict__ e, double2* __restrict__ vbuf, double2* __restrict__ y) {
+  const int len = n - k - 1;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double2* x = K + (k + 1) + (int64_t)k * ldk;
+  const double2* col = K + (k + 1) + (int64_t)(k + 1 + min(row, len - 1)) * ldk;
+  double2 xa[R], ca[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int jc = min(lane + 64 * r, len - 1);
+    xa[r] = x[jc];
+    ca[r] = col[jc];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool in = lane + 64 * r < len;
+    xa[r] = make_double2(in ? xa[r].x : 0.0, in ? xa[r].y : 0.0);
+    ca[r] = make_double2(in ? ca[r].x : 0.0, in ? ca[r].y : 0.0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double t2 = xa[r].x * xa[r].x + xa[r].y * xa[r].y;
+    s += (lane + 64 * r >= 1) ? t2 : 0.0;  // x2: entries after alpha
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const double2 alpha = make_double2(__shfl(xa[0].x, 0, 64), __shfl(xa[0].y, 0, 64));
+  double2 t, scale;
+  double beta;
+  if (s == 0.0 && alpha.y == 0.0) {
+    t = make_double2(0.0, 0.0);
+    beta = alpha.x;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double ar = alpha.x - beta, ai = alpha.y;
+    const double den = ar * ar + ai * ai;
+    scale = make_double2(ar / den, -ai / den);
+  }
+  double ar = 0.0, ai = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    const double2 xv = xa[r];
+    const double2 v = j == 0 ? make_double2(1.0, 0.0)
+                             : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+    if (row == 0 && j < len) vbuf[j] = v;
+    const double2 a = ca[r];  // zero beyond len
+    ar += a.x * v.x + a.y * v.y;  // conj(a) v
+    ai += a.x * v.y - a.y * v.x;
+  }
+  if (row == 0 && lane == 0) {
+    tau[k] = t;
+    d[k] = K[k + (int64_t)k * ldk].x;
+    e[k] = beta;
+  }
+  if (row >= len) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
+  }
+  if (lane == 0) y[row] = make_double2(ar, ai);
+}
+
 // A22 <- A22 - w v^H - v w^H with w = tau y - (1/2)|tau|^2 Re(v^H y) v.
 // Every block recomputes v^H y in the same order (identical result).
 // v comes from vbuf; blocks of the first column of tiles also store their
@@ -1221,8 +1295,12 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   auto column_steps = [&](int kbeg, int kend) {
     for (int k = kbeg; k < kend; ++k) {
       const int len = n - k - 1;
-      hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau,
-                         ws.d, ws.e, ws.v, ws.y);
+      if (len <= 512)
+        hipLaunchKernelGGL(k_house_hemv_reg<8>, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k,
+                           ws.tau, ws.d, ws.e, ws.v, ws.y);
+      else
+        hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau,
+                           ws.d, ws.e, ws.v, ws.y);
       hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
                          ws.K, n, n, k, ws.y, ws.tau, ws.v);
     }
