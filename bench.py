@@ -38,8 +38,8 @@ WORKLOADS = {
 # commands are in profiles/hbm_traffic_fp64_c2.md).  A value holds only
 # while the kernel source it was measured on is unchanged (sha256 below).
 MEASURED_TRAFFIC = {
-    ("C2", "fp64", "gram"): (2.6590e9, "paper_2512_04447_amd/csrc/gemm.hip",
-                             "8b6bc70d114a9d93d96378fea22e4328fe5baeb08cd14f0ecb62a8b1133ad580"),
+    ("C2", "fp64", "gram"): (2.6337e9, "paper_2512_04447_amd/csrc/gemm.hip",
+                             "ca2ed848dd0136ad8d302c7494b9380d81e4ee92cc048422c78d4ddac899512a"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
