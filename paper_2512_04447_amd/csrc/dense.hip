@@ -817,6 +817,140 @@ __global__ void k_tri_reset(unsigned* bar) {
   for (int i = threadIdx.x; i < TRI_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
 }
 
+// ---------------------------------------------------------------- LDS tail
+// The last steps k0..n-2 of the reduction in one workgroup once the trailing
+// matrix fits in LDS (m = n - k0 - 1 <= TAIL_MAX): the matrix A[k0+1:, k0+1:]
+// (all of it, the step updates both triangles as k_her2 does) and column k0
+// in LDS, block barriers between the parts of a step instead of two launches.
+// Same formulas as k_house_hemv / k_her2 (other summation orders).  Writes
+// d, e, tau for k0..n-1 and the reflectors into K's columns k0..n-2.
+// Dynamic LDS: (m^2 + 4 m) double2.
+constexpr int TAIL_MAX = 96;
+constexpr int TAIL_THREADS = 1024;
+
+__global__ void __launch_bounds__(TAIL_THREADS)
+k_tridiag_tail_lds(double2* __restrict__ K, int ldk, int n, int k0, double2* __restrict__ tau,
+                   double* __restrict__ d, double* __restrict__ e) {
+  extern __shared__ __align__(16) unsigned char tail_raw[];
+  const int m = n - k0 - 1;
+  double2* L = reinterpret_cast<double2*>(tail_raw);  // L[i][j] = A[k0+1+i][k0+1+j], row-major
+  double2* xc = L + m * m;                            // column k0, rows k0+1..
+  double2* vb = xc + m;                               // reflector of the step
+  double2* yb = vb + m;                               // A22 v, then w
+  __shared__ double red[TAIL_THREADS / 64];
+  __shared__ double2 par_s[3];                        // tau, scale, (beta, d)
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  for (int e2 = t; e2 < m * m; e2 += TAIL_THREADS) {
+    const int i = e2 / m, j = e2 - i * m;
+    L[e2] = K[(k0 + 1 + i) + (int64_t)(k0 + 1 + j) * ldk];
+  }
+  for (int i = t; i < m; i += TAIL_THREADS) xc[i] = K[(k0 + 1 + i) + (int64_t)k0 * ldk];
+  const double dk0 = K[k0 + (int64_t)k0 * ldk].x;
+  __syncthreads();
+  for (int kk = 0; kk < m; ++kk) {
+    const int k = k0 + kk, len = m - kk;
+    // x = column k below the diagonal: xc for the first step, else L[kk.., kk-1]
+    auto xat = [&](int i) -> double2 { return kk == 0 ? xc[i] : L[(kk + i) * m + (kk - 1)]; };
+    // 1. norm of x[1:] (block reduction)
+    double sp = 0.0;
+    for (int i = 1 + t; i < len; i += TAIL_THREADS) {
+      const double2 xv = xat(i);
+      sp += xv.x * xv.x + xv.y * xv.y;
+    }
+    sp = wave_sum(sp);
+    if (lane == 0) red[wid] = sp;
+    __syncthreads();
+    if (t == 0) {
+      double sn = 0.0;
+      for (int w = 0; w < TAIL_THREADS / 64; ++w) sn += red[w];
+      const double2 alpha = xat(0);
+      double2 tt, scale;
+      double beta;
+      if (sn == 0.0 && alpha.y == 0.0) {
+        tt = make_double2(0.0, 0.0);
+        beta = alpha.x;
+        scale = make_double2(0.0, 0.0);
+      } else {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sn);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tt = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double ar = alpha.x - beta, ai = alpha.y;
+        const double den = ar * ar + ai * ai;
+        scale = make_double2(ar / den, -ai / den);
+      }
+      par_s[0] = tt;
+      par_s[1] = scale;
+      tau[k] = tt;
+      d[k] = kk == 0 ? dk0 : L[(kk - 1) * m + (kk - 1)].x;
+      e[k] = beta;
+    }
+    __syncthreads();
+    const double2 tt = par_s[0], scale = par_s[1];
+    // 2. v = (1, x[1:] scale), into LDS and into column k of K
+    for (int i = t; i < len; i += TAIL_THREADS) {
+      const double2 xv = xat(i);
+      const double2 v = i == 0 ? make_double2(1.0, 0.0)
+                               : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+      vb[i] = v;
+      K[(k + 1 + i) + (int64_t)k * ldk] = v;
+    }
+    __syncthreads();
+    // 3. y = A22 v, y_i = sum_j conj(A22[j][i]) v_j (A22 Hermitian; column i
+    //    read across consecutive threads): 8 threads per row
+    {
+      const int i = t >> 3, part = t & 7;
+      double yr = 0.0, yi = 0.0;
+      if (i < len) {
+        for (int j = part; j < len; j += 8) {
+          const double2 a = L[(kk + j) * m + (kk + i)];
+          const double2 v = vb[j];
+          yr += a.x * v.x + a.y * v.y;
+          yi += a.x * v.y - a.y * v.x;
+        }
+      }
+      for (int off = 4; off > 0; off >>= 1) {
+        yr += __shfl_xor(yr, off, 8);
+        yi += __shfl_xor(yi, off, 8);
+      }
+      if (i < len && part == 0) yb[i] = make_double2(yr, yi);
+    }
+    __syncthreads();
+    // 4. s = Re(v^H y), w = tau y - (1/2)|tau|^2 s v
+    double ss = 0.0;
+    for (int i = t; i < len; i += TAIL_THREADS) ss += vb[i].x * yb[i].x + vb[i].y * yb[i].y;
+    ss = wave_sum(ss);
+    if (lane == 0) red[wid] = ss;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < TAIL_THREADS / 64; ++w) s += red[w];
+    const double c = -0.5 * (tt.x * tt.x + tt.y * tt.y) * s;
+    double2 wv = make_double2(0.0, 0.0);
+    if (t < len) {
+      const double2 y = yb[t], v = vb[t];
+      wv = make_double2(tt.x * y.x - tt.y * y.y + c * v.x, tt.x * y.y + tt.y * y.x + c * v.y);
+    }
+    __syncthreads();  // every thread has read yb and red
+    if (t < len) yb[t] = wv;
+    __syncthreads();
+    // 5. A22 <- A22 - w v^H - v w^H
+    for (int e2 = t; e2 < len * len; e2 += TAIL_THREADS) {
+      const int i = e2 / len, j = e2 - i * len;
+      const double2 wi = yb[i], vi = vb[i], wj = yb[j], vj = vb[j];
+      const double re = wi.x * vj.x + wi.y * vj.y + vi.x * wj.x + vi.y * wj.y;
+      const double im = wi.y * vj.x - wi.x * vj.y + vi.y * wj.x - vi.x * wj.y;
+      double2* a = L + (kk + i) * m + (kk + j);
+      a->x -= re;
+      a->y -= im;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    d[n - 1] = L[(m - 1) * m + (m - 1)].x;
+    e[n - 1] = 0.0;
+    tau[n - 1] = make_double2(0.0, 0.0);
+  }
+}
+
 // ---------------------------------------------------------------- bisection
 __device__ inline double pivmin_of(const double* e, int n) {
   double m = 1.0;
@@ -1291,7 +1425,8 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   // trailing matrix is larger than the LDS of the device holds, then the
   // resident kernel for the remaining steps
   const TriPlan tp = tri_plan(n);
-  const int kres = tp.k0 >= 0 ? tp.k0 : n - 1;
+  const int klds = std::max(0, n - 1 - TAIL_MAX);  // first step of the LDS tail
+  const int kres = tp.k0 >= 0 ? tp.k0 : klds;       // launches up to here
   auto column_steps = [&](int kbeg, int kend) {
     for (int k = kbeg; k < kend; ++k) {
       const int len = n - k - 1;
@@ -1330,9 +1465,19 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
     }
   }
   if (!resident) {
-    column_steps(kres, n - 1);
+    // the last steps (trailing matrix of at most TAIL_MAX) in one workgroup
+    const int kfrom = std::max(kres, klds);
+    column_steps(kres, kfrom);
     KS_LAUNCH_CHECK("tridiagonalisation");
-    hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
+    if (n >= 2) {
+      const int mt = n - kfrom - 1;
+      const size_t lds = ((size_t)mt * mt + 4 * (size_t)mt) * sizeof(double2);
+      hipLaunchKernelGGL(k_tridiag_tail_lds, dim3(1), dim3(TAIL_THREADS), lds, s, ws.K, n, n, kfrom, ws.tau, ws.d,
+                         ws.e);
+      KS_LAUNCH_CHECK("tridiagonalisation tail");
+    } else {
+      hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
+    }
   }
   hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), (size_t)2 * n * sizeof(double), s, ws.d, ws.e, n, nev, w,
                      ws.tnorm);
