@@ -159,7 +159,8 @@ typedef struct {
  * projector tables in device memory (values in the plan's precision) plus
  * their inverse by grid point (for the deterministic scatter), and launch
  * configurations.  `proj` may be NULL or have n_proj == 0 (no nonlocal
- * term).  nb_max bounds the block width of later calls.  Allocates device
+ * term).  nb_max bounds the block width of later calls (at most 1233: the
+ * subspace problem has order 3 nb_max, see hegv_reduce_solve).  Allocates device
  * memory; synchronises `stream` once at the end. */
 int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj,
                    int32_t nb_max, int32_t precision, void* stream);
@@ -198,7 +199,8 @@ int ks_precond_apply(const ks_plan* plan, int32_t kind, const void* X, const voi
  * <= 1e-14 * max diag(S)), then w and C are not written; -1 if the grid
  * barrier of the resident tridiagonalisation (n >= 1024, one cooperative
  * launch, co-residency guaranteed by the runtime) gave up after its bounded
- * wait, then w and C are not valid.  n <= 8192. */
+ * wait, then w and C are not valid.  n <= 3700 (inverse iteration keeps 44
+ * bytes per row in LDS), so ks_plan_create accepts nb_max <= 1233. */
 int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds,
                       double* w, void* C, int32_t ldc, void* work, size_t work_bytes,
                       int32_t* info_dev, void* stream);

@@ -677,6 +677,7 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   if (!out) return fail(-1, "out is null");
   if (!grid) return fail(-2, "grid is null");
   if (nb_max <= 0) return fail(-4, "nb_max must be positive");
+  if (3 * (int64_t)nb_max > kHegvMaxN) return fail(-4, "nb_max too large: the subspace problem of order 3 nb_max must be at most 3700");
   if (precision < KS_FP64 || precision > KS_MIXED_BF16X3) return fail(-5, "unknown precision");
   if (precision == KS_MIXED_BF16X3) return fail(KS_E_UNSUPPORTED, "the bf16x3 Gram split is not built");
   ks_plan* p = new ks_plan();
@@ -827,7 +828,7 @@ int ks_precond_apply(const ks_plan* p, int32_t kind, const void* X, const void* 
 }
 
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
-  if (n <= 0 || n > 8192) return fail(-1, "n out of range");
+  if (n <= 0 || n > kHegvMaxN) return fail(-1, "n out of range (1..3700: the inverse iteration stages 44 bytes per row in LDS)");
   if (nev <= 0 || nev > n) return fail(-2, "nev out of range");
   if (!bytes) return fail(-3, "bytes is null");
   *bytes = hegv_work(n, nev);
@@ -837,7 +838,7 @@ int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
 int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds, double* w, void* C,
                       int32_t ldc, void* work, size_t work_bytes, int32_t* info_dev, void* stream) {
   g_last_error.clear();
-  if (n <= 0 || n > 8192) return fail(-1, "n out of range");
+  if (n <= 0 || n > kHegvMaxN) return fail(-1, "n out of range (1..3700: the inverse iteration stages 44 bytes per row in LDS)");
   if (nev <= 0 || nev > n) return fail(-2, "nev out of range");
   if (!H) return fail(-3, "H is null");
   if (ldh < n) return fail(-4, "ldh < n");

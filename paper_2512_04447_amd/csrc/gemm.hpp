@@ -59,6 +59,9 @@ int zgemm(char ta, char tb, int M, int N, int K, double alpha, const double2* A,
 
 // ---- dense FP64 solver (dense.hip) ----
 size_t hegv_work(int n, int nev);
+// Largest order of the dense eigensolve: inverse iteration keeps five doubles
+// and an int per row in LDS (44 bytes; 160 KB per workgroup).
+constexpr int kHegvMaxN = 3700;
 // Smallest n whose tridiagonalisation uses the resident (cooperative) kernel;
 // only that kernel can report info = -1.
 int hegv_resident_min_n();

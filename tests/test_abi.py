@@ -43,6 +43,9 @@ def test_host_validation_rejects_bad_arguments_without_a_gpu():
     assert b"nev" in lib.ks_last_error() or True
     assert lib.hegv_reduce_solve(0, 1, None, 0, None, 0, None, None, 0, None, 0, None, None) == -1
     assert lib.hegv_reduce_solve(4, 2, None, 4, None, 4, None, None, 4, None, 0, None, None) == -3
+    # the dense eigensolve's size limit (LDS of the inverse iteration)
+    assert lib.hegv_workspace_size(3701, 10, C.byref(n)) == -1
+    assert lib.hegv_workspace_size(3700, 10, C.byref(n)) == 0
     assert lib.ks_workspace_size(None, 1, 1, C.byref(n)) == -1
     assert lib.ks_apply_h(None, None, None, 0, None, 0, 1, None, 0, None) == -1
     assert lib.lobpcg_step(None, None, None, None, None, 0, None) == -1
