@@ -1085,15 +1085,25 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
       if (j > j0 && lam - lam_prev < pertol) lam = lam_prev + pertol;
       lam_prev = lam;
     }
+    // d and e staged in LDS for the serial elimination (global loads there
+    // cost a memory latency per row): d in x (written only after the
+    // elimination), e in u2 (entry i is read before the elimination writes
+    // it)
+    double* sd = x;
+    double* se = u2;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      sd[i] = d[i];
+      se[i] = i + 1 < n ? e[i] : 0.0;
+    }
     __syncthreads();
     lam = lam_prev;
     if (threadIdx.x == 0) {
       // LU of T - lam I with partial pivoting; (c0, c1) are the diagonal and
       // superdiagonal of row i as modified by the previous elimination step
-      double c0 = d[0] - lam, c1 = n > 1 ? e[0] : 0.0;
+      double c0 = sd[0] - lam, c1 = n > 1 ? se[0] : 0.0;
       for (int i = 0; i + 1 < n; ++i) {
-        const double b = e[i];
-        const double n0 = d[i + 1] - lam, n1 = i + 2 < n ? e[i + 1] : 0.0;
+        const double b = se[i];
+        const double n0 = sd[i + 1] - lam, n1 = i + 2 < n ? se[i + 1] : 0.0;
         if (fabs(c0) >= fabs(b)) {
           const double p0 = c0 == 0.0 ? small : c0;
           const double l = b / p0;
@@ -1119,6 +1129,7 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
       u1[n - 1] = 0.0;
       u2[n - 1] = 0.0;
     }
+    __syncthreads();  // the elimination read d from x, which is overwritten next
     // deterministic start vector
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)(j * 40503u + 12345u);
