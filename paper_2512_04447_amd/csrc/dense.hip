@@ -500,6 +500,135 @@ k_her2(double2* __restrict__ K, int ldk, int n, int k, const double2* __restrict
   }
 }
 
+// Step k's rank-2 update (as k_her2) and step k+1's Householder vector and
+// product (as k_house_hemv_reg) in one launch, for trailing sizes up to 64 R.
+// Indices are those of step k's trailing matrix A22 (len x len).  One wave
+// per column c = 1..len-1; column c is column c-1 of step k+1's trailing
+// matrix, and the wave yields entry c-1 of y_{k+1}.  The wave loads its
+// column as step k left it, v_k, y_k and column 0, forms
+// w_k = tau_k y_k - (1/2)|tau_k|^2 Re(v_k^H y_k) v_k, updates column 0 and
+// its own column in registers (every wave column 0 alike), takes step k+1's
+// reflector from rows 1.. of the updated column 0 and its entry of y_{k+1}
+// from rows 1.. of its updated column, and stores its column.  Column 0 is
+// not stored: only the rows below step k+1's diagonal are used later, and
+// the next launch overwrites them with v_{k+1}; d[k+1] comes from the
+// registers.  Wave 0 of block 0 writes v_k into K[k+1:, k] (kept for the
+// back-transform), v_{k+1}, tau[k+1], d[k+1] and e[k+1].  v and y go from
+// (vin, yin) to (vout, yout), separate buffers because other waves still
+// read the inputs.  No wave reads a column another wave writes.  len >= 2.
+template <int R>
+__global__ void __launch_bounds__(256)
+k_her2_house_hemv_reg(double2* __restrict__ K, int ldk, int n, int k, double2* __restrict__ tau,
+                      double* __restrict__ d, double* __restrict__ e, const double2* __restrict__ vin,
+                      const double2* __restrict__ yin, double2* __restrict__ vout, double2* __restrict__ yout) {
+  const int len = n - k - 1;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = min(row + 1, len - 1);
+  double2* A = K + (k + 1) + (int64_t)(k + 1) * ldk;
+  const double2 tk = tau[k];
+  // every load first: unconditional, from indices clamped into range,
+  // entries past len zeroed afterwards
+  double2 va[R], ya[R], xa[R], ca[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int jc = min(lane + 64 * r, len - 1);
+    va[r] = vin[jc];
+    ya[r] = yin[jc];
+    xa[r] = A[jc];
+    ca[r] = A[jc + (int64_t)c * ldk];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool in = lane + 64 * r < len;
+    va[r] = make_double2(in ? va[r].x : 0.0, in ? va[r].y : 0.0);
+    ya[r] = make_double2(in ? ya[r].x : 0.0, in ? ya[r].y : 0.0);
+    xa[r] = make_double2(in ? xa[r].x : 0.0, in ? xa[r].y : 0.0);
+    ca[r] = make_double2(in ? ca[r].x : 0.0, in ? ca[r].y : 0.0);
+  }
+  // w_k
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) s += va[r].x * ya[r].x + va[r].y * ya[r].y;  // Re(conj(v) y)
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const double cw = -0.5 * (tk.x * tk.x + tk.y * tk.y) * s;
+  double2 wa[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    wa[r] = make_double2(tk.x * ya[r].x - tk.y * ya[r].y + cw * va[r].x, tk.x * ya[r].y + tk.y * ya[r].x + cw * va[r].y);
+  // v and w at index 0 and at index c (register c / 64 is the same for the
+  // whole wave)
+  const double2 v0 = make_double2(__shfl(va[0].x, 0, 64), __shfl(va[0].y, 0, 64));
+  const double2 w0 = make_double2(__shfl(wa[0].x, 0, 64), __shfl(wa[0].y, 0, 64));
+  double2 vsel = va[0], wsel = wa[0];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const bool pick = (c >> 6) == r;
+    vsel = make_double2(pick ? va[r].x : vsel.x, pick ? va[r].y : vsel.y);
+    wsel = make_double2(pick ? wa[r].x : wsel.x, pick ? wa[r].y : wsel.y);
+  }
+  const double2 vc = make_double2(__shfl(vsel.x, c & 63, 64), __shfl(vsel.y, c & 63, 64));
+  const double2 wc = make_double2(__shfl(wsel.x, c & 63, 64), __shfl(wsel.y, c & 63, 64));
+  // A22[i][j] -= w_i conj(v_j) + v_i conj(w_j) for j = 0 and j = c
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double2 wi = wa[r], vi = va[r];
+    xa[r].x -= wi.x * v0.x + wi.y * v0.y + vi.x * w0.x + vi.y * w0.y;
+    xa[r].y -= wi.y * v0.x - wi.x * v0.y + vi.y * w0.x - vi.x * w0.y;
+    ca[r].x -= wi.x * vc.x + wi.y * vc.y + vi.x * wc.x + vi.y * wc.y;
+    ca[r].y -= wi.y * vc.x - wi.x * vc.y + vi.y * wc.x - vi.x * wc.y;
+  }
+  // step k+1: x = rows 1.. of column 0, alpha its first entry
+  double s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double t2 = xa[r].x * xa[r].x + xa[r].y * xa[r].y;
+    s2 += (lane + 64 * r >= 2) ? t2 : 0.0;  // x2: entries after alpha
+  }
+  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+  const double2 alpha = make_double2(__shfl(xa[0].x, 1, 64), __shfl(xa[0].y, 1, 64));
+  double2 t, scale;
+  double beta;
+  if (s2 == 0.0 && alpha.y == 0.0) {
+    t = make_double2(0.0, 0.0);
+    beta = alpha.x;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s2);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double ar = alpha.x - beta, ai = alpha.y;
+    const double den = ar * ar + ai * ai;
+    scale = make_double2(ar / den, -ai / den);
+  }
+  const bool lead = row == 0;
+  double ar = 0.0, ai = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = lane + 64 * r;
+    const double2 xv = xa[r];
+    const double2 v = j == 1 ? make_double2(1.0, 0.0)
+                             : make_double2(xv.x * scale.x - xv.y * scale.y, xv.x * scale.y + xv.y * scale.x);
+    if (lead && j >= 1 && j < len) vout[j - 1] = v;
+    if (lead && j < len) K[(k + 1 + j) + (int64_t)k * ldk] = va[r];
+    const double2 a = ca[r];  // zero past len
+    const bool use = j >= 1;
+    ar += use ? a.x * v.x + a.y * v.y : 0.0;  // conj(a) v
+    ai += use ? a.x * v.y - a.y * v.x : 0.0;
+    if (row < len - 1 && j < len) A[j + (int64_t)c * ldk] = a;
+  }
+  if (lead && lane == 0) {
+    tau[k + 1] = t;
+    d[k + 1] = xa[0].x;  // updated A22[0][0]
+    e[k + 1] = beta;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
+  }
+  if (row < len - 1 && lane == 0) yout[row] = make_double2(ar, ai);
+}
+
 __global__ void k_tridiag_tail(const double2* __restrict__ K, int ldk, int n, double* __restrict__ d,
                                double* __restrict__ e, double2* __restrict__ tau) {
   if (threadIdx.x == 0) {
@@ -1336,6 +1465,8 @@ struct HegvWs {
   double2* ybuf;  // 2 n: products published by the resident tridiagonalisation
   double2* xbuf;  // 2 n: columns published by it
   unsigned* bar;  // its grid-barrier counters
+  double2* y2;    // n: second y and v of the fused column steps
+  double2* v2;
 };
 
 static HegvWs hegv_ws(void* work, int n, int nev) {
@@ -1357,13 +1488,15 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   w.ybuf = reinterpret_cast<double2*>(p); p += al((size_t)2 * n * sizeof(double2));
   w.xbuf = reinterpret_cast<double2*>(p); p += al((size_t)2 * n * sizeof(double2));
   w.bar = reinterpret_cast<unsigned*>(p); p += al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
+  w.y2 = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
+  w.v2 = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
   return w;
 }
 
 size_t hegv_work(int n, int nev) {
   return al(potrf_work(n)) + 2 * al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
          al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16) +
-         2 * al((size_t)2 * n * 16) + al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
+         2 * al((size_t)2 * n * 16) + al((size_t)TRI_BAR_WORDS * sizeof(unsigned)) + 2 * al((size_t)n * 16);
 }
 
 // Launch shape of the resident tridiagonalisation: it takes the last m
@@ -1438,18 +1571,32 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   const TriPlan tp = tri_plan(n);
   const int klds = std::max(0, n - 1 - TAIL_MAX);  // first step of the LDS tail
   const int kres = tp.k0 >= 0 ? tp.k0 : klds;       // launches up to here
+  // Trailing sizes above 512: two launches per column (product, then
+  // update).  From 512 down, one launch per column after the first: the
+  // update of step k fused with the product of step k+1, and a last update.
   auto column_steps = [&](int kbeg, int kend) {
-    for (int k = kbeg; k < kend; ++k) {
+    int k = kbeg;
+    for (; k < kend && n - k - 1 > 512; ++k) {
       const int len = n - k - 1;
-      if (len <= 512)
-        hipLaunchKernelGGL(k_house_hemv_reg<8>, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k,
-                           ws.tau, ws.d, ws.e, ws.v, ws.y);
-      else
-        hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau,
-                           ws.d, ws.e, ws.v, ws.y);
+      hipLaunchKernelGGL(k_house_hemv, dim3((unsigned)ceil_div(len, 4)), dim3(256), 0, s, ws.K, n, n, k, ws.tau,
+                         ws.d, ws.e, ws.v, ws.y);
       hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
                          ws.K, n, n, k, ws.y, ws.tau, ws.v);
     }
+    if (k >= kend) return;
+    double2* vb[2] = {ws.v, ws.v2};
+    double2* yb[2] = {ws.y, ws.y2};
+    int p = 0;
+    hipLaunchKernelGGL(k_house_hemv_reg<8>, dim3((unsigned)ceil_div(n - k - 1, 4)), dim3(256), 0, s, ws.K, n, n, k,
+                       ws.tau, ws.d, ws.e, vb[p], yb[p]);
+    for (; k + 1 < kend; ++k, p ^= 1) {
+      const int len = n - k - 1;  // >= 2: k + 1 < kend <= n - 1
+      hipLaunchKernelGGL(k_her2_house_hemv_reg<8>, dim3((unsigned)ceil_div(len - 1, 4)), dim3(256), 0, s, ws.K, n,
+                         n, k, ws.tau, ws.d, ws.e, vb[p], yb[p], vb[p ^ 1], yb[p ^ 1]);
+    }
+    const int len = n - k - 1;
+    hipLaunchKernelGGL(k_her2, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(len, 32)), dim3(256), 0, s,
+                       ws.K, n, n, k, yb[p], ws.tau, vb[p]);
   };
   column_steps(0, kres);
   KS_LAUNCH_CHECK("tridiagonalisation");
