@@ -1502,11 +1502,11 @@ size_t hegv_work(int n, int nev) {
 // Launch shape of the resident tridiagonalisation: it takes the last m
 // steps, m as large as the LDS of the device's compute units holds
 // (c m double2 per workgroup, at most one workgroup per CU), aiming at
-// TRI_CTARGET columns per workgroup; steps before n-1-m run one column per
-// launch.  A step of the resident kernel costs about as much as the two
-// launches of a step below n = TRI_MIN_N (grid barrier and the round trips
-// of the published vectors; measured on MI355X: slower at n = 480, 11%
-// faster at n = 1440), so smaller problems keep one column per launch.
+// TRI_CTARGET columns per workgroup; steps before n-1-m run as column
+// launches.  A step of the resident kernel costs about as much as the two
+// launches of a column step (grid barrier and the round trips of the
+// published vectors; measured on MI355X: slower at n = 480, 11% faster at
+// n = 1440), so problems below n = TRI_MIN_N keep column launches.
 // k0 < 0: not used.
 struct TriPlan {
   int k0 = -1, G = 0, c = 0;
