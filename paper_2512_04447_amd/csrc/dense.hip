@@ -43,18 +43,20 @@ __global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, doub
 // Unblocked Cholesky of the diagonal block at k0 (kb <= NB columns) in LDS,
 // then the inverse of that block (for the panel and the triangular solves).
 // Step j updates the trailing block with the unscaled column j divided by
-// the pivot d_j; scaling column j by 1/sqrt(d_j) touches only column j, so it
-// runs in the same phase as the next step's update and one barrier per
-// column suffices.
+// the pivot d_j; no later step reads column j, so the scaling of every
+// column by 1/sqrt(d_j) waits until the end (one pass, off the chain of
+// steps) and a step is one LDS round trip and one barrier.
 __global__ void __launch_bounds__(256)
 k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restrict__ dmax,
         int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv) {
   __shared__ double2 a[NB][NB + 1];
-  if (*info != 0) return;
-  const double tol = CHOL_TOL * (*dmax);
-  // the block: unconditional loads (indices clamped into the block), padding
-  // zeroed afterwards, four in flight per thread
+  __shared__ double sq[NB];
+  // the block: unconditional loads (indices clamped into the block), issued
+  // together with the flag and the tolerance's scale; padding zeroed
+  // afterwards, four in flight per thread
   static_assert(NB * NB == 4 * 256, "four entries per thread");
+  const int32_t info0 = *info;
+  const double tol = CHOL_TOL * (*dmax);
   double2 v[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -62,6 +64,7 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     const int i = e % NB, j = e / NB;
     v[u] = S[(k0 + min(i, kb - 1)) + (int64_t)(k0 + min(j, kb - 1)) * lds];
   }
+  if (info0 != 0) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + 256 * u;
@@ -70,31 +73,51 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     a[i][j] = make_double2(in ? v[u].x : 0.0, in ? v[u].y : 0.0);
   }
   __syncthreads();
+  // thread t owns row i = t % NB of columns p = t / NB + 8u (u = 0..3)
+  const int ri = threadIdx.x % NB, pc = threadIdx.x / NB;
   for (int j = 0; j < kb; ++j) {
     const double d = a[j][j].x;
     if (!(d > tol)) {
       if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
       return;  // uniform: every thread read the same d
     }
-    // column j-1 was scaled in the previous phase by other threads: no
-    // thread reads it here.  Update a[i][p] -= a[i][j] conj(a[p][j]) / d.
+    // a[i][p] -= a[i][j] conj(a[p][j]) / d for j < p <= i < kb: every read
+    // first (in range: the padding is zero), then the guarded writes; no
+    // entry written here is read in this step
     const double rd = 1.0 / d;
+    const double2 x = a[ri][j];
+    double2 y[4], z[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int i = e % NB, p = e / NB;
-      if (p > j && i >= p && i < kb) {
-        const double2 x = a[i][j], y = a[p][j];
-        a[i][p].x -= (x.x * y.x + x.y * y.y) * rd;
-        a[i][p].y -= (x.y * y.x - x.x * y.y) * rd;
+      y[u] = a[pc + 8 * u][j];
+      z[u] = a[ri][pc + 8 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = pc + 8 * u;
+      if (p > j && ri >= p && ri < kb) {
+        a[ri][p].x = z[u].x - (x.x * y[u].x + x.y * y[u].y) * rd;
+        a[ri][p].y = z[u].y - (x.y * y[u].x - x.x * y[u].y) * rd;
       }
     }
-    // scale column j (entries i > j are read above only by this step)
     __syncthreads();
-    const double ljj = sqrt(d), rl = 1.0 / ljj;
-    for (int i = j + threadIdx.x; i < kb; i += blockDim.x) {
-      if (i == j) a[j][j] = make_double2(ljj, 0.0);
-      else { a[i][j].x *= rl; a[i][j].y *= rl; }
+  }
+  // L: column j scaled by 1/sqrt(d_j), the diagonal sqrt(d_j)
+  if (threadIdx.x < kb) sq[threadIdx.x] = sqrt(a[threadIdx.x][threadIdx.x].x);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int i = e % NB, j = e / NB;
+    if (j < kb && i >= j && i < kb) {
+      const double ljj = sq[j];
+      if (i == j) {
+        a[j][j] = make_double2(ljj, 0.0);
+      } else {
+        const double rl = 1.0 / ljj;
+        a[i][j].x *= rl;
+        a[i][j].y *= rl;
+      }
     }
   }
   __syncthreads();
