@@ -1402,11 +1402,13 @@ k_backtransform(const double2* __restrict__ K, int ldk, int n, const double2* __
 
 // The same product with the reflectors in registers: lane l holds the
 // entries l + 64 r (r < R) of the current reflector, uses them for both the
-// dot product and the update, and loads the next reflector (k - 1) while
-// the current one is applied, so that a reflector costs no dependent global
-// round trip.  Loads are unconditional from indices clamped into range,
-// zeroed afterwards.  Same arithmetic and summation order as
-// k_backtransform.  n - 1 <= 64 R.
+// dot product and the update, and loads the next reflector (k - 1) and its
+// tau while the current one is applied, so that a reflector costs no
+// dependent global round trip.  Global loads are unconditional from indices
+// clamped into range, the reflector's entries past its length zeroed
+// afterwards; the entries of z are read once per reflector, also from
+// clamped indices (their products with the zeroed entries add nothing).
+// Same arithmetic and summation order as k_backtransform.  n - 1 <= 64 R.
 template <int R>
 __global__ void __launch_bounds__(64)
 k_backtransform_reg(const double2* __restrict__ K, int ldk, int n, const double2* __restrict__ tau,
@@ -1429,33 +1431,42 @@ k_backtransform_reg(const double2* __restrict__ K, int ldk, int n, const double2
       V[r] = make_double2(in_ ? V[r].x : 0.0, in_ ? V[r].y : 0.0);                             \
     }                                                                                          \
   } while (0)
-  if (n >= 2) KS_BT_LOAD(vc, n - 2);
+  double2 tc = make_double2(0.0, 0.0);
+  if (n >= 2) {
+    KS_BT_LOAD(vc, n - 2);
+    tc = tau[n - 2];
+  }
   for (int k = n - 2; k >= 0; --k) {
-    if (k > 0) KS_BT_LOAD(vn, k - 1);
-    const double2 t = tau[k];
-    if (t.x != 0.0 || t.y != 0.0) {  // uniform across the wave
+    const int kn = max(k - 1, 0);  // k = 0 reloads reflector 0 (unused)
+    KS_BT_LOAD(vn, kn);
+    const double2 tn = tau[kn];
+    if (tc.x != 0.0 || tc.y != 0.0) {  // uniform across the wave
       const int len = n - k - 1;
       double2* zk = z + k + 1;
+      // up to R = 16 the entries of z stay in registers for the update;
+      // above, they are read again (registers hold two reflectors already)
+      constexpr bool keep = R <= 16;
+      double2 bz[keep ? R : 1];
       double sr = 0.0, si = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lane + 64 * r;
-        if (i < len) {
-          const double2 b = zk[i];
-          sr += vc[r].x * b.x + vc[r].y * b.y;  // conj(v) z
-          si += vc[r].x * b.y - vc[r].y * b.x;
-        }
+        const double2 b = zk[min(lane + 64 * r, len - 1)];
+        if constexpr (keep) bz[r] = b;
+        sr += vc[r].x * b.x + vc[r].y * b.y;  // conj(v) z
+        si += vc[r].x * b.y - vc[r].y * b.x;
       }
       for (int off = 32; off > 0; off >>= 1) {
         sr += __shfl_xor(sr, off, 64);
         si += __shfl_xor(si, off, 64);
       }
-      const double fr = t.x * sr - t.y * si, fi = t.x * si + t.y * sr;
+      const double fr = tc.x * sr - tc.y * si, fi = tc.x * si + tc.y * sr;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = lane + 64 * r;
         if (i < len) {
-          double2 b = zk[i];
+          double2 b;
+          if constexpr (keep) b = bz[r];
+          else b = zk[i];
           b.x -= fr * vc[r].x - fi * vc[r].y;
           b.y -= fr * vc[r].y + fi * vc[r].x;
           zk[i] = b;
@@ -1465,6 +1476,7 @@ k_backtransform_reg(const double2* __restrict__ K, int ldk, int n, const double2
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) vc[r] = vn[r];
+    tc = tn;
   }
 #undef KS_BT_LOAD
   for (int i = lane; i < n; i += 64) C[i + (int64_t)j * ldc] = z[i];

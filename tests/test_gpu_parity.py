@@ -136,10 +136,12 @@ def colmajor(A):
     return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().T
 
 
-# 1440: the subspace of the 216-atom cell (trailing matrix resident in LDS
-# from the first step); 1800: one column per launch first, then resident
-@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (33, 11), (48, 16), (100, 40), (480, 160), (1440, 480),
-                                   (1800, 600)])
+# 960: two launches per column while the trailing matrix is above 512, then
+# one per column, then the LDS tail; back-transform with 16 entries per
+# lane; 1440: the subspace of the 216-atom cell (trailing matrix resident in
+# LDS from the first step); 1800: one column per launch first, then resident
+@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (33, 11), (48, 16), (100, 40), (480, 160), (960, 320),
+                                   (1440, 480), (1800, 600)])
 def test_hegv_reduce_solve_matches_oracle(ks, n, nev):
     import torch
 
