@@ -136,12 +136,15 @@ def colmajor(A):
     return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().T
 
 
+# 97: the LDS tail alone (trailing matrix of 96); 98: one column step
+# (product, then update) before it; 99: one fused step between them;
+# 514: one two-launch step (trailing size 513), then fused steps from 512;
 # 960: two launches per column while the trailing matrix is above 512, then
 # one per column, then the LDS tail; back-transform with 16 entries per
 # lane; 1440: the subspace of the 216-atom cell (trailing matrix resident in
 # LDS from the first step); 1800: one column per launch first, then resident
-@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (33, 11), (48, 16), (100, 40), (480, 160), (960, 320),
-                                   (1440, 480), (1800, 600)])
+@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (33, 11), (48, 16), (97, 32), (98, 33), (99, 33),
+                                   (100, 40), (480, 160), (514, 171), (960, 320), (1440, 480), (1800, 600)])
 def test_hegv_reduce_solve_matches_oracle(ks, n, nev):
     import torch
 
