@@ -901,6 +901,10 @@ static int pass_b(const ks_plan& p, int mode, c2<T>* buf, int64_t ld, int nb, co
 template <typename T>
 static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2<T>* dc, hipStream_t s) {
   constexpr int NBT = 4;
+  // FP32 orbitals with at most 4 projectors per atom: 8 bands per tile, so
+  // that the support list and the projector values are read once per 8
+  // bands (their bytes per point exceed the orbitals' for 4 FP32 bands)
+  constexpr int NBT4 = sizeof(T) == 4 ? 8 : 4;
   dim3 grid(p.natoms, (unsigned)ceil_div(nb, NBT));
   TimerScope ts(KF_NL_PROJECT, s);
   const T* beta = static_cast<const T*>(p.beta);
@@ -909,8 +913,8 @@ static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2
     hipLaunchKernelGGL((k_nl_project<T, 1, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
                        p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
   else if (p.maxp <= 4)
-    hipLaunchKernelGGL((k_nl_project<T, 4, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
-                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+    hipLaunchKernelGGL((k_nl_project<T, 4, NBT4>), dim3(p.natoms, (unsigned)ceil_div(nb, NBT4)), dim3(kThreads), 0,
+                       s, psi, ld, nb, p.supp_ptr, p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
   else if (p.maxp <= 9)
     hipLaunchKernelGGL((k_nl_project<T, 9, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
                        p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
