@@ -902,8 +902,8 @@ template <typename T>
 static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2<T>* dc, hipStream_t s) {
   constexpr int NBT = 4;
   // FP32 orbitals with at most 4 projectors per atom: 8 bands per tile, so
-  // that the support list and the projector values are read once per 8
-  // bands (their bytes per point exceed the orbitals' for 4 FP32 bands)
+  // that the support list and the projector values (20 B per point, against
+  // 32 B of orbital values for 4 FP32 bands) are read once per 8 bands
   constexpr int NBT4 = sizeof(T) == 4 ? 8 : 4;
   dim3 grid(p.natoms, (unsigned)ceil_div(nb, NBT));
   TimerScope ts(KF_NL_PROJECT, s);
