@@ -281,7 +281,7 @@ def main():
         while it < 200:
             lob2.step(b.KS_PRECOND_TPA, 0.1 * tol)
             it += 1
-            th = lob2.theta[: cfg.ntrack].cpu().numpy()
+            th = lob2.theta_host[: cfg.ntrack]
             if np.abs(th - ref).max() <= 1e-6:
                 break
         torch.cuda.synchronize()

@@ -28,7 +28,8 @@
  *   device memory allocated by ks_plan_create and freed by ks_plan_destroy.
  * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
  *   stream ordered; a call returns once its work is enqueued, except where
- *   noted (lobpcg_init and lobpcg_step read 4 bytes back per subspace solve).
+ *   noted (ks_plan_create; lobpcg_init and lobpcg_step when given a host
+ *   summary buffer, which they fill with one copy and wait for).
  * Errors: every function returns 0 on success; -i when argument i (1-based)
  *   is invalid (checked on the host before any launch); KS_E_HIP - code for
  *   a HIP runtime error; KS_E_WORKSPACE when work_bytes is too small;
@@ -92,11 +93,16 @@ typedef struct ks_plan ks_plan;
 /* LOBPCG iteration state (Knyazev's [X, W, P] Rayleigh-Ritz; the paper's
  * eigensolver).  All block pointers are device blocks of plan->nb_max or
  * fewer columns with the common leading dimension ld.  X, AX (= H X), P, AP,
- * W, AW hold the iterate; Xn, AXn, Pn, APn and T1 are scratch blocks of the
- * same shape.  lobpcg_step swaps the pointer pairs (X,Xn), (AX,AXn),
- * (P,Pn), (AP,APn) and (W,Xn) as it goes: read them back after each call.
- * theta[nb] (Ritz values) and res[nb] (residual 2-norms of the block the
- * step started from) are device arrays of doubles. */
+ * W, AW hold the iterate; Xn, Pn and T1 are scratch blocks of the same
+ * shape.  lobpcg_step swaps the pointer pairs (X,Xn), (P,Pn) and (W,Xn) as
+ * it goes: read them back after each call.  theta[nb] (Ritz values) and
+ * res[nb] (residual 2-norms of the block the step started from) are device
+ * arrays of doubles; status is a device array of KS_STATUS_WORDS int32.
+ * host_summary (optional, host memory of 16*nb + 4*KS_STATUS_WORDS bytes,
+ * pinned for an asynchronous copy): when set, lobpcg_init and lobpcg_step
+ * end with one device-to-host copy of theta[nb], res[nb] (doubles) and the
+ * status words into it and wait for that copy; when NULL they never
+ * synchronise the stream. */
 typedef struct {
   int32_t nb;
   int32_t has_p;   /* 0 before the first step; set by lobpcg_step */
@@ -108,17 +114,31 @@ typedef struct {
   void* P;
   void* AP;
   void* Xn;
-  void* AXn;
   void* Pn;
-  void* APn;
   void* T1;
   double* theta;
   double* res;
-  int32_t iter;       /* iterations done */
-  int32_t last_info;  /* info of the last subspace solve (0 = ok) */
-  int32_t dropped_p;  /* times P was dropped after a failed Cholesky */
+  int32_t* status;
+  void* host_summary;
+  int32_t iter;    /* iterations done */
   int32_t pad_;
 } ks_lobpcg_state;
+
+/* Status words written by every lobpcg_init / lobpcg_step (cleared at its
+ * start).  Deflation: a column that depends numerically on the columns
+ * before it (Cholesky pivot not above 1e-14 of the largest diagonal entry)
+ * is dropped instead of stopping the iteration: in W or P it becomes an
+ * exactly-zero column, in the basis [X W P] it gets zero Ritz coefficients. */
+#define KS_STATUS_WORDS 8
+#define KS_ST_FLAGS 0      /* KS_FLAG_* bits */
+#define KS_ST_DEAD_W 1     /* W columns deflated by its orthonormalisation */
+#define KS_ST_DEAD_P 2     /* P columns deflated likewise */
+#define KS_ST_DEAD_BASIS 3 /* basis vectors dropped by the subspace Cholesky */
+#define KS_ST_DEAD_X 4     /* X columns deflated (initial Cholesky-QR, mixed re-orthonormalisation) */
+#define KS_ST_INFO 5       /* 0, or -1: the resident tridiagonalisation's grid barrier timed out */
+#define KS_FLAG_DEFLATED 1     /* some column was deflated (the step is still valid) */
+#define KS_FLAG_SOLVE_FAILED 2 /* KS_ST_INFO != 0: theta and the new block are not valid */
+#define KS_FLAG_NONFINITE 4    /* a Ritz value or residual norm is not finite */
 
 /* Preconditioner kinds.  KS_PRECOND_CNN applies the learned network below to
  * each residual (input channels Re r~, Im r~, h^2 (V_loc - theta_i), with
@@ -133,7 +153,7 @@ typedef struct {
 #define KS_PRECOND_CNN 2
 #define KS_PRECOND_CNN_TPA 3
 
-typedef struct {
+typedef struct ks_lobpcg_opts {
   int32_t precond;  /* KS_PRECOND_* */
   int32_t pad_;
   /* Soft locking: a band with residual norm <= lock_tol contributes an
@@ -150,10 +170,13 @@ typedef struct {
  * [sample][channel][Ng]. */
 #define KS_CNN_NPARAM 9106
 
-/* Which operation a workspace query is for. */
+/* Which operation a workspace query is for (KS_OP_PRECOND: ks_precond_apply
+ * with KS_PRECOND_NONE or KS_PRECOND_TPA; KS_OP_PRECOND_CNN: with the
+ * learned kinds). */
 #define KS_OP_APPLY_H 1
 #define KS_OP_PRECOND 2
 #define KS_OP_LOBPCG 3
+#define KS_OP_PRECOND_CNN 5
 
 /* Build a plan: radix schedules and twiddle tables for the three axes, the
  * projector tables in device memory (values in the plan's precision) plus
@@ -177,15 +200,24 @@ int ks_apply_h(const ks_plan* plan, const void* v_loc, const void* psi, int64_t 
                void* hpsi, int64_t ld_hpsi, int32_t nb, void* work, size_t work_bytes,
                void* stream);
 
-/* Residual and preconditioner: R = AX - X diag(theta); res[i] = ||r_i||_2;
- * W = K(R) where K is the identity (KS_PRECOND_NONE) or the Teter-Payne-
- * Allan kinetic preconditioner (KS_PRECOND_TPA: w_i = IFFT(K(x) FFT(r_i)),
- * x = T(G)/E_i, E_i = <x_i|T|x_i>, K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2
- * +8x^3+16x^4)).  Columns with res[i] <= lock_tol are written as zeros.
- * All blocks share ld. */
-int ks_precond_apply(const ks_plan* plan, int32_t kind, const void* X, const void* AX,
-                     const double* theta, int64_t ld, int32_t nb, double lock_tol,
-                     void* W, double* res, void* work, size_t work_bytes, void* stream);
+/* Residual and preconditioner (the preconditioned residuals are the W block
+ * of LOBPCG):  R = AX - X diag(theta);  res[i] = ||r_i||_2;  W = K(R) with
+ * K chosen by opts->precond:
+ *   KS_PRECOND_NONE: the identity;
+ *   KS_PRECOND_TPA: the Teter-Payne-Allan kinetic preconditioner,
+ *     w_i = IFFT(K(x) FFT(r_i)), x = T(G)/E_i, E_i = <x_i|T|x_i>,
+ *     K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4);
+ *   KS_PRECOND_CNN / KS_PRECOND_CNN_TPA: the learned network (below) with
+ *     parameters opts->cnn_params (device, KS_CNN_NPARAM floats) on r, or on
+ *     the TPA output with its skip connection.
+ * Columns with res[i] <= opts->lock_tol are written as zeros.  v_loc: Ng
+ * reals of the plan's precision (the network's third input channel; may be
+ * NULL for NONE and TPA).  All
+ * blocks share ld.  Workspace: ks_workspace_size(KS_OP_PRECOND) for NONE and
+ * TPA, ks_workspace_size(KS_OP_PRECOND_CNN) for the learned kinds. */
+int ks_precond_apply(const ks_plan* plan, const ks_lobpcg_opts* opts, const void* v_loc, const void* X,
+                     const void* AX, const double* theta, int64_t ld, int32_t nb, void* W, double* res, void* work,
+                     size_t work_bytes, void* stream);
 
 /* Generalised Hermitian eigensolve by the paper's reduction (Eq. 1 and the
  * paragraph after it), FP64 complex, column-major:
@@ -196,34 +228,57 @@ int ks_precond_apply(const ks_plan* plan, int32_t kind, const void* X, const voi
  * On return w[0..nev) ascending, C (n x nev, ldc) with C^H S C = I, S holds
  * L in its lower triangle and H is overwritten.  info_dev (device int32):
  * 0 ok; n + k if the leading minor k of S is not positive definite (pivot
- * <= 1e-14 * max diag(S)), then w and C are not written; -1 if the grid
- * barrier of the resident tridiagonalisation (n >= 1024, one cooperative
- * launch, co-residency guaranteed by the runtime) gave up after its bounded
- * wait, then w and C are not valid.  n <= 3700 (inverse iteration keeps 44
- * bytes per row in LDS), so ks_plan_create accepts nb_max <= 1233. */
+ * <= 1e-14 * max diag(S)); -1 if the grid barrier of the resident
+ * tridiagonalisation (n >= 1024, one cooperative launch, co-residency
+ * guaranteed by the runtime) gave up after its bounded wait.  When info is
+ * not 0, w and C are left unchanged (the work after the factorisation still
+ * runs on the device, on values that are then discarded).  n <= 3700
+ * (inverse iteration keeps 44 bytes per row in LDS), so ks_plan_create
+ * accepts nb_max <= 1233. */
 int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds,
                       double* w, void* C, int32_t ldc, void* work, size_t work_bytes,
                       int32_t* info_dev, void* stream);
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes);
 
 /* LOBPCG start: X <- X L^-H with L = chol(X^H X) (Cholesky-QR of the initial
- * block in st->X), AX = H X, Rayleigh-Ritz on span(X): X <- X Z, AX <- AX Z,
- * theta = Ritz values ascending.  Sets st->has_p = 0, st->iter = 0. */
+ * block in st->X), AX = H X, Rayleigh-Ritz on span(X): X <- X Z, then
+ * AX = H X by a fresh H-apply; theta = Ritz values ascending.  Sets
+ * st->has_p = 0, st->iter = 0 and the status words (res is not written). */
 int lobpcg_init(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st, void* work,
                 size_t work_bytes, void* stream);
 
-/* One LOBPCG iteration:
- *   R = AX - X Theta, res;  W = K(R) with soft-locked columns zeroed;
- *   W <- W D L^-H (unit columns, then Cholesky-QR within the block);
- *   AW = H W;  P, AP masked by the lock mask and orthonormalised the same way;
- *   S = V^H V, H = V^H AV for V = [X W P] (Hermitised; zero columns decoupled);
- *   hegv_reduce_solve -> Theta, C (on a failed Cholesky P is dropped and the
- *   solve repeated);  X <- V C, AX <- AV C, P <- V_{[W P]} C_{[W P]}, AP likewise.
- * On the mixed plans X is then re-orthonormalised (FP64 Cholesky-QR of X
- * with the matching update of AX).  Reads the 4-byte info of each subspace
- * solve back to the host. */
+/* One LOBPCG iteration, as the oracle's reading of Knyazev's method:
+ *   1. R = AX - X Theta, res = column norms of R;  W = K(R) (ks_precond_apply
+ *      with opts), zero for soft-locked bands (res <= lock_tol);
+ *   2. W <- W - X (X^H W), then W <- W D L^-H (unit columns, Cholesky-QR
+ *      within the block, deflating);
+ *   3. AW = H W;
+ *   4. (from the second step) P masked by the lock test, orthonormalised as
+ *      W, AP = H P;
+ *   5. S = V^H V, H = V^H AV for V = [X W P] (or [X W]), Hermitised; exactly
+ *      zero columns decoupled (S_kk = 1, H_kk = 2 max|H_ii| + 1);
+ *   6. lowest nb eigenpairs of H C = S C Theta by the reduction of
+ *      hegv_reduce_solve with a deflating Cholesky (numerically dependent
+ *      basis vectors get zero coefficients);
+ *   7. X <- V C, P <- V_{[W P]} C_{[W P]};
+ *   8. mixed plans: X <- X L^-H (Cholesky-QR, FP64 factor);
+ *   9. AX = H X by a fresh H-apply (AP is formed afresh in the next step).
+ * Status words as above; no host synchronisation unless st->host_summary
+ * is set. */
 int lobpcg_step(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st,
                 const ks_lobpcg_opts* opts, void* work, size_t work_bytes, void* stream);
+
+/* Convergence check by subspace angles: the sine of the largest principal
+ * angle between the column spans of A and B (k orthonormal columns each,
+ * the plan's precision, leading dimension ld),
+ *   sin_max = sqrt(1 - sigma_min(A^H B)^2),
+ * with A^H B from the Gram kernel and sigma_min^2 the lowest eigenvalue of
+ * (A^H B)^H (A^H B) from the dense eigensolve (accurate to about 1e-7 in
+ * sin_max).  Written to the device double *sin_max (NaN if the eigensolve
+ * reports a failure).  k <= nb_max.  Workspace: ks_workspace_size(KS_OP_ANGLE, k). */
+#define KS_OP_ANGLE 6
+int ks_subspace_sin(const ks_plan* plan, const void* A, const void* B, int64_t ld, int32_t k, double* sin_max,
+                    void* work, size_t work_bytes, void* stream);
 
 /* Training targets for the learned preconditioner: for every column i at
  * once, solve the Jacobi-Davidson correction equation

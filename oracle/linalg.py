@@ -43,6 +43,33 @@ def cholesky_lower(S: np.ndarray, rel_tol: float = CHOL_REL_TOL):
     return L, 0
 
 
+def cholesky_lower_deflate(S: np.ndarray, rel_tol: float = CHOL_REL_TOL):
+    """Cholesky with deflation of dependent columns, S ~ L L^H.
+
+    The Crout recurrence of ``cholesky_lower``, except that a column whose
+    pivot d_k = S_kk - sum_j |L_kj|^2 is not above rel_tol * max_i S_ii is
+    declared dead instead of stopping: L_kk = 1 and L_ik = 0 below it, so it
+    takes no part in the later columns.  The live columns then hold exactly
+    the Cholesky factor of S restricted to the live indices (a greedy choice
+    from the left of a maximal well-conditioned set of basis vectors).
+    Returns (L, dead) with dead a boolean mask.
+    """
+    S = np.asarray(S, dtype=np.complex128)
+    n = S.shape[0]
+    L = np.zeros_like(S)
+    dead = np.zeros(n, dtype=bool)
+    dmax = float(np.max(np.real(np.diag(S)))) if n else 0.0
+    for k in range(n):
+        d = float(np.real(S[k, k]) - np.sum(np.abs(L[k, :k]) ** 2))
+        if not (d > rel_tol * dmax):
+            dead[k] = True
+            L[k, k] = 1.0
+            continue
+        L[k, k] = math.sqrt(d)
+        L[k + 1:, k] = (S[k + 1:, k] - L[k + 1:, :k] @ np.conj(L[k, :k])) / L[k, k]
+    return L, dead
+
+
 def solve_lower(L: np.ndarray, B: np.ndarray) -> np.ndarray:
     """Y with L Y = B, forward substitution row by row."""
     n = L.shape[0]
@@ -162,3 +189,25 @@ def hegv_two_trsm(H: np.ndarray, S: np.ndarray, nev: int):
     w, Z = jacobi_eigh(K)
     C = solve_lower_conj_t(L, Z[:, :nev])
     return w[:nev], C, 0
+
+
+def hegv_two_trsm_deflate(H: np.ndarray, S: np.ndarray, nev: int):
+    """The reduction of ``hegv_two_trsm`` on a possibly singular S.
+
+    Columns that ``cholesky_lower_deflate`` declares dead are dropped from the
+    basis: the pencil restricted to the live indices is solved exactly as in
+    ``hegv_two_trsm`` (its Cholesky factor is the live part of L), and the
+    coefficients of the dead basis vectors are zero.  Needs at least nev live
+    columns.  Returns (w[:nev], C, ndead).
+    """
+    n = H.shape[0]
+    _, dead = cholesky_lower_deflate(S)
+    live = np.nonzero(~dead)[0]
+    if len(live) < nev:
+        raise np.linalg.LinAlgError("fewer independent basis vectors than wanted eigenpairs")
+    w, Cl, info = hegv_two_trsm(H[np.ix_(live, live)], S[np.ix_(live, live)], nev)
+    if info:
+        raise np.linalg.LinAlgError("live block not positive definite")  # unreachable: same pivots
+    C = np.zeros((n, nev), dtype=np.complex128)
+    C[live] = Cl
+    return w, C, int(np.sum(dead))

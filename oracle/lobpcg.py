@@ -19,21 +19,22 @@ Readings of points the paper leaves open (each listed in the design notes):
 * W and P are each orthonormalised *within their own block* before the Gram
   matrices are formed: columns are scaled to unit length (a zero column
   stays zero), then B <- B L^-H with L L^H = B^H B (Cholesky-QR; a zero
-  column gets a unit pivot).  If that Cholesky fails the block is
-  orthonormalised through the eigen-decomposition of its Gram matrix
-  instead (SVQB, Stathopoulos and Wu, SIAM J. Sci. Comput. 23 (2002)):
-  directions with eigenvalue below 1e-12 of the largest become zero
-  columns.  Without this the basis loses rank as the
-  residuals fall and the iteration stalls near 1e-6 (Hetmaniuk and
-  Lehoucq, "Basis selection in LOBPCG", J. Comput. Phys. 218 (2006),
-  analyse the same loss).
+  column gets a unit pivot).  The Cholesky deflates: a column whose pivot
+  is not above 1e-14 of the largest diagonal entry depends numerically on
+  the columns before it and becomes a zero column (the Cholesky-QR of the
+  remaining ones is exact).  Without this orthonormalisation the basis
+  loses rank as the residuals fall and the iteration stalls near 1e-6
+  (Hetmaniuk and Lehoucq, "Basis selection in LOBPCG", J. Comput. Phys. 218
+  (2006), analyse the same loss).
 * No orthogonalisation *across* blocks, so S != I (the X-W, X-P and W-P
   blocks are full) and the Cholesky plus two-solve reduction does real work.
 * A zero column k of [W, P] is decoupled from the subspace problem:
   S_kk = 1 and H_kk = 2 max_i |H_ii| + 1 (its other entries are exactly
   zero), so it sits above every retained Ritz value and gets zero weight.
-* On a Cholesky failure of the subspace overlap the P block is dropped and
-  the reduction is retried; a second failure is an error.
+* The Cholesky of the subspace overlap deflates in the same way: a basis
+  vector that depends numerically on the vectors before it in [X, W, P] is
+  dropped (zero Ritz coefficients), and the reduction and eigensolve run on
+  the remaining ones.  No step of the iteration is repeated.
 * H_s and S_s are Hermitised, (A + A^H)/2, before the reduction.
 * AX and AP are formed by applying H to the new X and P every iteration,
   not by rotating AV with the Ritz coefficients: the rotated products drift
@@ -51,11 +52,8 @@ from typing import Callable, Optional
 import numpy as np
 
 from .hamiltonian import OracleCell, apply_h
-from .linalg import cholesky_lower, hegv_two_trsm, jacobi_eigh, solve_lower
+from .linalg import cholesky_lower, cholesky_lower_deflate, hegv_two_trsm_deflate, jacobi_eigh, solve_lower
 from .precond import band_kinetic_energy, tpa_apply
-
-
-SVQB_TOL = 1e-12
 
 
 def _herm(A: np.ndarray) -> np.ndarray:
@@ -115,9 +113,10 @@ def orthonormalise_block(B: np.ndarray, AB: Optional[np.ndarray] = None):
     """Unit-normalise the columns of B, then Cholesky-QR: B <- B D L^-H.
 
     D = diag(1/||b_i||) (0 for a zero column) and L L^H = D B^H B D with a
-    unit pivot for zero columns.  AB (= H B) receives the same transform.
-    Returns (B', AB', info); on a Cholesky failure (info > 0) the block
-    is orthonormalised by SVQB instead.
+    unit pivot for zero columns, from the deflating Cholesky: a dead
+    (numerically dependent) column becomes a zero column, the live ones are
+    orthonormalised by the live part of L.  AB (= H B) receives the same
+    transform.  Returns (B', AB', number of dead columns).
     """
     nrm = np.linalg.norm(B, axis=1)
     d = np.where(nrm > 0.0, 1.0 / np.where(nrm > 0.0, nrm, 1.0), 0.0)
@@ -126,21 +125,16 @@ def orthonormalise_block(B: np.ndarray, AB: Optional[np.ndarray] = None):
     G = _herm(gram(Bs, Bs))
     zero = np.real(np.diag(G)) == 0.0
     G[zero, zero] = 1.0
-    L, info = cholesky_lower(G)
-    if info:
-        # SVQB: G = U diag(lam) U^H; keep lam > svqb_tol * max(lam), B <- Bs U lam^-1/2
-        # with the columns of dropped directions set to zero
-        Gs = G.copy()
-        Gs[zero, zero] = 0.0  # zero columns stay zero directions (dropped)
-        lam, U = jacobi_eigh(Gs)
-        keep = lam > SVQB_TOL * np.max(lam)
-        M = np.where(keep[None, :], U / np.sqrt(np.where(keep, lam, 1.0))[None, :], 0.0)
-        Bq = rotate(Bs, M)
-        ABq = None if ABs is None else rotate(ABs, M)
-        return Bq, ABq, info
-    Bq = np.conj(solve_lower(L, np.conj(Bs)))
-    ABq = None if ABs is None else np.conj(solve_lower(L, np.conj(ABs)))
-    return Bq, ABq, 0
+    L, dead = cholesky_lower_deflate(G)
+    live = np.nonzero(~dead)[0]
+    Ll = L[np.ix_(live, live)]
+    Bq = np.zeros_like(Bs)
+    Bq[live] = np.conj(solve_lower(Ll, np.conj(Bs[live])))
+    ABq = None
+    if ABs is not None:
+        ABq = np.zeros_like(ABs)
+        ABq[live] = np.conj(solve_lower(Ll, np.conj(ABs[live])))
+    return Bq, ABq, int(np.sum(dead))
 
 
 def decouple_zero_columns(Hs: np.ndarray, Ss: np.ndarray):
@@ -165,32 +159,26 @@ def step(cell: OracleCell, st: State, precond: Optional[Callable] = None,
     R = R * active[:, None]
     W = R if precond is None else precond(R, st)
     W = W - rotate(st.X, gram(st.X, W))
-    W, _, info = orthonormalise_block(W)
-    if info:
-        events.append("w_not_orthonormalised")
+    W, _, ndead = orthonormalise_block(W)
+    if ndead:
+        events.append(f"w_deflated_{ndead}")
     AW = apply_h(cell, W)
     blocks = [st.X, W]
     ablocks = [st.AX, AW]
     if st.P is not None:
-        P, _, info = orthonormalise_block(st.P * active[:, None])
-        if info:
-            events.append("p_not_orthonormalised")
+        P, _, ndead = orthonormalise_block(st.P * active[:, None])
+        if ndead:
+            events.append(f"p_deflated_{ndead}")
         blocks.append(P)
         ablocks.append(apply_h(cell, P))
-    while True:
-        V = np.concatenate(blocks, axis=0)
-        AV = np.concatenate(ablocks, axis=0)
-        Ss = _herm(gram(V, V))
-        Hs = _herm(gram(V, AV))
-        Hs, Ss, _ = decouple_zero_columns(Hs, Ss)
-        w, C, info = hegv_two_trsm(Hs, Ss, nb)
-        if info == 0:
-            break
-        if len(blocks) == 3:
-            events.append("dropped_p")
-            blocks, ablocks = blocks[:2], ablocks[:2]
-            continue
-        raise np.linalg.LinAlgError(f"subspace overlap not positive definite (info={info})")
+    V = np.concatenate(blocks, axis=0)
+    AV = np.concatenate(ablocks, axis=0)
+    Ss = _herm(gram(V, V))
+    Hs = _herm(gram(V, AV))
+    Hs, Ss, _ = decouple_zero_columns(Hs, Ss)
+    w, C, ndead = hegv_two_trsm_deflate(Hs, Ss, nb)
+    if ndead:
+        events.append(f"basis_deflated_{ndead}")
     Xn = rotate(V, C)
     Pn = rotate(V[nb:], C[nb:])
     return State(Xn, apply_h(cell, Xn), w.copy(), Pn, None, st.iteration + 1, st.events + events)

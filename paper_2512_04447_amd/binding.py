@@ -7,8 +7,10 @@ shared library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -19,7 +21,11 @@ LIB_PATH = os.path.join(HERE, "libksh.so")
 KS_FP64, KS_MIXED_FP32, KS_MIXED_BF16X3 = 0, 1, 2
 KS_PRECOND_NONE, KS_PRECOND_TPA, KS_PRECOND_CNN, KS_PRECOND_CNN_TPA = 0, 1, 2, 3
 KS_CNN_NPARAM = 9106
-KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD = 1, 2, 3, 4
+KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD, KS_OP_PRECOND_CNN, KS_OP_ANGLE = 1, 2, 3, 4, 5, 6
+# status words of a LOBPCG step
+KS_STATUS_WORDS = 8
+KS_ST_FLAGS, KS_ST_DEAD_W, KS_ST_DEAD_P, KS_ST_DEAD_BASIS, KS_ST_DEAD_X, KS_ST_INFO = range(6)
+KS_FLAG_DEFLATED, KS_FLAG_SOLVE_FAILED, KS_FLAG_NONFINITE = 1, 2, 4
 KS_E_HIP, KS_E_WORKSPACE, KS_E_NUMERIC, KS_E_UNSUPPORTED = -1000, -2001, -2002, -2003
 
 EXPORTS = (
@@ -28,6 +34,7 @@ EXPORTS = (
     "ks_workspace_size",
     "ks_apply_h",
     "ks_precond_apply",
+    "ks_subspace_sin",
     "hegv_reduce_solve",
     "hegv_workspace_size",
     "lobpcg_init",
@@ -81,15 +88,13 @@ class KsLobpcgState(C.Structure):
         ("P", C.c_void_p),
         ("AP", C.c_void_p),
         ("Xn", C.c_void_p),
-        ("AXn", C.c_void_p),
         ("Pn", C.c_void_p),
-        ("APn", C.c_void_p),
         ("T1", C.c_void_p),
         ("theta", C.c_void_p),
         ("res", C.c_void_p),
+        ("status", C.c_void_p),
+        ("host_summary", C.c_void_p),
         ("iter", C.c_int32),
-        ("last_info", C.c_int32),
-        ("dropped_p", C.c_int32),
         ("pad_", C.c_int32),
     ]
 
@@ -103,6 +108,21 @@ class KsError(RuntimeError):
 
 
 _lib = None
+# Plans alive in this process; destroyed by an exit hook while the HIP
+# runtime is still up (a plan's tables must not be freed from a finaliser
+# that runs during interpreter or runtime teardown).
+_live_plans = weakref.WeakSet()
+_exiting = False
+
+
+def _destroy_live_plans():
+    global _exiting
+    for plan in list(_live_plans):
+        plan.destroy()
+    _exiting = True
+
+
+atexit.register(_destroy_live_plans)
 
 
 def load() -> C.CDLL:
@@ -118,7 +138,8 @@ def load() -> C.CDLL:
     lib.ks_plan_destroy.argtypes = [vp]
     lib.ks_workspace_size.argtypes = [vp, i32, i32, C.POINTER(sz)]
     lib.ks_apply_h.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, sz, vp]
-    lib.ks_precond_apply.argtypes = [vp, i32, vp, vp, vp, i64, i32, C.c_double, vp, vp, vp, sz, vp]
+    lib.ks_precond_apply.argtypes = [vp, C.POINTER(KsLobpcgOpts), vp, vp, vp, vp, i64, i32, vp, vp, vp, sz, vp]
+    lib.ks_subspace_sin.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
     lib.hegv_reduce_solve.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp, vp]
     lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
     lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
@@ -223,6 +244,7 @@ class Plan:
                                 self.precision, C.c_void_p(_stream(stream)))
         check(rc, "ks_plan_create")
         self.handle = h
+        _live_plans.add(self)
 
     @property
     def complex_dtype(self):
@@ -242,11 +264,17 @@ class Plan:
         return int(n.value)
 
     def destroy(self):
+        """Free the plan's device tables now (idempotent)."""
         if getattr(self, "handle", None):
             load().ks_plan_destroy(self.handle)
             self.handle = None
+        _live_plans.discard(self)
 
     def __del__(self):  # pragma: no cover
+        # after the exit hook has run, a finaliser frees nothing: the exit
+        # hook destroyed every live plan already
+        if _exiting:
+            return
         try:
             self.destroy()
         except Exception:
@@ -265,15 +293,47 @@ def ks_apply_h(plan: Plan, v, psi, hpsi, nb: int | None = None, work=None, strea
     return hpsi
 
 
-def ks_precond_apply(plan: Plan, kind: int, X, AX, theta, W, res, lock_tol: float = 0.0, work=None, stream=None):
+def _opts(precond: int, lock_tol: float, cnn_params=None) -> KsLobpcgOpts:
+    o = KsLobpcgOpts()
+    o.precond = int(precond)
+    o.lock_tol = float(lock_tol)
+    if cnn_params is not None:
+        if cnn_params.numel() != KS_CNN_NPARAM:
+            raise KsError("cnn_params must hold KS_CNN_NPARAM values")
+        o.cnn_params = _ptr(cnn_params)
+    return o
+
+
+def ks_precond_apply(plan: Plan, kind: int, X, AX, theta, W, res, lock_tol: float = 0.0, v=None, cnn_params=None,
+                     work=None, stream=None):
+    """W = K(AX - X diag(theta)) and res = its column norms; the learned
+    kinds need v (the local potential) and cnn_params."""
     nb = X.shape[0]
-    need = plan.workspace_size(KS_OP_PRECOND, nb)
+    learned = kind in (KS_PRECOND_CNN, KS_PRECOND_CNN_TPA)
+    need = plan.workspace_size(KS_OP_PRECOND_CNN if learned else KS_OP_PRECOND, nb)
     if work is None:
         work = _work(need, X.device)
-    rc = load().ks_precond_apply(plan.handle, kind, _ptr(X), _ptr(AX), _ptr(theta), X.stride(0), nb, float(lock_tol),
-                                 _ptr(W), _ptr(res), _ptr(work), work.numel(), C.c_void_p(_stream(stream)))
+    o = _opts(kind, lock_tol, cnn_params)
+    rc = load().ks_precond_apply(plan.handle, C.byref(o), None if v is None else _ptr(v), _ptr(X), _ptr(AX),
+                                 _ptr(theta), X.stride(0), nb, _ptr(W), _ptr(res), _ptr(work), work.numel(),
+                                 C.c_void_p(_stream(stream)))
     check(rc, "ks_precond_apply")
     return W
+
+
+def ks_subspace_sin(plan: Plan, A, B, k: int, out=None, work=None, stream=None):
+    """Device double: sine of the largest principal angle between the spans
+    of the first k rows (columns of the blocks) of A and B."""
+    import torch
+
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=A.device)
+    if work is None:
+        work = _work(plan.workspace_size(KS_OP_ANGLE, k), A.device)
+    rc = load().ks_subspace_sin(plan.handle, _ptr(A), _ptr(B), A.stride(0), int(k), _ptr(out), _ptr(work),
+                                work.numel(), C.c_void_p(_stream(stream)))
+    check(rc, "ks_subspace_sin")
+    return out
 
 
 def kernel_timer(enable: bool, family: int) -> None:
@@ -306,16 +366,22 @@ def hegv_reduce_solve(H, S, nev: int, w, Cmat, info, work=None, stream=None):
 
 
 class Lobpcg:
-    """Device buffers of one LOBPCG run and the calls that advance it."""
+    """Device buffers of one LOBPCG run and the calls that advance it.
 
-    BLOCKS = ("X", "AX", "W", "AW", "P", "AP", "Xn", "AXn", "Pn", "APn", "T1")
+    With ``summary=True`` (the default) every init/step ends with the one
+    device-to-host copy of (theta, res, status) into pinned host memory,
+    readable afterwards as ``theta_host``, ``res_host`` and ``status_host``;
+    with ``summary=False`` the calls never wait for the device."""
 
-    def __init__(self, plan: Plan, v, X0, stream=None):
+    BLOCKS = ("X", "AX", "W", "AW", "P", "AP", "Xn", "Pn", "T1")
+
+    def __init__(self, plan: Plan, v, X0, stream=None, summary: bool = True):
         import torch
 
         self.plan = plan
         self.v = v
         nb = X0.shape[0]
+        self.nb = nb
         dev = X0.device
         self.buf = {}
         for name in self.BLOCKS:
@@ -323,6 +389,7 @@ class Lobpcg:
         self.buf["X"].copy_(X0)
         self.theta = torch.zeros(nb, dtype=torch.float64, device=dev)
         self.res = torch.zeros(nb, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(KS_STATUS_WORDS, dtype=torch.int32, device=dev)
         self.work = _work(plan.workspace_size(KS_OP_LOBPCG, nb), dev)
         self._by_ptr = {_ptr(t): t for t in self.buf.values()}
         st = KsLobpcgState()
@@ -332,6 +399,11 @@ class Lobpcg:
             setattr(st, name, _ptr(self.buf[name]))
         st.theta = _ptr(self.theta)
         st.res = _ptr(self.res)
+        st.status = _ptr(self.status)
+        self.summary = None
+        if summary:
+            self.summary = torch.zeros(16 * nb + 4 * KS_STATUS_WORDS, dtype=torch.uint8, pin_memory=True)
+            st.host_summary = self.summary.data_ptr()
         self.st = st
         self.stream = stream
 
@@ -346,16 +418,29 @@ class Lobpcg:
     def step(self, precond: int = KS_PRECOND_TPA, lock_tol: float = 0.0, cnn_params=None):
         """One iteration; ``cnn_params`` (FP32 device tensor of KS_CNN_NPARAM
         values) is required for KS_PRECOND_CNN and KS_PRECOND_CNN_TPA."""
-        o = KsLobpcgOpts()
-        o.precond = precond
-        o.lock_tol = float(lock_tol)
-        if cnn_params is not None:
-            if cnn_params.numel() != KS_CNN_NPARAM:
-                raise KsError("cnn_params must hold KS_CNN_NPARAM values")
-            o.cnn_params = _ptr(cnn_params)
+        o = _opts(precond, lock_tol, cnn_params)
         rc = load().lobpcg_step(self.plan.handle, _ptr(self.v), C.byref(self.st), C.byref(o), _ptr(self.work),
                                 self.work.numel(), C.c_void_p(_stream(self.stream)))
         check(rc, "lobpcg_step")
+
+    def _summary_np(self):
+        if self.summary is None:
+            raise KsError("this run has no host summary buffer")
+        return self.summary.numpy()
+
+    @property
+    def theta_host(self):
+        """Ritz values from the last call's summary copy (numpy, no device access)."""
+        return self._summary_np()[: 8 * self.nb].view(np.float64).copy()
+
+    @property
+    def res_host(self):
+        """Residual norms of the block the last step started from (numpy)."""
+        return self._summary_np()[8 * self.nb: 16 * self.nb].view(np.float64).copy()
+
+    @property
+    def status_host(self):
+        return self._summary_np()[16 * self.nb:].view(np.int32).copy()
 
     @property
     def X(self):

@@ -239,23 +239,17 @@ __global__ void k_identity(double2* __restrict__ A, int lda, int n) {
   }
 }
 
-// M = D Y (rows scaled) if the Cholesky succeeded, else M = D.  Written in the
-// block precision.
+// M = D Y (rows scaled), written in the block precision.  Y = L^-H from the
+// deflating Cholesky has zero rows and columns for dead columns, so those
+// columns of the orthonormalised block are exactly zero.
 template <typename T>
 __global__ void k_cholqr_coef(const double2* __restrict__ Y, int ldy, int n, const double* __restrict__ dvec,
-                              const int32_t* __restrict__ info, c2<T>* __restrict__ M, int ldm) {
+                              c2<T>* __restrict__ M, int ldm) {
   const int64_t total = (int64_t)n * n;
-  const bool ok = *info == 0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % n), j = (int)(e / n);
-    double2 v;
-    if (ok) {
-      const double2 y = Y[i + (int64_t)j * ldy];
-      v = make_double2(dvec[i] * y.x, dvec[i] * y.y);
-    } else {
-      v = make_double2(i == j ? dvec[i] : 0.0, 0.0);
-    }
-    M[i + (int64_t)j * ldm] = cmake<c2<T>>((T)v.x, (T)v.y);
+    const double2 y = Y[i + (int64_t)j * ldy];
+    M[i + (int64_t)j * ldm] = cmake<c2<T>>((T)(dvec[i] * y.x), (T)(dvec[i] * y.y));
   }
 }
 
@@ -302,11 +296,51 @@ __global__ void k_copy_d(const double2* __restrict__ src, int ld_src, double2* _
 static unsigned grid_for(int64_t total) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 4096)); }
 
 // ---------------------------------------------------------------- workspace
+// Buffers of the residual + preconditioner stage besides its FFT scratch
+// block: partial sums and kinetic energies (TPA), and the learned network's
+// band chunk (inputs, activations, outputs, non-finite flags, column norms).
+struct PrecondWs {
+  double* partial = nullptr;
+  double* E = nullptr;
+  int cnn_chunk = 0;
+  float* cnn_x = nullptr;    // chunk x 3 x Ng
+  float* cnn_buf = nullptr;  // chunk x 32 x Ng
+  float* cnn_y = nullptr;    // chunk x 2 x Ng
+  int32_t* cnn_bad = nullptr;
+  double* cnn_norm = nullptr;  // nb column norms of the TPA output
+  double* cnn_part = nullptr;  // column-norm partial sums of one chunk
+};
+
+static char* precond_layout(const ks_plan& p, char* q, int nb, bool cnn, PrecondWs& w) {
+  auto take = [&](size_t bytes) { char* r = q; q += al(bytes); return r; };
+  const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
+  const size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p.zc));
+  w.partial = reinterpret_cast<double*>(take((size_t)nb * cnt * 8));
+  w.E = reinterpret_cast<double*>(take((size_t)nb * 8));
+  if (cnn) {
+    w.cnn_chunk = std::min(nb, 32);
+    w.cnn_x = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 3 * p.Ng * 4));
+    w.cnn_buf = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 32 * p.Ng * 4));
+    w.cnn_y = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 2 * p.Ng * 4));
+    w.cnn_bad = reinterpret_cast<int32_t*>(take((size_t)w.cnn_chunk * 4));
+    w.cnn_norm = reinterpret_cast<double*>(take((size_t)nb * 8));
+    w.cnn_part = reinterpret_cast<double*>(take(column_norms_partial(w.cnn_chunk) * 8));
+  }
+  return q;
+}
+
+// ks_precond_apply's workspace: the FFT scratch block, then PrecondWs.
+static size_t precond_full_work_bytes(const ks_plan& p, int nb, bool cnn) {
+  static char probe alignas(256);
+  const size_t es = p.prec == KS_FP64 ? 16 : 8;
+  PrecondWs w;
+  char* end = precond_layout(p, &probe + al((size_t)p.Ng * nb * es), nb, cnn, w);
+  return (size_t)(end - &probe);
+}
+
 struct LobWs {
   double2* S;   // m x m
   double2* H;
-  double2* S0;
-  double2* H0;
   double2* C;   // m x nb (FP64)
   void* Cb;     // m x nb block precision
   double2* G;   // nb x nb
@@ -314,24 +348,18 @@ struct LobWs {
   void* M;      // nb x nb block precision
   double* dvec; // nb
   double* wnew; // m
-  double* lam;  // nb, SVQB eigenvalues
-  int32_t* info;  // 4 ints
-  double* partial;
-  double* E;
+  int32_t* info;  // 4 ints of scratch
+  void* summary;  // theta, res (nb doubles each) and the status words, packed for one read
   void* dc;
   void* gram;
   void* hegv;
   void* potrf;
   double2* ttmp;
-  int cnn_chunk;
-  float* cnn_x;    // chunk x 3 x Ng
-  float* cnn_buf;  // chunk x 32 x Ng
-  float* cnn_y;    // chunk x 2 x Ng
-  int32_t* cnn_bad; // chunk flags: non-finite network output
-  double* cnn_norm;  // nb column norms of the TPA output
-  double* cnn_part;  // column-norm partial sums of one chunk
+  PrecondWs pw;
   char* end;
 };
+
+static size_t summary_bytes(int nb) { return (size_t)16 * nb + KS_STATUS_WORDS * 4; }
 
 static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   const int m = 3 * nb;
@@ -341,8 +369,6 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   auto take = [&](size_t bytes) { char* r = q; q += al(bytes); return r; };
   w.S = reinterpret_cast<double2*>(take((size_t)m * m * 16));
   w.H = reinterpret_cast<double2*>(take((size_t)m * m * 16));
-  w.S0 = reinterpret_cast<double2*>(take((size_t)m * m * 16));
-  w.H0 = reinterpret_cast<double2*>(take((size_t)m * m * 16));
   w.C = reinterpret_cast<double2*>(take((size_t)m * nb * 16));
   w.Cb = take((size_t)m * nb * es);
   w.G = reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
@@ -350,24 +376,14 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.M = take((size_t)nb * nb * es);
   w.dvec = reinterpret_cast<double*>(take((size_t)nb * 8));
   w.wnew = reinterpret_cast<double*>(take((size_t)m * 8));
-  w.lam = reinterpret_cast<double*>(take((size_t)nb * 8));
   w.info = reinterpret_cast<int32_t*>(take(16));
-  const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
-  const size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p.zc));
-  w.partial = reinterpret_cast<double*>(take((size_t)nb * cnt * 8));
-  w.E = reinterpret_cast<double*>(take((size_t)nb * 8));
+  w.summary = take(summary_bytes(nb));
   w.dc = take((size_t)nb * std::max(p.nproj, 1) * es);
   w.gram = take(gram_work_bytes(m, p.Ng));
   w.hegv = take(hegv_work(m, nb));
   w.potrf = take(potrf_work(nb));
   w.ttmp = reinterpret_cast<double2*>(take((size_t)32 * std::max(nb, 1) * 16));
-  w.cnn_chunk = std::min(nb, 32);
-  w.cnn_x = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 3 * p.Ng * 4));
-  w.cnn_buf = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 32 * p.Ng * 4));
-  w.cnn_y = reinterpret_cast<float*>(take((size_t)w.cnn_chunk * 2 * p.Ng * 4));
-  w.cnn_bad = reinterpret_cast<int32_t*>(take((size_t)w.cnn_chunk * 4));
-  w.cnn_norm = reinterpret_cast<double*>(take((size_t)nb * 8));
-  w.cnn_part = reinterpret_cast<double*>(take(column_norms_partial(w.cnn_chunk) * 8));
+  q = precond_layout(p, q, nb, true, w.pw);
   w.end = q;
   return w;
 }
@@ -377,6 +393,45 @@ static size_t lobpcg_work_bytes(const ks_plan& p, int nb) {
   static char probe alignas(256);
   LobWs w = lob_ws(p, &probe, nb);
   return (size_t)(w.end - &probe);
+}
+
+// ks_subspace_sin's workspace
+struct AngleWs {
+  double2* G;  // k x k
+  double2* M;  // k x k
+  double2* S;  // k x k identity
+  double2* C;  // k
+  double* w;
+  int32_t* info;
+  void* gram;
+  void* hegv;
+  char* end;
+};
+
+static AngleWs angle_ws(const ks_plan& p, void* work, int k) {
+  char* q = static_cast<char*>(work);
+  AngleWs w;
+  auto take = [&](size_t bytes) { char* r = q; q += al(bytes); return r; };
+  w.G = reinterpret_cast<double2*>(take((size_t)k * k * 16));
+  w.M = reinterpret_cast<double2*>(take((size_t)k * k * 16));
+  w.S = reinterpret_cast<double2*>(take((size_t)k * k * 16));
+  w.C = reinterpret_cast<double2*>(take((size_t)k * 16));
+  w.w = reinterpret_cast<double*>(take(8));
+  w.info = reinterpret_cast<int32_t*>(take(16));
+  w.gram = take(gram_work_bytes(k, p.Ng));
+  w.hegv = take(hegv_work(k, 1));
+  w.end = q;
+  return w;
+}
+
+static size_t angle_work_bytes(const ks_plan& p, int k) {
+  static char probe alignas(256);
+  return (size_t)(angle_ws(p, &probe, k).end - &probe);
+}
+
+__global__ void k_sin_from_sigma2(const double* __restrict__ w, const int32_t* __restrict__ info,
+                                  double* __restrict__ out) {
+  if (threadIdx.x == 0) *out = *info != 0 ? __longlong_as_double(0x7ff8000000000000ll) : sqrt(fmax(0.0, 1.0 - *w));
 }
 
 // ---------------------------------------------------------------- LOBPCG pieces
@@ -391,41 +446,65 @@ static BlockList<c2<T>> blist(const void* a, const void* b, const void* c, int64
   return L;
 }
 
-__global__ void k_zero_dead_diag(double2* __restrict__ G, int ldg, int n, const double* __restrict__ dvec) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && dvec[i] == 0.0) G[i + (int64_t)i * ldg] = make_double2(0.0, 0.0);
-}
-
-static int read_info(const int32_t* dev, int32_t* host, hipStream_t s) {
-  KS_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  KS_HIP(hipStreamSynchronize(s));
+template <typename T>
+static int subspace_sin(const ks_plan& p, const void* A, const void* B, int64_t ld, int k, double* out, void* work,
+                        hipStream_t s) {
+  AngleWs w = angle_ws(p, work, k);
+  int rc;
+  auto LA = blist<T>(A, nullptr, nullptr, ld, k);
+  auto LB = blist<T>(B, nullptr, nullptr, ld, k);
+  if ((rc = gram_general<T>(LA, LB, k, p.Ng, w.G, k, w.gram, s))) return rc;
+  if ((rc = zgemm('C', 'N', k, k, k, 1.0, w.G, k, w.G, k, 0.0, w.M, k, s))) return rc;
+  hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)k * k)), dim3(256), 0, s, w.S, k, k);
+  if ((rc = hegv(k, 1, w.M, k, w.S, k, w.w, w.C, k, w.hegv, w.info, nullptr, s))) return rc;
+  hipLaunchKernelGGL(k_sin_from_sigma2, dim3(1), dim3(64), 0, s, w.w, w.info, out);
+  KS_LAUNCH_CHECK("subspace_sin");
   return 0;
 }
 
-// SVQB coefficients: M[:, j] = d .* U[:, j] / sqrt(lam_j) when lam_j > tol *
-// lam_max, else zero (lam ascending, so lam_max = lam[n-1]).
-template <typename T>
-__global__ void k_svqb_coef(const double2* __restrict__ U, int ldu, int n, const double* __restrict__ lam,
-                            const double* __restrict__ dvec, double tol, c2<T>* __restrict__ M, int ldm) {
-  const int64_t total = (int64_t)n * n;
-  const double lmax = lam[n - 1];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    const bool keep = lam[j] > tol * lmax;
-    const double sc = keep ? dvec[i] / sqrt(lam[j]) : 0.0;
-    const double2 u = U[i + (int64_t)j * ldu];
-    M[i + (int64_t)j * ldm] = cmake<c2<T>>((T)(sc * u.x), (T)(sc * u.y));
+__global__ void k_status_clear(int32_t* __restrict__ st) {
+  if (threadIdx.x < KS_STATUS_WORDS) st[threadIdx.x] = 0;
+}
+
+// Flags of the step from its counters, the subspace solve's info and the
+// finiteness of theta and res (res may be null); then theta, res and the
+// status words packed into `summary` for one device-to-host copy.
+__global__ void __launch_bounds__(256)
+k_finish_status(int32_t* __restrict__ st, const double* __restrict__ theta, const double* __restrict__ res, int nb,
+                unsigned char* __restrict__ summary) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int my = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const double t = theta[i];
+    if (!isfinite(t) || (res && !isfinite(res[i]))) my = 1;
+  }
+  if (my) atomicOr(&bad, 1);
+  __syncthreads();
+  double* sd = reinterpret_cast<double*>(summary);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    sd[i] = theta[i];
+    sd[nb + i] = res ? res[i] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    int f = 0;
+    if (st[KS_ST_DEAD_W] + st[KS_ST_DEAD_P] + st[KS_ST_DEAD_BASIS] + st[KS_ST_DEAD_X] > 0) f |= KS_FLAG_DEFLATED;
+    if (st[KS_ST_INFO] != 0) f |= KS_FLAG_SOLVE_FAILED;
+    if (bad) f |= KS_FLAG_NONFINITE;
+    st[KS_ST_FLAGS] = f;
+    int32_t* si = reinterpret_cast<int32_t*>(sd + 2 * nb);
+    for (int k = 0; k < KS_STATUS_WORDS; ++k) si[k] = st[k];
   }
 }
 
 // B <- B D L^-H (columns scaled to unit norm, then Cholesky-QR), written to
-// out (and AB to aout when given).  If the Cholesky fails the block is
-// orthonormalised through the eigenvectors of its scaled Gram matrix (SVQB)
-// and directions with eigenvalue below svqb_tol * max become zero columns;
-// this reads the Cholesky info back to the host.
+// out.  The Cholesky deflates: a column that depends numerically on the
+// ones before it becomes an exactly-zero column (counted in *ndead).  No
+// host synchronisation.
 template <typename T>
-static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B, const void* AB, void* out, void* aout,
-                                int64_t ld, int nb, const double* res, double lock_tol, hipStream_t s) {
+static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B, void* out, int64_t ld, int nb,
+                                const double* res, double lock_tol, int32_t* ndead, hipStream_t s) {
   int rc;
   auto L1 = blist<T>(B, nullptr, nullptr, ld, nb);
   if ((rc = gram<T>(L1, L1, nullptr, nb, p.Ng, w.G, nb, nullptr, 0, w.gram, s))) return rc;
@@ -433,38 +512,58 @@ static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B,
                      w.dvec);
   hipLaunchKernelGGL(k_scale_gram, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.G, nb, nb, w.dvec);
   KS_LAUNCH_CHECK("colscale");
-  // keep the scaled Gram for the SVQB fallback, zero columns with a zero
-  // diagonal so that they are dropped exactly
-  hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.G, nb, w.H0, nb, nb, nb);
-  hipLaunchKernelGGL(k_zero_dead_diag, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, w.H0, nb, nb, w.dvec);
-  if ((rc = potrf(nb, w.G, nb, w.potrf, w.info + 1, s))) return rc;
-  int32_t hinfo = 0;
-  if ((rc = read_info(w.info + 1, &hinfo, s))) return rc;
-  if (hinfo == 0) {
-    hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb);
-    if ((rc = trsm('C', nb, nb, w.G, nb, w.Y, nb, w.potrf, w.ttmp, w.info + 1, s))) return rc;
-    hipLaunchKernelGGL((k_cholqr_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb, w.dvec,
-                       w.info + 1, static_cast<c2<T>*>(w.M), nb);
-    KS_LAUNCH_CHECK("cholqr_coef");
-  } else {
-    hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.S0, nb, nb);
-    if ((rc = hegv(nb, nb, w.H0, nb, w.S0, nb, w.lam, w.C, nb, w.hegv, w.info + 2, s))) return rc;
-    // S0 = I: only the tridiagonalisation's barrier can fail here
-    if (nb >= hegv_resident_min_n()) {
-      int32_t sinfo = 0;
-      if ((rc = read_info(w.info + 2, &sinfo, s))) return rc;
-      if (sinfo != 0) return fail(KS_E_NUMERIC, "SVQB eigensolve failed");
-    }
-    const double tol = p.prec == KS_FP64 ? 1e-12 : 1e-6;
-    hipLaunchKernelGGL((k_svqb_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.C, nb, nb, w.lam,
-                       w.dvec, tol, static_cast<c2<T>*>(w.M), nb);
-    KS_LAUNCH_CHECK("svqb_coef");
-  }
+  if ((rc = potrf_deflate(nb, w.G, nb, w.potrf, w.info + 1, ndead, s))) return rc;
+  hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb);
+  if ((rc = trsm('C', nb, nb, w.G, nb, w.Y, nb, w.potrf, w.ttmp, w.info + 1, s))) return rc;
+  hipLaunchKernelGGL((k_cholqr_coef<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb, w.dvec,
+                     static_cast<c2<T>*>(w.M), nb);
+  KS_LAUNCH_CHECK("cholqr_coef");
   const auto* M = static_cast<const c2<T>*>(w.M);
-  if ((rc = rotate<T>(L1, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(out), nullptr, ld, s))) return rc;
-  if (AB) {
-    auto L2 = blist<T>(AB, nullptr, nullptr, ld, nb);
-    if ((rc = rotate<T>(L2, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(aout), nullptr, ld, s))) return rc;
+  return rotate<T>(L1, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(out), nullptr, ld, s);
+}
+
+// Residual, norms and preconditioned residual W (lock-masked), for every
+// preconditioner kind: the learned ones run the network on the residual
+// (KS_PRECOND_CNN) or on the TPA output with the skip connection
+// (KS_PRECOND_CNN_TPA), in band chunks.  tmp: one Ng x nb scratch block.
+template <typename T>
+static int precond_full(const ks_plan& p, int kind_full, double lock_tol, const float* cnn_params, const T* v,
+                        const c2<T>* X, const c2<T>* AX, const double* theta, int64_t ld, int nb, c2<T>* W,
+                        double* res, c2<T>* tmp, const PrecondWs& pw, hipStream_t s) {
+  const bool learned = kind_full == KS_PRECOND_CNN || kind_full == KS_PRECOND_CNN_TPA;
+  const int kind = kind_full == KS_PRECOND_CNN ? KS_PRECOND_NONE
+                   : kind_full == KS_PRECOND_CNN_TPA ? KS_PRECOND_TPA
+                                                     : kind_full;
+  int rc;
+  if ((rc = precond_apply<T>(p, kind, X, AX, theta, ld, nb, lock_tol, W, res, tmp, pw.partial, pw.E, s))) return rc;
+  if (!learned) return 0;
+  const bool skip = kind_full == KS_PRECOND_CNN_TPA;
+  for (int b0 = 0; b0 < nb; b0 += pw.cnn_chunk) {
+    const int nc = std::min(pw.cnn_chunk, nb - b0);
+    c2<T>* R = W + (int64_t)b0 * ld;
+    const double* nrm = res + b0;
+    if (skip) {
+      if ((rc = column_norms<T>(R, ld, nc, p.Ng, pw.cnn_part, pw.cnn_norm + b0, s))) return rc;
+      nrm = pw.cnn_norm + b0;
+    }
+    if ((rc = cnn_input_impl<T>(p, R, ld, nrm, v, theta + b0, nc, pw.cnn_x, s))) return rc;
+    if ((rc = cnn_infer_impl(p, cnn_params, nc, pw.cnn_x, pw.cnn_y, pw.cnn_buf, s))) return rc;
+    if (skip && (rc = cnn_skip_impl(p, nc, pw.cnn_x, pw.cnn_y, s))) return rc;
+    if ((rc = cnn_output_impl<T>(p, pw.cnn_y, nc, res + b0, lock_tol, pw.cnn_bad, R, ld, s))) return rc;
+  }
+  return 0;
+}
+
+// theta <- the new Ritz values, status flags, and (with a host summary
+// buffer) the one device-to-host copy of the step, then a wait for it.
+static int finish_step(const LobWs& w, ks_lobpcg_state* st, const double* res, int nb, hipStream_t s) {
+  KS_HIP(hipMemcpyAsync(st->theta, w.wnew, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_finish_status, dim3(1), dim3(256), 0, s, st->status, st->theta, res, nb,
+                     static_cast<unsigned char*>(w.summary));
+  KS_LAUNCH_CHECK("finish_status");
+  if (st->host_summary) {
+    KS_HIP(hipMemcpyAsync(st->host_summary, w.summary, summary_bytes(nb), hipMemcpyDeviceToHost, s));
+    KS_HIP(hipStreamSynchronize(s));
   }
   return 0;
 }
@@ -475,13 +574,11 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
   const int64_t ld = st->ld;
   LobWs w = lob_ws(p, work, nb);
   int rc;
-  // Cholesky-QR of the start block
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, s, st->status);
+  // Cholesky-QR of the start block (a dependent column would become zero)
   auto LX = blist<T>(st->X, nullptr, nullptr, ld, nb);
   if ((rc = gram<T>(LX, LX, nullptr, nb, p.Ng, w.G, nb, nullptr, 0, w.gram, s))) return rc;
-  if ((rc = potrf(nb, w.G, nb, w.potrf, w.info + 1, s))) return rc;
-  int32_t hinfo = 0;
-  if ((rc = read_info(w.info + 1, &hinfo, s))) return rc;
-  if (hinfo != 0) return fail(KS_E_NUMERIC, "initial block is rank deficient");
+  if ((rc = potrf_deflate(nb, w.G, nb, w.potrf, w.info + 1, st->status + KS_ST_DEAD_X, s))) return rc;
   hipLaunchKernelGGL(k_identity, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb, nb);
   if ((rc = trsm('C', nb, nb, w.G, nb, w.Y, nb, w.potrf, w.ttmp, w.info + 1, s))) return rc;
   hipLaunchKernelGGL((k_to_block<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.Y, nb,
@@ -500,9 +597,9 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
   auto L1 = blist<T>(st->X, nullptr, nullptr, ld, nb);
   auto L2 = blist<T>(st->AX, nullptr, nullptr, ld, nb);
   if ((rc = gram<T>(L1, L1, &L2, nb, p.Ng, w.S, nb, w.H, nb, w.gram, s))) return rc;
-  if ((rc = hegv(nb, nb, w.H, nb, w.S, nb, w.wnew, w.C, nb, w.hegv, w.info, s))) return rc;
-  if ((rc = read_info(w.info, &hinfo, s))) return rc;
-  if (hinfo != 0) return fail(KS_E_NUMERIC, "Rayleigh-Ritz of the initial block failed");
+  if ((rc = hegv(nb, nb, w.H, nb, w.S, nb, w.wnew, w.C, nb, w.hegv, st->status + KS_ST_INFO,
+                 st->status + KS_ST_DEAD_BASIS, s)))
+    return rc;
   hipLaunchKernelGGL((k_to_block<T>), dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.C, nb,
                      static_cast<c2<T>*>(w.Cb), nb, nb, nb);
   const auto* Cb = static_cast<const c2<T>*>(w.Cb);
@@ -513,12 +610,9 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
                        static_cast<c2<T>*>(st->AX), ld, nb, static_cast<c2<T>*>(st->T1), static_cast<c2<T>*>(w.dc),
                        s)))
     return rc;
-  KS_HIP(hipMemcpyAsync(st->theta, w.wnew, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
   st->has_p = 0;
   st->iter = 0;
-  st->last_info = 0;
-  st->dropped_p = 0;
-  return 0;
+  return finish_step(w, st, nullptr, nb, s);
 }
 
 template <typename T>
@@ -529,39 +623,18 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   LobWs w = lob_ws(p, work, nb);
   int rc;
   using T2 = c2<T>;
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, s, st->status);
   // 1. residual, its norms, preconditioned and lock-masked W (into Xn)
-  const bool learned = o->precond == KS_PRECOND_CNN || o->precond == KS_PRECOND_CNN_TPA;
-  const int kind = o->precond == KS_PRECOND_CNN ? KS_PRECOND_NONE
-                   : o->precond == KS_PRECOND_CNN_TPA ? KS_PRECOND_TPA
-                                                      : o->precond;
-  if ((rc = precond_apply<T>(p, kind, static_cast<const T2*>(st->X), static_cast<const T2*>(st->AX), st->theta, ld,
-                             nb, o->lock_tol, static_cast<T2*>(st->Xn), st->res, static_cast<T2*>(st->T1), w.partial,
-                             w.E, s)))
+  if ((rc = precond_full<T>(p, o->precond, o->lock_tol, o->cnn_params, static_cast<const T*>(v),
+                            static_cast<const T2*>(st->X), static_cast<const T2*>(st->AX), st->theta, ld, nb,
+                            static_cast<T2*>(st->Xn), st->res, static_cast<T2*>(st->T1), w.pw, s)))
     return rc;
-  if (learned) {
-    // learned preconditioner, in band chunks, on the residual (CNN) or on
-    // the TPA output with the skip connection (CNN_TPA)
-    const bool skip = o->precond == KS_PRECOND_CNN_TPA;
-    for (int b0 = 0; b0 < nb; b0 += w.cnn_chunk) {
-      const int nc = std::min(w.cnn_chunk, nb - b0);
-      T2* R = static_cast<T2*>(st->Xn) + (int64_t)b0 * ld;
-      const double* nrm = st->res + b0;
-      if (skip) {
-        if ((rc = column_norms<T>(R, ld, nc, p.Ng, w.cnn_part, w.cnn_norm + b0, s))) return rc;
-        nrm = w.cnn_norm + b0;
-      }
-      if ((rc = cnn_input_impl<T>(p, R, ld, nrm, static_cast<const T*>(v), st->theta + b0, nc, w.cnn_x, s)))
-        return rc;
-      if ((rc = cnn_infer_impl(p, o->cnn_params, nc, w.cnn_x, w.cnn_y, w.cnn_buf, s))) return rc;
-      if (skip && (rc = cnn_skip_impl(p, nc, w.cnn_x, w.cnn_y, s))) return rc;
-      if ((rc = cnn_output_impl<T>(p, w.cnn_y, nc, st->res + b0, o->lock_tol, w.cnn_bad, R, ld, s))) return rc;
-    }
-  }
   // 2. W <- W - X (X^H W), then W <- W D L^-H
   if ((rc = project_out<T>(static_cast<const T2*>(st->X), static_cast<const T2*>(st->Xn), static_cast<T2*>(st->W), ld,
                            nb, p.Ng, w.G, w.Cb, w.gram, s)))
     return rc;
-  if ((rc = block_orthonormalise<T>(p, w, st->W, nullptr, st->Xn, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
+  if ((rc = block_orthonormalise<T>(p, w, st->W, st->Xn, ld, nb, nullptr, 0.0, st->status + KS_ST_DEAD_W, s)))
+    return rc;
   std::swap(st->W, st->Xn);
   // 3. AW = H W
   if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->W), ld, static_cast<T2*>(st->AW), ld,
@@ -569,7 +642,8 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
     return rc;
   // 4. P, AP masked and orthonormalised
   if (st->has_p) {
-    if ((rc = block_orthonormalise<T>(p, w, st->P, nullptr, st->Pn, nullptr, ld, nb, st->res, o->lock_tol, s)))
+    if ((rc = block_orthonormalise<T>(p, w, st->P, st->Pn, ld, nb, st->res, o->lock_tol, st->status + KS_ST_DEAD_P,
+                                      s)))
       return rc;
     std::swap(st->P, st->Pn);
     if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->P), ld, static_cast<T2*>(st->AP), ld,
@@ -577,37 +651,17 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
       return rc;
   }
   // 5. subspace matrices
-  const int mfull = st->has_p ? 3 * nb : 2 * nb;
+  const int m = st->has_p ? 3 * nb : 2 * nb;
   auto LV = blist<T>(st->X, st->W, st->P, ld, nb);
   auto LAV = blist<T>(st->AX, st->AW, st->AP, ld, nb);
-  if ((rc = gram<T>(LV, LV, &LAV, mfull, p.Ng, w.S, mfull, w.H, mfull, w.gram, s))) return rc;
-  hipLaunchKernelGGL(k_decouple, dim3(1), dim3(256), 0, s, w.S, mfull, w.H, mfull, mfull);
+  if ((rc = gram<T>(LV, LV, &LAV, m, p.Ng, w.S, m, w.H, m, w.gram, s))) return rc;
+  hipLaunchKernelGGL(k_decouple, dim3(1), dim3(256), 0, s, w.S, m, w.H, m, m);
   KS_LAUNCH_CHECK("decouple");
-  if (st->has_p) {
-    hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)mfull * mfull)), dim3(256), 0, s, w.S, mfull, w.S0, mfull,
-                       mfull, mfull);
-    hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)mfull * mfull)), dim3(256), 0, s, w.H, mfull, w.H0, mfull,
-                       mfull, mfull);
-  }
-  // 6. reduction and eigensolve; drop P on a failed Cholesky
-  int m = mfull;
-  if ((rc = hegv(m, nb, w.H, mfull, w.S, mfull, w.wnew, w.C, m, w.hegv, w.info, s))) return rc;
-  int32_t hinfo = 0;
-  if ((rc = read_info(w.info, &hinfo, s))) return rc;
-  if (hinfo < 0) return fail(KS_E_NUMERIC, "subspace eigensolve: tridiagonalisation grid barrier timed out");
-  if (hinfo != 0 && st->has_p) {
-    st->dropped_p += 1;
-    m = 2 * nb;
-    hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)mfull * mfull)), dim3(256), 0, s, w.S0, mfull, w.S, mfull,
-                       mfull, mfull);
-    hipLaunchKernelGGL(k_copy_d, dim3(grid_for((int64_t)mfull * mfull)), dim3(256), 0, s, w.H0, mfull, w.H, mfull,
-                       mfull, mfull);
-    if ((rc = hegv(m, nb, w.H, mfull, w.S, mfull, w.wnew, w.C, m, w.hegv, w.info, s))) return rc;
-    if ((rc = read_info(w.info, &hinfo, s))) return rc;
-    if (hinfo < 0) return fail(KS_E_NUMERIC, "subspace eigensolve: tridiagonalisation grid barrier timed out");
-  }
-  st->last_info = hinfo;
-  if (hinfo != 0) return fail(KS_E_NUMERIC, "subspace overlap is not positive definite");
+  // 6. reduction and eigensolve; basis vectors that depend numerically on
+  // earlier ones are dropped by the deflating Cholesky
+  if ((rc = hegv(m, nb, w.H, m, w.S, m, w.wnew, w.C, m, w.hegv, st->status + KS_ST_INFO,
+                 st->status + KS_ST_DEAD_BASIS, s)))
+    return rc;
   // 7. rotation: X <- V C and P <- V[:, nb:] C[nb:, :] in one pass over V
   hipLaunchKernelGGL((k_to_block<T>), dim3(grid_for((int64_t)m * nb)), dim3(256), 0, s, w.C, m,
                      static_cast<T2*>(w.Cb), m, m, nb);
@@ -619,17 +673,41 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   std::swap(st->P, st->Pn);
   // 8. mixed plans: FP64-factor Cholesky-QR of X
   if (p.prec != KS_FP64) {
-    if ((rc = block_orthonormalise<T>(p, w, st->X, nullptr, st->Xn, nullptr, ld, nb, nullptr, 0.0, s))) return rc;
+    if ((rc = block_orthonormalise<T>(p, w, st->X, st->Xn, ld, nb, nullptr, 0.0, st->status + KS_ST_DEAD_X, s)))
+      return rc;
     std::swap(st->X, st->Xn);
   }
   // 9. AX by a fresh H-apply (AP is formed the same way next step)
   if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->X), ld, static_cast<T2*>(st->AX), ld,
                        nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))
     return rc;
-  KS_HIP(hipMemcpyAsync(st->theta, w.wnew, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
   st->has_p = 1;
   st->iter += 1;
-  return 0;
+  return finish_step(w, st, st->res, nb, s);
+}
+
+// The projector set's CSR structure, checked on the host before any table
+// is built from it: both atom pointer arrays start at 0, never decrease and
+// end at the totals; every value block has |S_a| * p_a entries; support
+// indices lie on the grid; at most 9 projectors per atom (the widest
+// projection kernel).  Returns the reason, or nullptr when valid.
+static const char* check_projset(const ks_projset& ps, int64_t Ng) {
+  if (ps.n_atoms < 0 || ps.n_proj < 0 || ps.n_supp < 0) return "negative projector set sizes";
+  const int32_t* sp = ps.atom_supp_ptr;
+  const int32_t* pp = ps.atom_proj_ptr;
+  const int64_t* bp = ps.beta_ptr;
+  if (sp[0] != 0 || pp[0] != 0 || bp[0] != 0) return "projector CSR pointers must start at 0";
+  for (int a = 0; a < ps.n_atoms; ++a) {
+    if (sp[a + 1] < sp[a] || pp[a + 1] < pp[a]) return "projector CSR pointers decrease";
+    const int np = pp[a + 1] - pp[a];
+    if (np > 9) return "more than 9 projectors per atom";
+    if (bp[a + 1] - bp[a] != (int64_t)np * (sp[a + 1] - sp[a]))
+      return "beta_ptr does not match |S_a| * projectors of an atom";
+  }
+  if (pp[ps.n_atoms] != ps.n_proj || sp[ps.n_atoms] != ps.n_supp) return "projector CSR pointers inconsistent";
+  for (int64_t i = 0; i < ps.n_supp; ++i)
+    if (ps.supp_idx[i] < 0 || ps.supp_idx[i] >= Ng) return "support index out of the grid";
+  return nullptr;
 }
 
 }  // namespace ks
@@ -693,6 +771,18 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
     p->fft.twopi_over_L[a] = 2.0 * M_PI / grid->L[a];
     p->Ng *= grid->n[a];
   }
+  // the projector set is checked before any device work
+  if (proj && proj->n_proj > 0) {
+    const char* why = nullptr;
+    if (!proj->atom_supp_ptr || !proj->supp_idx || !proj->atom_proj_ptr || !proj->beta_ptr || !proj->beta || !proj->D)
+      why = "projector set has null arrays";
+    else
+      why = check_projset(*proj, p->Ng);
+    if (why) {
+      delete p;
+      return fail(-3, why);
+    }
+  }
   const size_t es = precision == KS_FP64 ? 16 : 8;
   const int n0 = grid->n[0], n1 = grid->n[1], n2 = grid->n[2];
   const int plane = n1 * n2;
@@ -724,19 +814,6 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   for (int a = 0; a < 3 && rc == 0; ++a)
     rc = precision == KS_FP64 ? upload_twiddles<double>(grid->n[a], &p->tw[a]) : upload_twiddles<float>(grid->n[a], &p->tw[a]);
   if (rc == 0 && proj && proj->n_proj > 0) {
-    if (!proj->atom_supp_ptr || !proj->supp_idx || !proj->atom_proj_ptr || !proj->beta_ptr || !proj->beta || !proj->D) {
-      ks_plan_destroy(p);
-      return fail(-3, "projector set has null arrays");
-    }
-    for (int64_t i = 0; i < proj->n_supp; ++i)
-      if (proj->supp_idx[i] < 0 || proj->supp_idx[i] >= p->Ng) {
-        ks_plan_destroy(p);
-        return fail(-3, "support index out of the grid");
-      }
-    if (proj->atom_proj_ptr[proj->n_atoms] != proj->n_proj || proj->atom_supp_ptr[proj->n_atoms] != proj->n_supp) {
-      ks_plan_destroy(p);
-      return fail(-3, "projector CSR pointers inconsistent");
-    }
     rc = precision == KS_FP64 ? upload_proj<double>(p, proj) : upload_proj<float>(p, proj);
   }
   if (rc) {
@@ -765,7 +842,9 @@ int ks_workspace_size(const ks_plan* p, int32_t op, int32_t nb, size_t* bytes) {
   if (!bytes) return fail(-4, "bytes is null");
   switch (op) {
     case KS_OP_APPLY_H: *bytes = apply_h_work_bytes(*p, nb); return 0;
-    case KS_OP_PRECOND: *bytes = precond_work_bytes(*p, nb); return 0;
+    case KS_OP_PRECOND: *bytes = precond_full_work_bytes(*p, nb, false); return 0;
+    case KS_OP_PRECOND_CNN: *bytes = precond_full_work_bytes(*p, nb, true); return 0;
+    case KS_OP_ANGLE: *bytes = angle_work_bytes(*p, nb); return 0;
     case KS_OP_LOBPCG: *bytes = lobpcg_work_bytes(*p, nb); return 0;
     case KS_OP_JD: *bytes = jd_work_bytes(*p, nb); return 0;
     default: return fail(-2, "unknown op");
@@ -798,33 +877,55 @@ int ks_apply_h(const ks_plan* p, const void* v_loc, const void* psi, int64_t ld_
                         reinterpret_cast<float2*>(dc), s);
 }
 
-int ks_precond_apply(const ks_plan* p, int32_t kind, const void* X, const void* AX, const double* theta, int64_t ld,
-                     int32_t nb, double lock_tol, void* W, double* res, void* work, size_t work_bytes, void* stream) {
+int ks_precond_apply(const ks_plan* p, const ks_lobpcg_opts* opts, const void* v_loc, const void* X, const void* AX,
+                     const double* theta, int64_t ld, int32_t nb, void* W, double* res, void* work, size_t work_bytes,
+                     void* stream) {
   g_last_error.clear();
   if (!p) return fail(-1, "plan is null");
-  if (kind != KS_PRECOND_NONE && kind != KS_PRECOND_TPA) return fail(-2, "unknown preconditioner");
-  if (!X) return fail(-3, "X is null");
-  if (!AX) return fail(-4, "AX is null");
-  if (!theta) return fail(-5, "theta is null");
-  if (ld < p->Ng) return fail(-6, "ld < Ng");
-  if (nb <= 0 || nb > p->nb_max) return fail(-7, "nb out of range");
+  if (!opts) return fail(-2, "opts is null");
+  const int kind = opts->precond;
+  if (kind != KS_PRECOND_NONE && kind != KS_PRECOND_TPA && kind != KS_PRECOND_CNN && kind != KS_PRECOND_CNN_TPA)
+    return fail(-2, "unknown preconditioner");
+  const bool learned = kind == KS_PRECOND_CNN || kind == KS_PRECOND_CNN_TPA;
+  if (learned && !opts->cnn_params) return fail(-2, "CNN preconditioner without parameters");
+  if (learned && !v_loc) return fail(-3, "v_loc is null (the learned kinds read the local potential)");
+  if (!X) return fail(-4, "X is null");
+  if (!AX) return fail(-5, "AX is null");
+  if (!theta) return fail(-6, "theta is null");
+  if (ld < p->Ng) return fail(-7, "ld < Ng");
+  if (nb <= 0 || nb > p->nb_max) return fail(-8, "nb out of range");
   if (!W) return fail(-9, "W is null");
   if (!res) return fail(-10, "res is null");
   if (!work) return fail(-11, "work is null");
-  if (work_bytes < precond_work_bytes(*p, nb)) return fail(KS_E_WORKSPACE, "workspace too small");
+  if (work_bytes < precond_full_work_bytes(*p, nb, learned)) return fail(KS_E_WORKSPACE, "workspace too small");
   const size_t es = p->prec == KS_FP64 ? 16 : 8;
   char* tmp = static_cast<char*>(work);
-  const int n0 = p->fft.ax[0].n, n1 = p->fft.ax[1].n, n2 = p->fft.ax[2].n;
-  const size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p->zc));
-  double* partial = reinterpret_cast<double*>(tmp + al((size_t)p->Ng * nb * es));
-  double* E = reinterpret_cast<double*>(reinterpret_cast<char*>(partial) + al((size_t)nb * cnt * 8));
+  PrecondWs pw;
+  precond_layout(*p, tmp + al((size_t)p->Ng * nb * es), nb, learned, pw);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->prec == KS_FP64)
-    return precond_apply<double>(*p, kind, static_cast<const double2*>(X), static_cast<const double2*>(AX), theta, ld,
-                                 nb, lock_tol, static_cast<double2*>(W), res, reinterpret_cast<double2*>(tmp), partial,
-                                 E, s);
-  return precond_apply<float>(*p, kind, static_cast<const float2*>(X), static_cast<const float2*>(AX), theta, ld, nb,
-                              lock_tol, static_cast<float2*>(W), res, reinterpret_cast<float2*>(tmp), partial, E, s);
+    return precond_full<double>(*p, kind, opts->lock_tol, opts->cnn_params, static_cast<const double*>(v_loc),
+                                static_cast<const double2*>(X), static_cast<const double2*>(AX), theta, ld, nb,
+                                static_cast<double2*>(W), res, reinterpret_cast<double2*>(tmp), pw, s);
+  return precond_full<float>(*p, kind, opts->lock_tol, opts->cnn_params, static_cast<const float*>(v_loc),
+                             static_cast<const float2*>(X), static_cast<const float2*>(AX), theta, ld, nb,
+                             static_cast<float2*>(W), res, reinterpret_cast<float2*>(tmp), pw, s);
+}
+
+int ks_subspace_sin(const ks_plan* p, const void* A, const void* B, int64_t ld, int32_t k, double* sin_max,
+                    void* work, size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!A) return fail(-2, "A is null");
+  if (!B) return fail(-3, "B is null");
+  if (ld < p->Ng) return fail(-4, "ld < Ng");
+  if (k <= 0 || k > p->nb_max) return fail(-5, "k out of range");
+  if (!sin_max) return fail(-6, "sin_max is null");
+  if (!work) return fail(-7, "work is null");
+  if (work_bytes < angle_work_bytes(*p, k)) return fail(KS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return p->prec == KS_FP64 ? subspace_sin<double>(*p, A, B, ld, k, sin_max, work, s)
+                            : subspace_sin<float>(*p, A, B, ld, k, sin_max, work, s);
 }
 
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
@@ -851,7 +952,7 @@ int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int
   if (work_bytes < hegv_work(n, nev)) return fail(KS_E_WORKSPACE, "workspace too small");
   if (!info_dev) return fail(-12, "info is null");
   return hegv(n, nev, static_cast<double2*>(H), ldh, static_cast<double2*>(S), lds, w, static_cast<double2*>(C), ldc,
-              work, info_dev, static_cast<hipStream_t>(stream));
+              work, info_dev, nullptr, static_cast<hipStream_t>(stream));
 }
 
 static int check_state(const ks_plan* p, const ks_lobpcg_state* st) {
@@ -859,8 +960,8 @@ static int check_state(const ks_plan* p, const ks_lobpcg_state* st) {
   if (!st) return fail(-3, "state is null");
   if (st->nb <= 0 || st->nb > p->nb_max) return fail(-3, "state nb out of range");
   if (st->ld < p->Ng) return fail(-3, "state ld < Ng");
-  const void* ptrs[] = {st->X, st->AX, st->W, st->AW, st->P, st->AP, st->Xn, st->AXn, st->Pn, st->APn, st->T1,
-                        st->theta, st->res};
+  const void* ptrs[] = {st->X, st->AX, st->W, st->AW, st->P, st->AP, st->Xn, st->Pn, st->T1, st->theta, st->res,
+                        st->status};
   for (const void* q : ptrs)
     if (!q) return fail(-3, "state has a null buffer");
   return 0;

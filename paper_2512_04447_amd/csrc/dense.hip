@@ -24,8 +24,11 @@ constexpr double CHOL_TOL = 1e-14;
 static inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 // ---------------------------------------------------------------- potrf
-__global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, double* dmax, int32_t* info) {
+__global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, double* dmax, int32_t* info,
+                             int32_t* __restrict__ dead, unsigned long long* __restrict__ bound) {
   __shared__ double red[4];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dead[i] = 0;
+  if (threadIdx.x == 0) *bound = 0ull;
   double m = -DBL_MAX;
   for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, S[i + (int64_t)i * lds].x);
   // block max by a fixed tree
@@ -46,11 +49,22 @@ __global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, doub
 // the pivot d_j; no later step reads column j, so the scaling of every
 // column by 1/sqrt(d_j) waits until the end (one pass, off the chain of
 // steps) and a step is one LDS round trip and one barrier.
+//
+// A pivot not above the tolerance stops the factorisation (info) when
+// dead == nullptr.  Otherwise the column is deflated: dead[k0 + j] = 1, the
+// pivot becomes 1 and the column below it 0, so it takes no part in later
+// columns (the live columns hold the Cholesky factor of the overlap
+// restricted to them), and row j of the block's inverse is zeroed: the
+// triangular solves built from these inverses then give L^-1 with zero row
+// and column j, which drops basis vector j from every product with it.
 __global__ void __launch_bounds__(256)
 k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restrict__ dmax,
-        int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv) {
+        int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv, int32_t* __restrict__ dead,
+        int32_t* __restrict__ ndead) {
   __shared__ double2 a[NB][NB + 1];
   __shared__ double sq[NB];
+  __shared__ int sdead[NB];
+  if (threadIdx.x < NB) sdead[threadIdx.x] = 0;
   // the block: unconditional loads (indices clamped into the block), issued
   // together with the flag and the tolerance's scale; padding zeroed
   // afterwards, four in flight per thread
@@ -78,8 +92,21 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
   for (int j = 0; j < kb; ++j) {
     const double d = a[j][j].x;
     if (!(d > tol)) {
-      if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
-      return;  // uniform: every thread read the same d
+      if (dead == nullptr) {
+        if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
+        return;  // uniform: every thread read the same d
+      }
+      // deflate column j (uniform branch); no thread reads column j again
+      // in this step, and the barrier orders these writes before the next
+      if (pc == 0 && ri > j && ri < kb) a[ri][j] = make_double2(0.0, 0.0);
+      if (threadIdx.x == 0) {
+        a[j][j] = make_double2(1.0, 0.0);
+        sdead[j] = 1;
+        dead[k0 + j] = 1;
+        if (ndead) atomicAdd(ndead, 1);
+      }
+      __syncthreads();
+      continue;
     }
     // a[i][p] -= a[i][j] conj(a[p][j]) / d for j < p <= i < kb: every read
     // first (in range: the padding is zero), then the guarded writes; no
@@ -142,7 +169,7 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
         accr += l.x * y.x - l.y * y.y;
         acci += l.x * y.y + l.y * y.x;
       }
-      const bool live = c <= i && i < kb && c < kb;
+      const bool live = c <= i && i < kb && c < kb && sdead[i] == 0;
       const double inv = 1.0 / a[i][i].x;
       const double dr = ((i == c ? 1.0 : 0.0) - accr) * inv, di = -acci * inv;
       xc[i] = make_double2(live ? dr : 0.0, live ? di : 0.0);
@@ -173,34 +200,48 @@ static int copy_block(const double2* src, int ld_src, double2* dst, int ld_dst, 
 
 struct PotrfWs {
   double* dmax;
+  unsigned long long* bound;  // Gershgorin bound of the reduced matrix (bits of a double >= 0)
+  int32_t* dead;  // n: deflated columns
   double2* linv;  // nblk x NB x NB
   double2* panel; // n x NB
+  char* end;
 };
 
 static PotrfWs potrf_ws(void* work, int n) {
   char* p = static_cast<char*>(work);
   PotrfWs w;
   w.dmax = reinterpret_cast<double*>(p);
+  w.bound = reinterpret_cast<unsigned long long*>(p + 16);
   p += 256;
+  w.dead = reinterpret_cast<int32_t*>(p);
+  p += al((size_t)n * sizeof(int32_t));
   w.linv = reinterpret_cast<double2*>(p);
   p += al((size_t)ceil_div(n, NB) * NB * NB * sizeof(double2));
   w.panel = reinterpret_cast<double2*>(p);
+  p += al((size_t)n * NB * sizeof(double2));
+  w.end = p;
   return w;
 }
 
 size_t potrf_work(int n) {
-  return 256 + al((size_t)ceil_div(n, NB) * NB * NB * sizeof(double2)) + al((size_t)n * NB * sizeof(double2));
+  static char probe alignas(256);
+  return (size_t)(potrf_ws(&probe, n).end - &probe);
 }
 
-static int potrf_impl(int n, double2* S, int lds, void* work, int32_t* info, int info_offset, hipStream_t s) {
+// deflate: columns whose pivot fails are dropped (k_potf2) and counted in
+// *ndead instead of stopping with info.
+static int potrf_impl(int n, double2* S, int lds, void* work, int32_t* info, int info_offset, bool deflate,
+                      int32_t* ndead, hipStream_t s) {
   PotrfWs w = potrf_ws(work, n);
-  hipLaunchKernelGGL(k_potrf_init, dim3(1), dim3(256), 0, s, S, lds, n, w.dmax, info);
+  hipLaunchKernelGGL(k_potrf_init, dim3(1), dim3(256), 0, s, S, lds, n, w.dmax, info, w.dead, w.bound);
   KS_LAUNCH_CHECK("potrf_init");
   int rc;
+  int32_t* dead = deflate ? w.dead : nullptr;
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int kb = std::min(NB, n - k0);
     double2* linv = w.linv + (size_t)(k0 / NB) * NB * NB;
-    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, s, S, lds, k0, kb, w.dmax, info, info_offset, linv);
+    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, s, S, lds, k0, kb, w.dmax, info, info_offset, linv, dead,
+                       ndead);
     KS_LAUNCH_CHECK("potf2");
     const int rest = n - k0 - kb;
     if (rest <= 0) break;
@@ -216,7 +257,11 @@ static int potrf_impl(int n, double2* S, int lds, void* work, int32_t* info, int
 }
 
 int potrf(int n, double2* S, int lds, void* work, int32_t* info, hipStream_t s) {
-  return potrf_impl(n, S, lds, work, info, 0, s);
+  return potrf_impl(n, S, lds, work, info, 0, false, nullptr, s);
+}
+
+int potrf_deflate(int n, double2* S, int lds, void* work, int32_t* info, int32_t* ndead, hipStream_t s) {
+  return potrf_impl(n, S, lds, work, info, 0, true, ndead, s);
 }
 
 // B <- op(L)^-1 B using the inverted diagonal blocks from potrf.
@@ -264,18 +309,51 @@ __global__ void k_set_identity(double2* __restrict__ A, int lda, int n) {
   }
 }
 
-// K <- (K + K^H)/2
-__global__ void k_hermitise(double2* __restrict__ K, int ldk, int n) {
-  const int64_t total = (int64_t)n * n;
+// K = (H + H^H)/2 out of place, one block per column j; with bound given,
+// atomicMax of the column's absolute sum (the Gershgorin bound of the
+// spectrum of a Hermitian K; non-negative doubles order like their bits, so
+// the result does not depend on the order of the updates).
+__global__ void __launch_bounds__(256)
+k_hermitise_to(const double2* __restrict__ H, int ldh, double2* __restrict__ K, int ldk, int n,
+               unsigned long long* __restrict__ bound) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double2 a = H[i + (int64_t)j * ldh];
+    const double2 b = H[j + (int64_t)i * ldh];
+    const double2 m = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    K[i + (int64_t)j * ldk] = m;
+    sum += sqrt(m.x * m.x + m.y * m.y);
+  }
+  if (bound == nullptr) return;
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(bound, (unsigned long long)__double_as_longlong(red[0] + red[1] + red[2] + red[3]));
+}
+
+// Deflated basis vectors: K has zero row and column j (L^-1 has), and the
+// diagonal entry becomes 2 * bound + 1, above every eigenvalue of the live
+// part, so the lowest eigenvectors have no component along j.
+__global__ void k_deflate_diag(double2* __restrict__ K, int ldk, int n, const int32_t* __restrict__ dead,
+                               const unsigned long long* __restrict__ bound) {
+  const double big = 2.0 * __longlong_as_double((long long)*bound) + 1.0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    if (dead[j]) K[j + (int64_t)j * ldk] = make_double2(big, 0.0);
+}
+
+// Results of the strict solve leave the workspace only when the Cholesky
+// succeeded (and the tridiagonalisation's barrier did not time out).
+__global__ void k_commit_results(const double* __restrict__ wsrc, double* __restrict__ w, int nev,
+                                 const double2* __restrict__ Csrc, int ldcs, double2* __restrict__ C, int ldc, int n,
+                                 const int32_t* __restrict__ info) {
+  if (*info != 0) return;
+  const int64_t total = (int64_t)n * nev;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % n), j = (int)(e / n);
-    if (i > j) continue;
-    double2 a = K[i + (int64_t)j * ldk];
-    double2 b = K[j + (int64_t)i * ldk];
-    double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-    if (i == j) m.y = 0.0;
-    K[i + (int64_t)j * ldk] = m;
-    K[j + (int64_t)i * ldk] = make_double2(m.x, -m.y);
+    C[i + (int64_t)j * ldc] = Csrc[i + (int64_t)j * ldcs];
+    if (i == 0) w[j] = wsrc[j];
   }
 }
 
@@ -1502,6 +1580,8 @@ struct HegvWs {
   unsigned* bar;  // its grid-barrier counters
   double2* y2;    // n: second y and v of the fused column steps
   double2* v2;
+  double* wev;    // nev: eigenvalues before they are committed
+  char* end;
 };
 
 static HegvWs hegv_ws(void* work, int n, int nev) {
@@ -1525,13 +1605,14 @@ static HegvWs hegv_ws(void* work, int n, int nev) {
   w.bar = reinterpret_cast<unsigned*>(p); p += al((size_t)TRI_BAR_WORDS * sizeof(unsigned));
   w.y2 = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
   w.v2 = reinterpret_cast<double2*>(p); p += al((size_t)n * sizeof(double2));
+  w.wev = reinterpret_cast<double*>(p); p += al((size_t)nev * 8);
+  w.end = p;
   return w;
 }
 
 size_t hegv_work(int n, int nev) {
-  return al(potrf_work(n)) + 2 * al((size_t)n * n * 16) + 3 * al((size_t)n * 16) + 2 * al((size_t)n * 8) + 256 +
-         al((size_t)(nev + 1) * 4) + 256 + al((size_t)n * nev * 8) + al((size_t)NB * n * 16) +
-         2 * al((size_t)2 * n * 16) + al((size_t)TRI_BAR_WORDS * sizeof(unsigned)) + 2 * al((size_t)n * 16);
+  static char probe alignas(256);
+  return (size_t)(hegv_ws(&probe, n, nev).end - &probe);
 }
 
 // Launch shape of the resident tridiagonalisation: it takes the last m
@@ -1579,11 +1660,13 @@ static TriPlan tri_plan(int n) {
 }
 
 int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, double2* C, int ldc, void* work,
-         int32_t* info, hipStream_t s) {
+         int32_t* info, int32_t* ndead, hipStream_t s) {
   HegvWs ws = hegv_ws(work, n, nev);
   TimerScope ts(KF_HEGV, s);
   int rc;
-  if ((rc = potrf_impl(n, S, lds_, ws.potrf, info, n, s))) return rc;
+  const bool deflate = ndead != nullptr;
+  const PotrfWs pw = potrf_ws(ws.potrf, n);
+  if ((rc = potrf_impl(n, S, lds_, ws.potrf, info, n, deflate, ndead, s))) return rc;
   // The two triangular solves of the reduction, Y = L^-1 H and
   // K = L^-1 Y^H, and the final C = L^-H Z go through X = L^-1: the blocked
   // solve runs once, on the identity (its result is exactly zero above the
@@ -1596,10 +1679,14 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   // Y = X H (in K's buffer), K = Y X^H (in H), then K <- (K + K^H)/2
   if ((rc = zgemm('N', 'N', n, n, n, 1.0, ws.X, n, H, ldh, 0.0, ws.K, n, s))) return rc;
   if ((rc = zgemm('N', 'C', n, n, n, 1.0, ws.K, n, ws.X, n, 0.0, H, ldh, s))) return rc;
-  if ((rc = copy_block(H, ldh, ws.K, n, n, n, s))) return rc;
-  hipLaunchKernelGGL(k_hermitise, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)), dim3(256),
-                     0, s, ws.K, n, n);
+  hipLaunchKernelGGL(k_hermitise_to, dim3((unsigned)n), dim3(256), 0, s, H, ldh, ws.K, n, n,
+                     deflate ? pw.bound : nullptr);
   KS_LAUNCH_CHECK("hermitise");
+  if (deflate) {
+    hipLaunchKernelGGL(k_deflate_diag, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, ws.K, n, n, pw.dead,
+                       pw.bound);
+    KS_LAUNCH_CHECK("deflate_diag");
+  }
   // Householder tridiagonalisation: one column per launch while the
   // trailing matrix is larger than the LDS of the device holds, then the
   // resident kernel for the remaining steps
@@ -1672,11 +1759,14 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
       hipLaunchKernelGGL(k_tridiag_tail, dim3(1), dim3(64), 0, s, ws.K, n, n, ws.d, ws.e, ws.tau);
     }
   }
-  hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), (size_t)2 * n * sizeof(double), s, ws.d, ws.e, n, nev, w,
+  // the deflating solve writes w directly; the strict one commits it at the
+  // end only when the factorisation succeeded
+  double* wout = deflate ? w : ws.wev;
+  hipLaunchKernelGGL(k_bisect, dim3(nev), dim3(64), (size_t)2 * n * sizeof(double), s, ws.d, ws.e, n, nev, wout,
                      ws.tnorm);
-  hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, w, nev, ws.tnorm, ws.cl, ws.ncl);
+  hipLaunchKernelGGL(k_clusters, dim3(1), dim3(64), 0, s, wout, nev, ws.tnorm, ws.cl, ws.ncl);
   hipLaunchKernelGGL(k_inverse_iteration, dim3(nev), dim3(256), (size_t)n * (5 * sizeof(double) + sizeof(int)), s,
-                     ws.d, ws.e, n, w, ws.tnorm, ws.cl, ws.ncl, ws.Z, n);
+                     ws.d, ws.e, n, wout, ws.tnorm, ws.cl, ws.ncl, ws.Z, n);
   KS_LAUNCH_CHECK("bisection / inverse iteration");
   // Q Z_T into H (no longer needed), then C = L^-H (Q Z_T) = X^H (Q Z_T)
   {
@@ -1694,7 +1784,13 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
       hipLaunchKernelGGL(k_backtransform, dim3(nev), dim3(64), lds, s, ws.K, n, n, ws.tau, ws.Z, n, H, ldh);
     KS_LAUNCH_CHECK("backtransform");
   }
-  return zgemm('C', 'N', n, nev, n, 1.0, ws.X, n, H, ldh, 0.0, C, ldc, s);
+  if (deflate) return zgemm('C', 'N', n, nev, n, 1.0, ws.X, n, H, ldh, 0.0, C, ldc, s);
+  // strict: C staged in K (free after the back-transform), then committed
+  if ((rc = zgemm('C', 'N', n, nev, n, 1.0, ws.X, n, H, ldh, 0.0, ws.K, n, s))) return rc;
+  hipLaunchKernelGGL(k_commit_results, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * nev, 256), 2048)),
+                     dim3(256), 0, s, ws.wev, w, nev, ws.K, n, C, ldc, n, info);
+  KS_LAUNCH_CHECK("commit");
+  return 0;
 }
 
 }  // namespace ks

@@ -578,6 +578,9 @@ k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* _
   const int ns = supp_ptr[a + 1] - s0;
   const int p0 = proj_ptr[a];
   const int np = proj_ptr[a + 1] - p0;
+  // an atom without projectors has no coefficients to form (and no
+  // projector table to read)
+  if (np == 0) return;
   const T* bet = beta + beta_ptr[a];
   double acc[MAXP][NBT][2];
 #pragma unroll

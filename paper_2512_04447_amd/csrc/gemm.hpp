@@ -65,11 +65,19 @@ constexpr int kHegvMaxN = 3700;
 // Smallest n whose tridiagonalisation uses the resident (cooperative) kernel;
 // only that kernel can report info = -1.
 int hegv_resident_min_n();
+// ndead == nullptr: strict solve (info = n + k on a failed Cholesky, and then
+// w and C are left unchanged).  Otherwise the Cholesky deflates: basis
+// vectors that depend numerically on earlier ones are dropped (zero rows of
+// C), their count added to *ndead, and info only reports the resident
+// tridiagonalisation's barrier (-1).
 int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds, double* w, double2* C, int ldc, void* work,
-         int32_t* info, hipStream_t s);
+         int32_t* info, int32_t* ndead, hipStream_t s);
 // Cholesky S = L L^H in place (lower), info as for hegv (k, not n + k).
 size_t potrf_work(int n);
 int potrf(int n, double2* S, int lds, void* work, int32_t* info, hipStream_t s);
+// The same with deflation of dependent columns (pivot 1, zero column below
+// it, zero row in the inverted diagonal block), counted in *ndead.
+int potrf_deflate(int n, double2* S, int lds, void* work, int32_t* info, int32_t* ndead, hipStream_t s);
 // B <- op(L)^-1 B for the lower factor L from potrf (its workspace holds
 // the inverted diagonal blocks); op 'N' or 'C'.
 int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ldb, void* potrf_ws, void* tmp,

@@ -159,47 +159,12 @@ def train_multi(sets, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int 
     return nets[0].params, hist
 
 
-def run_to_tolerance(plan, v, X0, ntrack: int, precond: int, lock_tol: float, maxit: int, ref=None,
-                     tol_ha: float = 1e-6, res_tol: float = 0.0, cnn_params=None, switch_to_tpa: bool = True,
-                     log=print):
-    """LOBPCG from X0 with one D2H read of (theta, res) per iteration.
+def run_to_tolerance(*args, **kwargs):
+    """The driver of :mod:`paper_2512_04447_amd.solve` (kept here for callers
+    of the training module)."""
+    from .solve import run_to_tolerance as run
 
-    Stops at the first iteration where every tracked |theta_i - ref_i| <=
-    tol_ha (when ref is given), or max tracked residual <= res_tol, or
-    maxit.  With the learned preconditioner the run switches to TPA for
-    good when the max tracked residual has not dropped by 10% over 3
-    iterations.  Returns a dict with the wall time from X0 (init included),
-    the iteration count and the per-iteration history.
-    """
-    import torch
-
-    lob = b.Lobpcg(plan, v, X0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lob.init()
-    hist = []
-    pc = precond
-    switched = None
-    for it in range(1, maxit + 1):
-        learned = pc in (b.KS_PRECOND_CNN, b.KS_PRECOND_CNN_TPA)
-        lob.step(pc, lock_tol, cnn_params if learned else None)
-        tr = torch.cat([lob.theta[:ntrack], lob.res[:ntrack]]).cpu().numpy()
-        th, res = tr[:ntrack], tr[ntrack:]
-        rmax = float(res.max())
-        err = float(np.abs(th - ref).max()) if ref is not None else None
-        hist.append((time.perf_counter() - t0, rmax, err, th))
-        if it % 5 == 0:
-            log(f"[tta] iteration {it}: max res {rmax:.3e}" + (f", max err {err:.3e}" if err is not None else "")
-                + f", {hist[-1][0]:.1f}s")
-        if learned and switch_to_tpa and it > 3 and rmax > 0.9 * hist[-4][1]:
-            pc = b.KS_PRECOND_TPA
-            switched = it
-            log(f"[tta] learned preconditioner stalled at iteration {it}; switching to TPA")
-        if (ref is not None and err <= tol_ha) or rmax <= res_tol:
-            break
-    torch.cuda.synchronize()
-    return {"seconds": time.perf_counter() - t0, "iterations": it, "max_res": rmax, "max_err": err,
-            "switched_to_tpa_at": switched, "history": hist, "lobpcg": lob}
+    return run(*args, **kwargs)
 
 
 def train(plan, pairs: PairSet, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 2, val_frac: float = 0.1,

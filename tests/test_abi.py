@@ -73,3 +73,54 @@ def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.KsError):
         binding.load()
+
+
+def _projset(binding, supp_ptr, supp_idx, proj_ptr, beta_ptr, nbeta, nproj):
+    import numpy as np
+
+    arrs = binding.ProjectorArrays(np.asarray(supp_ptr, np.int32), np.asarray(supp_idx, np.int32),
+                                   np.asarray(proj_ptr, np.int32), np.asarray(beta_ptr, np.int64),
+                                   np.ones(nbeta), np.ones(nproj))
+    return arrs, arrs.struct()
+
+
+def test_plan_create_rejects_inconsistent_projector_sets_on_the_host():
+    from paper_2512_04447_amd import binding
+
+    lib = binding.load()
+    g = binding.KsGrid()
+    g.n[0] = g.n[1] = g.n[2] = 8
+    g.L[0] = g.L[1] = g.L[2] = 5.0
+    out = C.c_void_p()
+    bad = [
+        # (supp_ptr, supp_idx, proj_ptr, beta_ptr, nbeta, nproj, message fragment)
+        ([1, 3], [0, 1, 2], [0, 1], [0, 2], 2, 1, "start at 0"),
+        ([0, 3, 2], [0, 1, 2], [0, 1, 2], [0, 3, 3], 3, 2, "decrease"),
+        ([0, 2, 4], [0, 1, 2, 3], [0, 2, 1], [0, 4, 4], 4, 1, "decrease"),
+        ([0, 2], [0, 1], [0, 1], [0, 3], 3, 1, "beta_ptr"),
+        ([0, 2], [0, 1], [0, 10], [0, 20], 20, 10, "more than 9"),
+        ([0, 2], [0, 512], [0, 1], [0, 2], 2, 1, "out of the grid"),
+        ([0, 2], [0, -1], [0, 1], [0, 2], 2, 1, "out of the grid"),
+        ([0, 2], [0, 1], [0, 2], [0, 4], 4, 1, "inconsistent"),
+    ]
+    for sp, si, pp, bp, nbeta, nproj, frag in bad:
+        keep, ps = _projset(binding, sp, si, pp, bp, nbeta, nproj)
+        rc = lib.ks_plan_create(C.byref(out), C.byref(g), C.byref(ps), 4, binding.KS_FP64, None)
+        assert rc == -3, (sp, pp, bp, rc)
+        assert frag in lib.ks_last_error().decode(), (frag, lib.ks_last_error())
+
+
+def test_precond_apply_validates_its_options_on_the_host():
+    from paper_2512_04447_amd import binding
+
+    lib = binding.load()
+    fake = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert lib.ks_precond_apply(None, None, fake, fake, fake, fake, 8, 1, fake, fake, fake, 0, None) == -1
+    o = binding.KsLobpcgOpts()
+    o.precond = 7
+    # a plan pointer is needed to reach the option checks; none of these calls reach the device
+    assert lib.ks_precond_apply(fake, None, fake, fake, fake, fake, 8, 1, fake, fake, fake, 0, None) == -2
+    assert lib.ks_precond_apply(fake, C.byref(o), fake, fake, fake, fake, 8, 1, fake, fake, fake, 0, None) == -2
+    o.precond = binding.KS_PRECOND_CNN
+    assert lib.ks_precond_apply(fake, C.byref(o), fake, fake, fake, fake, 8, 1, fake, fake, fake, 0, None) == -2
+    assert "parameters" in lib.ks_last_error().decode()

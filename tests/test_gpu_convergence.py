@@ -1,0 +1,151 @@
+"""Converged eigenpairs of the HIP path against the oracle, at the sizes of
+the benchmark cells: the FP64 path to 1e-10 Ha of the oracle's converged
+eigenvalues, the mixed-precision path (finished by FP64 refinement) to
+1e-6 Ha with principal angles <= 1e-5, and the 216-atom cell certified by
+the oracle's own H-apply on sampled Ritz vectors (Krylov-Weinstein and
+Kato-Temple bounds)."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import ksinputs as ki
+from oracle import hamiltonian as oh
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "c2_eigenvalues.txt")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _c2_golden():
+    return np.loadtxt(GOLDEN_C2, comments="#", usecols=1)
+
+
+def _setup(name, prec):
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    cfg = ki.config(name)
+    cell = ki.make_cell(cfg)
+    proj = b.ProjectorArrays.from_cell(cell) if cell.nproj else None
+    plan = b.Plan(cell.n, cell.L, proj, cfg.nb, prec)
+    dt = torch.float64 if prec == b.KS_FP64 else torch.float32
+    v = torch.from_numpy(cell.V).to(dt).cuda()
+    return cfg, cell, proj, plan, v
+
+
+def test_c2_fp64_eigenvalues_within_1e10_of_the_oracle(ks):
+    """64-atom cell, 48^3 grid, 160 bands, s+p projectors: LOBPCG to a
+    tracked residual of 1e-8; all 128 tracked eigenvalues within 1e-10 Ha of
+    the oracle's (tests/golden/c2_eigenvalues.txt, written by the oracle
+    alone)."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import solve
+
+    cfg, cell, proj, plan, v = _setup("C2", b.KS_FP64)
+    x0 = torch.from_numpy(ki.make_x0(cfg)).cuda()
+    _say("C2 fp64 to residual 1e-8")
+    r = solve.run_to_tolerance(plan, v, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-9, 150, res_tol=1e-8, log=_say)
+    assert r["stopped"] == "res_tol", r["stopped"]
+    th = r["lobpcg"].theta_host[: cfg.ntrack]
+    gold = _c2_golden()[: cfg.ntrack]
+    err = float(np.abs(th - gold).max())
+    _say("  iterations", r["iterations"], "max |theta - oracle|", err)
+    assert err <= 1e-10
+
+
+def test_c2_mixed_refined_within_1e6_and_subspace_angle_1e5(ks):
+    """The mixed path (complex64 blocks, FP32 FFT/H-apply/Gram, FP64 subspace
+    solve) from the same initial block, handed over to FP64 steps near its
+    FP32 floor: tracked eigenvalues within 1e-6 Ha of the oracle's and the
+    sine of the largest principal angle to the FP64 GPU subspace (itself
+    within 1e-10 Ha of the oracle) at most 1e-5."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import solve
+
+    cfg, cell, proj, plan64, v64 = _setup("C2", b.KS_FP64)
+    x0 = torch.from_numpy(ki.make_x0(cfg)).cuda()
+    gold = _c2_golden()
+    r64 = solve.run_to_tolerance(plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-9, 150, res_tol=1e-8, log=_say)
+    k = solve.angle_cut(gold, cfg.ntrack)
+    assert k >= cfg.ntrack // 2
+    ref_X = r64["lobpcg"].X[:k].clone()
+    del r64
+    planm = b.Plan(cell.n, cell.L, proj, cfg.nb, b.KS_MIXED_FP32)
+    crit = solve.Criterion(gold[: cfg.ntrack], ref_X, plan64, k)
+    _say("C2 mixed + refinement, angle cut", k)
+    r = solve.run_mixed_refined(planm, v64.float(), plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-4, crit, 100,
+                                log=_say)
+    _say("  iterations", r["iterations"], "(mixed", r["mixed_iterations"], ") err", r["max_err"], "sin", r["sin"])
+    assert r["reached"]
+    assert r["mixed_iterations"] >= 3
+    assert r["max_err"] <= 1e-6 and r["sin"] <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_c3_fp64_certified_by_the_oracle_and_mixed_refined_within_tolerance(ks):
+    """216-atom cell, 96^3 grid, 480 bands (432 tracked).  FP64 to a tracked
+    residual of 1e-8; on 12 sampled tracked bands the oracle's own H-apply
+    gives the Rayleigh quotient rho and residual r of the GPU's Ritz vector:
+    |theta_GPU - rho| <= 1e-10 Ha, and by Kato-Temple (gap from the nearest
+    other Ritz value) |rho - lambda| <= 1e-10 Ha.  Then the mixed path with
+    FP64 refinement: tracked eigenvalues within 1e-6 Ha of the FP64 ones and
+    the principal-angle sine to the FP64 subspace at most 1e-5."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import solve
+
+    t0 = time.time()
+    cfg, cell, proj, plan64, v64 = _setup("C3", b.KS_FP64)
+    x0 = torch.from_numpy(ki.make_x0(cfg)).cuda()
+    _say("C3 fp64 to residual 1e-8", f"(setup {time.time() - t0:.0f}s)")
+    r64 = solve.run_to_tolerance(plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-9, 80, res_tol=1e-8, log=_say)
+    assert r64["stopped"] == "res_tol"
+    lob = r64["lobpcg"]
+    theta = lob.theta_host
+    sample = np.unique(np.linspace(0, cfg.ntrack - 1, 12).round().astype(int))
+    Xs = lob.X[torch.from_numpy(sample).cuda()].cpu().numpy()
+    k = solve.angle_cut(theta, cfg.ntrack)
+    assert k >= cfg.ntrack // 2
+    ref_X = lob.X[:k].clone()
+    del lob, r64
+    torch.cuda.empty_cache()
+    # mixed + refinement against the FP64 run
+    planm = b.Plan(cell.n, cell.L, proj, cfg.nb, b.KS_MIXED_FP32)
+    crit = solve.Criterion(theta[: cfg.ntrack], ref_X, plan64, k)
+    _say("C3 mixed + refinement, angle cut", k)
+    r = solve.run_mixed_refined(planm, v64.float(), plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-4, crit, 80,
+                                log=_say)
+    _say("  iterations", r["iterations"], "(mixed", r["mixed_iterations"], ") err", r["max_err"], "sin", r["sin"])
+    assert r["reached"] and r["max_err"] <= 1e-6 and r["sin"] <= 1e-5
+    del r, ref_X, crit
+    torch.cuda.empty_cache()
+    # the oracle certifies the FP64 eigenvalues on the sampled bands
+    t1 = time.time()
+    oc = oh.oracle_cell(cfg, cell.D)
+    _say(f"  oracle cell in {time.time() - t1:.0f}s")
+    for row, i in enumerate(sample):
+        x = Xs[row] / np.linalg.norm(Xs[row])
+        hx = oh.apply_h(oc, x[None])[0]
+        rho = float(np.real(np.vdot(x, hx)))
+        rn = float(np.linalg.norm(hx - rho * x))
+        gap = float(np.min(np.abs(np.delete(theta, i) - rho)))
+        kt = rn * rn / gap
+        _say(f"  band {i}: |theta - rho| {abs(theta[i] - rho):.2e} ||r|| {rn:.2e} gap {gap:.2e} Kato-Temple {kt:.2e}")
+        assert abs(theta[i] - rho) <= 1e-10
+        assert rn <= 2e-8
+        assert kt <= 1e-10

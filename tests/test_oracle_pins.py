@@ -464,3 +464,166 @@ def test_bfloat16_rounding_matches_torch_conversion():
     # representable: the low 16 bits of the binary32 pattern are zero
     assert np.all((got.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
     assert np.isnan(ocnn.round_bf16(np.array([np.nan], dtype=np.float32))[0])
+
+
+# ---------------------------------------------------------------- deflating Cholesky (P8 for a singular overlap)
+
+
+def _dependent_basis(rng, N=40, m=9, dep=((4, (1, 2)), (7, (0, 4)))):
+    """N x m complex basis whose column k (for each (k, (i, j)) in dep) is a
+    combination of columns i and j before it."""
+    V = rng.standard_normal((N, m)) + 1j * rng.standard_normal((N, m))
+    for k, (i, j) in dep:
+        V[:, k] = (0.3 - 0.7j) * V[:, i] + 1.9 * V[:, j]
+    return V
+
+
+def test_deflating_cholesky_equals_plain_cholesky_on_positive_definite_input():
+    rng = np.random.default_rng(41)
+    S = random_hpd(30, rng, cond=1e6)
+    L, dead = ola.cholesky_lower_deflate(S)
+    assert not dead.any()
+    np.testing.assert_allclose(L, np.linalg.cholesky(S), rtol=0, atol=1e-12 * np.abs(S).max())
+
+
+def test_deflating_cholesky_drops_exactly_the_dependent_columns():
+    rng = np.random.default_rng(42)
+    V = _dependent_basis(rng)
+    S = V.conj().T @ V
+    L, dead = ola.cholesky_lower_deflate(S)
+    assert np.nonzero(dead)[0].tolist() == [4, 7]
+    live = np.nonzero(~dead)[0]
+    # the live part is the library Cholesky of the live overlap; dead columns are unit vectors
+    ref = np.linalg.cholesky(S[np.ix_(live, live)])
+    np.testing.assert_allclose(L[np.ix_(live, live)], ref, rtol=0, atol=1e-11 * np.abs(S).max())
+    for k in (4, 7):
+        e = np.zeros(S.shape[0]); e[k] = 1.0
+        np.testing.assert_array_equal(L[:, k], e)
+
+
+def test_deflated_reduction_gives_the_ritz_values_of_the_span():
+    """Ritz values of a Hermitian A on span(V) do not depend on the basis:
+    the deflated two-solve reduction on the dependent basis equals the
+    library generalised solve on an independent basis of the same span."""
+    rng = np.random.default_rng(43)
+    N, nev = 40, 4
+    V = _dependent_basis(rng, N=N)
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    A = A + A.conj().T
+    Hs, Ss = V.conj().T @ A @ V, V.conj().T @ V
+    w, C, ndead = ola.hegv_two_trsm_deflate(Hs, Ss, nev)
+    assert ndead == 2
+    keep = [0, 1, 2, 3, 5, 6, 8]
+    U = V[:, keep]
+    ref = scipy.linalg.eigh(U.conj().T @ A @ U, U.conj().T @ U, eigvals_only=True)[:nev]
+    assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max()
+    X = V @ C
+    assert np.abs(X.conj().T @ X - np.eye(nev)).max() <= 1e-9
+    # Galerkin condition: the residual is orthogonal to the span
+    assert np.abs(V.conj().T @ (A @ X - X * w)).max() <= 1e-9 * np.abs(A).max() * np.abs(V).max()
+    assert np.abs(C[[4, 7]]).max() == 0.0
+
+
+def test_orthonormalise_block_zeroes_a_dependent_column_and_keeps_the_span():
+    rng = np.random.default_rng(44)
+    Vm = _dependent_basis(rng, N=50, m=6, dep=((3, (0, 1)),))
+    B = Vm.T.copy()  # band-major: rows are the columns
+    Bq, _, ndead = olob.orthonormalise_block(B)
+    assert ndead == 1
+    assert np.abs(Bq[3]).max() == 0.0
+    live = [0, 1, 2, 4, 5]
+    G = Bq[live].conj() @ Bq[live].T
+    assert np.abs(G - np.eye(5)).max() <= 1e-12
+    # same span: projecting the original columns on the new ones loses nothing
+    Q = Bq[live].T
+    resid = Vm - Q @ (Q.conj().T @ Vm)
+    assert np.abs(resid).max() <= 1e-10 * np.abs(Vm).max()
+
+
+# ---------------------------------------------------------------- Adam beyond the first step; geometry in closed form
+
+
+def test_adam_constant_gradient_moves_by_lr_sign_at_every_step():
+    """With a constant gradient the bias-corrected moments equal g and g^2
+    exactly at every t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    step is lr * g / (|g| + eps).  A wrong decay or bias correction breaks
+    this from t = 2 on."""
+    p = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -4.0, 1e-3, 250.0])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    for t in range(1, 51):
+        p1, m, v = ocnn.adam_update(p, g, m, v, t, lr=1e-3)
+        assert np.allclose(p - p1, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0), t
+        p = p1
+
+
+def test_adam_two_steps_worked_by_hand():
+    """g1 = 1 then g2 = -2, lr 0.1, from m = v = 0.  Step 1 moves by -0.1.
+    Step 2: m2 = 0.9*0.1 - 0.2 = -0.11, v2 = 0.999*0.001 + 0.004 = 0.004999,
+    m2 / (1 - 0.81) = -0.578947..., v2 / (1 - 0.998001) = 2.500750...,
+    sqrt = 1.581376..., so the step is +0.1 * 0.578947 / 1.581376 = +0.036610."""
+    p0 = np.array([0.0])
+    p1, m, v = ocnn.adam_update(p0, np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.1)
+    assert abs(p1[0] - (-0.1)) <= 1e-9
+    p2, m, v = ocnn.adam_update(p1, np.array([-2.0]), m, v, 2, lr=0.1)
+    assert abs(m[0] - (-0.11)) <= 1e-15 and abs(v[0] - 0.004999) <= 1e-15
+    assert abs((p2[0] - p1[0]) - 0.036610) <= 2e-6
+
+
+def test_potential_at_an_atom_on_a_grid_point_is_the_image_shell_sum():
+    """One atom on a grid point of a cubic cell, L = 4.1, sigma = 0.8: the
+    images within 10 sigma = 8 bohr are the atom itself and the shells
+    |T| = L (6), L sqrt(2) (12) and L sqrt(3) (8); |T| = 2L = 8.2 is out.
+    So V(R) = A (1 + 6 e^{-L^2/2s^2} + 12 e^{-2L^2/2s^2} + 8 e^{-3L^2/2s^2})."""
+    L, s, A, n = 4.1, 0.8, -2.0, 10
+    cfg = ki.custom_config("one", L, n, ((0.3, 0.5, 0.7),), 1, v_depth=A, v_sigma=s)
+    pos = oh.oracle_positions(cfg)
+    V = oh.oracle_potential(cfg, pos)
+    q = lambda k: math.exp(-k * L * L / (2 * s * s))  # noqa: E731
+    expect = A * (1 + 6 * q(1) + 12 * q(2) + 8 * q(3))
+    idx = (3 * n + 5) * n + 7
+    assert abs(V[idx] - expect) <= 1e-14 * abs(expect)
+    # a neighbouring grid point along z: the same shells seen from dz = h
+    h = L / n
+    shells = [(0, 0, 0)] + [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]
+    tot = 0.0
+    for a, b, c in shells:
+        d2 = (a * L) ** 2 + (b * L) ** 2 + (h - c * L) ** 2
+        if d2 <= (10 * s) ** 2:
+            tot += math.exp(-d2 / (2 * s * s))
+    assert abs(V[idx + 1] - A * tot) <= 1e-14 * abs(A * tot)
+
+
+def test_projector_values_follow_the_gaussian_and_solid_harmonic_shapes():
+    """Atom on a grid point: s values at two support points have the ratio
+    exp(-(r1^2 - r2^2)/(2 rc^2)); p_x is odd in x and equals x times the s
+    shape up to one constant; d_xy vanishes on the coordinate planes; every
+    projector is normalised on the grid; the support is every grid point
+    with minimum-image distance below 4 rc (counted by brute force)."""
+    L, n, rc = 7.0, 14, 0.55
+    cfg = ki.custom_config("one", L, n, ((0.5, 0.5, 0.5),), 1, lmax=2, rc=rc)
+    pos = oh.oracle_positions(cfg)
+    supp, vals = oh.oracle_projectors(cfg, pos)
+    assert len(supp) == 9
+    h = L / n
+    # brute-force support: integer offsets from the atom's grid point (7, 7, 7)
+    offs = [(a, b, c) for a in range(-n // 2, n // 2) for b in range(-n // 2, n // 2) for c in range(-n // 2, n // 2)
+            if (a * a + b * b + c * c) * h * h < (4 * rc) ** 2]
+    assert len(supp[0]) == len(offs)
+    lin = {((7 + a) * n + 7 + b) * n + 7 + c: (a * h, b * h, c * h) for a, b, c in offs}
+    assert set(supp[0].tolist()) == set(lin)
+    xyz = np.array([lin[i] for i in supp[0].tolist()])
+    r2 = np.sum(xyz * xyz, axis=1)
+    bs, bx, bxy = vals[0], vals[1], vals[4]
+    i0 = int(np.argmin(r2))
+    ratio = bs / bs[i0]
+    assert np.abs(ratio - np.exp(-(r2 - r2[i0]) / (2 * rc * rc))).max() <= 1e-13
+    nz = np.abs(xyz[:, 0]) > 0
+    c = bx[nz] / (xyz[nz, 0] * bs[nz])
+    assert np.abs(c - c[0]).max() <= 1e-12 * abs(c[0])
+    assert np.abs(bx[~nz]).max() == 0.0
+    plane = (np.abs(xyz[:, 0]) < 1e-12) | (np.abs(xyz[:, 1]) < 1e-12)
+    assert np.abs(bxy[plane]).max() <= 1e-15
+    for v in vals:
+        assert abs(float(np.sum(v * v)) - 1.0) <= 1e-13
