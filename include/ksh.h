@@ -240,6 +240,22 @@ int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int
                       int32_t* info_dev, void* stream);
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes);
 
+/* hegv_reduce_solve for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and the same results, with the workspace taken from a
+ * static device array of KS_NOALLOC_SCRATCH_BYTES (32 MiB) that each GPU the
+ * library runs on holds until the process ends.  n <= KS_NOALLOC_MAX_N
+ * (512); larger n (or a workspace beyond the array) returns -1 or
+ * KS_E_WORKSPACE without launching anything.  Calls no hipMalloc or hipFree;
+ * its kernels are never timed.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (different streams or threads) race and
+ * give wrong results; serialise them. */
+#define KS_NOALLOC_MAX_N 512
+#define KS_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define KS_NOALLOC_MAX_DEVICES 64
+int hegv_reduce_solve_noalloc(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds, double* w, void* C,
+                              int32_t ldc, int32_t* info_dev, void* stream);
+
 /* LOBPCG start: X <- X L^-H with L = chol(X^H X) (Cholesky-QR of the initial
  * block in st->X), AX = H X, Rayleigh-Ritz on span(X): X <- X Z, then
  * AX = H X by a fresh H-apply; theta = Ritz values ascending.  Sets

@@ -37,6 +37,7 @@ EXPORTS = (
     "ks_subspace_sin",
     "hegv_reduce_solve",
     "hegv_workspace_size",
+    "hegv_reduce_solve_noalloc",
     "lobpcg_init",
     "lobpcg_step",
     "ks_jd_correction",
@@ -142,6 +143,7 @@ def load() -> C.CDLL:
     lib.ks_subspace_sin.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
     lib.hegv_reduce_solve.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp, vp]
     lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
+    lib.hegv_reduce_solve_noalloc.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, vp]
     lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
     lib.lobpcg_step.argtypes = [vp, vp, C.POINTER(KsLobpcgState), C.POINTER(KsLobpcgOpts), vp, sz, vp]
     f32 = C.c_float

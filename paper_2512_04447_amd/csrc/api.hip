@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "gemm.hpp"
@@ -31,10 +33,12 @@ struct FamilyTimer {
   hipEvent_t open = nullptr;
 };
 static FamilyTimer g_timers[KS_KERNEL_FAMILIES];
+// set while an entry point that must not create runtime objects runs
+static thread_local bool g_timers_suppressed = false;
 
 void timer_begin(int f, hipStream_t s) {
   FamilyTimer& t = g_timers[f];
-  if (!t.on) return;
+  if (!t.on || g_timers_suppressed) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
   if (hipEventRecord(e, s) != hipSuccess) {
@@ -46,7 +50,7 @@ void timer_begin(int f, hipStream_t s) {
 
 void timer_end(int f, hipStream_t s) {
   FamilyTimer& t = g_timers[f];
-  if (!t.on || !t.open) return;
+  if (!t.on || !t.open || g_timers_suppressed) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
   if (hipEventRecord(e, s) != hipSuccess) {
@@ -926,6 +930,62 @@ int ks_subspace_sin(const ks_plan* p, const void* A, const void* B, int64_t ld, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   return p->prec == KS_FP64 ? subspace_sin<double>(*p, A, B, ld, k, sin_max, work, s)
                             : subspace_sin<float>(*p, A, B, ld, k, sin_max, work, s);
+}
+
+// ---------------------------------------------------------------- no-allocation dense solve
+// The workspace of hegv_reduce_solve_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only stands for the symbol): the
+// device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[KS_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[KS_NOALLOC_MAX_DEVICES] = {};
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  KS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= KS_NOALLOC_MAX_DEVICES) return fail(KS_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(KS_E_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+int hegv_reduce_solve_noalloc(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int32_t lds, double* w, void* C,
+                              int32_t ldc, int32_t* info_dev, void* stream) {
+  g_last_error.clear();
+  if (n <= 0 || n > KS_NOALLOC_MAX_N)
+    return fail(-1, "n out of range for the no-allocation solve (1.." + std::to_string(KS_NOALLOC_MAX_N) + ")");
+  if (nev <= 0 || nev > n) return fail(-2, "nev out of range");
+  if (!H) return fail(-3, "H is null");
+  if (ldh < n) return fail(-4, "ldh < n");
+  if (!S) return fail(-5, "S is null");
+  if (lds < n) return fail(-6, "lds < n");
+  if (!w) return fail(-7, "w is null");
+  if (!C) return fail(-8, "C is null");
+  if (ldc < n) return fail(-9, "ldc < n");
+  if (!info_dev) return fail(-10, "info is null");
+  if (hegv_work(n, nev) > (size_t)KS_NOALLOC_SCRATCH_BYTES)
+    return fail(KS_E_WORKSPACE, "workspace of this size exceeds the static scratch array");
+  void* work = nullptr;
+  int rc = scratch_address(&work);
+  if (rc) return rc;
+  // the solve reads no workspace value before writing it (its counters and
+  // masks are set by its own first kernels), so the previous call's
+  // contents need no clearing
+  g_timers_suppressed = true;
+  rc = hegv(n, nev, static_cast<double2*>(H), ldh, static_cast<double2*>(S), lds, w, static_cast<double2*>(C), ldc,
+            work, info_dev, nullptr, static_cast<hipStream_t>(stream));
+  g_timers_suppressed = false;
+  return rc;
 }
 
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
