@@ -1,23 +1,36 @@
-"""Benchmark: LOBPCG iterations/s of the HIP path on one MI355X.
+"""Benchmark: LOBPCG on one MI355X, the 216-atom diamond-like cell.
 
-Workload (default): the 64-atom diamond-like cell -- 2x2x2 conventional
-diamond supercell, L = 13.48 bohr, 48^3 grid, 160 bands (128 tracked),
-Gaussian local potential and s+p Gaussian Kleinman-Bylander projectors,
-complex128 throughout, Teter-Payne-Allan preconditioner.  Inputs are seeded
+Headline workload: 3x3x3 conventional diamond supercell, 216 atoms,
+L = 20.22 bohr, 96^3 grid, 480 bands (432 tracked), Gaussian local potential
+and s+p Gaussian Kleinman-Bylander projectors, complex128 throughout (the
+plain FP64 GPU path), Teter-Payne-Allan preconditioner.  Inputs are seeded
 and synthetic.  A step is one full LOBPCG iteration: residual and
 preconditioner, block orthonormalisation, H-apply (batched 3D FFT, local and
 nonlocal terms), Gram GEMMs, Cholesky + two triangular solves + Hermitian
-eigensolve + back-transform, rotation GEMMs.
+eigensolve + back-transform, rotation GEMMs; each step ends with its one
+device-to-host copy of (theta, res, status).
 
-Prints ONE JSON line.  Extra legs: time to 1e-6 Ha (fresh solve from the
-initial block against the stored oracle eigenvalues) and the CPU oracle
-timed on the host for one LOBPCG iteration of the same cell.
+One JSON line.  `value` is FP64 LOBPCG iterations/s on that cell.  Legs in
+the same line:
+* time to 1e-6 Ha (eigenvalues within 1e-6 Ha of the FP64 run's converged
+  values and the sine of the largest principal angle to its subspace at most
+  1e-5) from the same initial block: FP64 + TPA, mixed precision + TPA, and
+  mixed precision + the learned preconditioner, the mixed runs finished by
+  FP64 refinement steps;
+* per-kernel-family rates, run-level GFLOP/s and the roofline fraction of a
+  whole step;
+* the 64-atom cell (48^3, 160 bands): iterations/s and time to 1e-6 Ha
+  against the oracle's converged eigenvalues;
+* cpu_baseline: the CPU oracle on the host, one LOBPCG iteration of the
+  64-atom cell (median of 3 after a warm-up), and the 216-atom cell's
+  oracle iteration extrapolated from timed samples of its phases.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -30,17 +43,15 @@ METRIC = "time to 1e-6 Ha eigenpairs & LOBPCG iter/s: FP64 vs mixed+learned prec
 WORKLOADS = {
     "C1": "diamond 8-atom cell, L=6.74 bohr, 16^3 grid, 16 bands, local potential only",
     "C2": "diamond-like 2x2x2 supercell, 64 atoms, L=13.48 bohr, 48^3 grid, 160 bands, s+p KB projectors",
-    "C3": "diamond-like 3x3x3 supercell, 216 atoms, L=20.22 bohr, 96^3 grid, 480 bands, s+p KB projectors",
+    "C3": "diamond-like 3x3x3 supercell, 216 atoms, L=20.22 bohr, 96^3 grid, 480 bands (432 tracked), "
+          "s+p KB projectors",
     "C4": "bcc 4x4x4 supercell, 128 atoms, L=23.92 bohr, 112^3 grid, 960 bands, s+p+d KB projectors",
 }
 # HBM bytes per launch of a kernel family, from FETCH_SIZE and WRITE_SIZE
-# counter runs scaled by a known-size copy (the per-dispatch table and the
-# commands are in profiles/hbm_traffic_fp64_c2.md).  A value holds only
-# while the kernel source it was measured on is unchanged (sha256 below).
-MEASURED_TRAFFIC = {
-    ("C2", "fp64", "gram"): (2.6337e9, "paper_2512_04447_amd/csrc/gemm.hip",
-                             "ca2ed848dd0136ad8d302c7494b9380d81e4ee92cc048422c78d4ddac899512a"),
-}
+# counter runs scaled by a known-size copy (the per-dispatch tables and the
+# commands are in profiles/).  A value holds only while the kernel source it
+# was measured on is unchanged (sha256 below).
+MEASURED_TRAFFIC = {}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
@@ -53,86 +64,21 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="C3")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
-                    help="fp64 (the default workload) or mixed (complex64 blocks, FP32 products)")
+                    help="fp64 (the headline workload) or mixed (complex64 blocks, FP32 products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tta", action="store_true")
-    ap.add_argument("--compare", default=None,
-                    help="time-to-1e-6-Ha comparison on one cell (C2, C3 or C4) instead of the throughput bench")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-tolerance legs")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 64-atom leg")
     ap.add_argument("--mixed-lock", type=float, default=1e-4)
-    ap.add_argument("--weights", default=None, help="FP32 parameters of the learned preconditioner on r (.npy)")
-    ap.add_argument("--weights-tpa", default=None, help="FP32 parameters of the residual network on TPA(r) (.npy)")
-    ap.add_argument("--maxit", type=int, default=150)
+    ap.add_argument("--weights", default=None, help="FP32 parameters of the learned preconditioner (.npy)")
+    ap.add_argument("--maxit", type=int, default=80)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="first run one plain device-to-device copy of MB megabytes (a known-size dispatch for "
                          "scaling hardware byte counters)")
     return ap.parse_args()
-
-
-def compare(args):
-    """Time to 1e-6 Ha from the same initial block: FP64 + TPA (the plain
-    path, run to residual 1e-8; its final Ritz values are the reference),
-    then the mixed-precision path with TPA and with the trained network.
-    The FP64 run's own time to 1e-6 Ha is read from its history."""
-    import torch
-
-    import ksinputs as ki
-    from paper_2512_04447_amd import binding as b
-    from paper_2512_04447_amd import learned as lr
-
-    cfg = ki.config(args.compare)
-    cell = ki.make_cell(cfg)
-    t0 = time.perf_counter()
-    X0 = ki.make_x0(cfg)
-    log(f"[compare] {cfg.name}: n={cfg.n} nb={cfg.nb} ntrack={cfg.ntrack} X0 in {time.perf_counter() - t0:.1f}s")
-    proj = b.ProjectorArrays.from_cell(cell) if cell.nproj else None
-    x0 = torch.from_numpy(X0).cuda()
-    del X0
-    out = {}
-
-    def leg(name, prec, pc, lock, ref=None, res_tol=0.0, params=None):
-        plan = b.Plan(cell.n, cell.L, proj, cfg.nb, prec)
-        dt = torch.float64 if prec == b.KS_FP64 else torch.float32
-        v = torch.from_numpy(cell.V).to(dt).cuda()
-        xs = x0 if prec == b.KS_FP64 else x0.to(torch.complex64)
-        r = lr.run_to_tolerance(plan, v, xs, cfg.ntrack, pc, lock, args.maxit, ref=ref, res_tol=res_tol,
-                                cnn_params=params, log=log)
-        lob = r.pop("lobpcg")
-        th = lob.theta[: cfg.ntrack].cpu().numpy()
-        hist = r.pop("history")
-        log(f"[compare] {name}: {r['iterations']} iterations, {r['seconds']:.2f}s, max res {r['max_res']:.2e}")
-        r["max_res_history"] = [float(f"{h[1]:.3e}") for h in hist]
-        del lob, xs, v
-        torch.cuda.empty_cache()
-        return r, hist, th
-
-    r64, h64, ref = leg("fp64+tpa", b.KS_FP64, b.KS_PRECOND_TPA, 0.1 * cfg.res_tol, res_tol=cfg.res_tol)
-    # FP64's own time to 1e-6 Ha against its converged values
-    first = next((i for i, h in enumerate(h64) if np.abs(h[3] - ref).max() <= 1e-6), len(h64) - 1)
-    out["fp64_tpa"] = {"seconds_to_1e-6_Ha": round(h64[first][0], 3), "iterations_to_1e-6_Ha": first + 1,
-                       "converged_iterations": r64["iterations"], "final_max_res": r64["max_res"],
-                       "s_per_iter": round(r64["seconds"] / r64["iterations"], 4),
-                       "max_res_history": r64["max_res_history"]}
-    rm, hm, thm = leg("mixed+tpa", b.KS_MIXED_FP32, b.KS_PRECOND_TPA, args.mixed_lock, ref=ref)
-    out["mixed_tpa"] = {"seconds_to_1e-6_Ha": round(rm["seconds"], 3), "iterations_to_1e-6_Ha": rm["iterations"],
-                        "max_err_Ha": rm["max_err"], "s_per_iter": round(rm["seconds"] / rm["iterations"], 4),
-                        "reached": bool(rm["max_err"] <= 1e-6), "max_res_history": rm["max_res_history"]}
-    for key, kind, wpath in (("mixed_cnn", b.KS_PRECOND_CNN, args.weights or lr.WEIGHTS),
-                             ("mixed_cnn_tpa", b.KS_PRECOND_CNN_TPA, args.weights_tpa or lr.WEIGHTS_TPA)):
-        if not os.path.exists(wpath):
-            continue
-        params = torch.from_numpy(np.load(wpath)).cuda()
-        rc, hc, thc = leg(key.replace("_", "+", 1), b.KS_MIXED_FP32, kind, args.mixed_lock, ref=ref, params=params)
-        out[key] = {"seconds_to_1e-6_Ha": round(rc["seconds"], 3), "iterations_to_1e-6_Ha": rc["iterations"],
-                    "max_err_Ha": rc["max_err"], "s_per_iter": round(rc["seconds"] / rc["iterations"], 4),
-                    "reached": bool(rc["max_err"] <= 1e-6), "switched_to_tpa_at": rc["switched_to_tpa_at"],
-                    "max_res_history": rc["max_res_history"]}
-    print(json.dumps({"metric": METRIC, "compare": cfg.name, "n_gpus": 1, "data": "synthetic",
-                      "config": {"workload": cfg.name, "Ng": cfg.Ng, "bands": cfg.nb, "tracked": cfg.ntrack},
-                      "legs": out}))
 
 
 def measured_traffic(cfg_name, precision, family):
@@ -154,8 +100,8 @@ def measured_traffic(cfg_name, precision, family):
 
 
 def family_work(cfg, es):
-    """Algorithmic flops / bytes per step for each kernel family; es is the
-    bytes of one complex element of the blocks (16 FP64, 8 mixed)."""
+    """Algorithmic flops / bytes per LOBPCG step for each kernel family; es is
+    the bytes of one complex element of the blocks (16 FP64, 8 mixed)."""
     Ng, nb = cfg.Ng, cfg.nb
     m = 3 * nb
     blk = Ng * nb * es
@@ -166,6 +112,8 @@ def family_work(cfg, es):
         # Hermitian triangles of the W and P self-Grams (S only) and of the
         # basis Gram (S and H); the full X^H W of the projection W - X X^H W
         "gram_flops": 8 * Ng * (nb * (nb + 1) / 2 * (2 + extra) + nb * nb + 2 * m * (m + 1) / 2),
+        # the basis Gram alone: S and H over [X W P], Hermitian triangles
+        "gram_basis_flops": 8 * Ng * m * (m + 1),
         # W and P orthonormalising rotations, the projection update, and one
         # pass over V giving X' = V C and P' = V[:, nb:] C[nb:]
         "rotate_flops": 8 * Ng * (nb * nb * (3 + extra) + m * nb + 2 * nb * nb),
@@ -175,7 +123,283 @@ def family_work(cfg, es):
         "pass_b_bytes": blk * (1 + 2 + 2 * n_h),
         # pass C: TPA (R+W), H (tmp R + psi R + W) per H-apply
         "pass_c_bytes": blk * (2 + 3 * n_h),
+        # nonlocal projection: every orbital value read once per H-apply
+        "nl_project_bytes": blk * n_h,
+        # nonlocal scatter: H psi read and written once per H-apply
+        "nl_scatter_bytes": 2 * blk * n_h,
+        # the subspace solve (Cholesky, the two triangular solves as products,
+        # tridiagonalisation, back-transform, C = L^-H Z)
+        "hegv_flops": 4 * m ** 3 / 3 + 8 * m ** 3 + 16 * m ** 3 / 3 + 12 * m * m * nb,
     }
+
+
+def make_inputs(cfg_name):
+    import torch
+
+    import ksinputs as ki
+    from paper_2512_04447_amd import binding as b
+
+    cfg = ki.config(cfg_name)
+    t0 = time.perf_counter()
+    cell = ki.make_cell(cfg)
+    X0 = ki.make_x0(cfg)
+    proj = b.ProjectorArrays.from_cell(cell) if cell.nproj else None
+    x0 = torch.from_numpy(X0).cuda()
+    log(f"[bench] {cfg.name}: n={cfg.n} nb={cfg.nb} atoms={cell.natoms} nproj={cell.nproj} "
+        f"(inputs in {time.perf_counter() - t0:.1f}s)")
+    return cfg, cell, proj, X0, x0
+
+
+def plan_for(b, cell, proj, cfg, mixed):
+    import torch
+
+    plan = b.Plan(cell.n, cell.L, proj, cfg.nb, b.KS_MIXED_FP32 if mixed else b.KS_FP64)
+    v = torch.from_numpy(cell.V).to(torch.float32 if mixed else torch.float64).cuda()
+    return plan, v
+
+
+def throughput(b, cfg, plan, v, x0, steps, warmup, mixed):
+    """Timed LOBPCG steps, then the same number again under per-family HIP
+    event timers.  Returns (wall seconds, {family: (ms per step, launches
+    per step)})."""
+    import torch
+
+    lob = b.Lobpcg(plan, v, x0.to(torch.complex64) if mixed else x0)
+    lob.init()
+    tol = cfg.res_tol
+    lock = 1e-4 if mixed else 0.1 * tol
+    for _ in range(warmup):
+        lob.step(b.KS_PRECOND_TPA, lock)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lob.step(b.KS_PRECOND_TPA, lock)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ["gram", "rotate", "pass_a", "pass_b", "pass_c", "nl_project", "hegv", "zgemm", "gram_basis",
+             "nl_scatter"]
+    for f in range(len(names)):
+        b.kernel_timer(True, f)
+    for _ in range(steps):
+        lob.step(b.KS_PRECOND_TPA, lock)
+    torch.cuda.synchronize()
+    fam = {}
+    for f, nm in enumerate(names):
+        ms, n = b.kernel_timer_read(f)
+        b.kernel_timer(False, f)
+        fam[nm] = (ms / steps, n / steps)
+    del lob
+    torch.cuda.empty_cache()
+    return wall, fam
+
+
+def rates(cfg, fam, mixed, ms_per_step):
+    """Per-family achieved rates against the MI355X peaks, the dominant
+    kernel's roofline object, run-level GFLOP/s and the step's roofline
+    fraction (the sum of every family's time at its peak over the measured
+    step time)."""
+    w = family_work(cfg, 8 if mixed else 16)
+    mma = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
+    spec = {  # family: (work key, bound, peak, unit, scale to unit)
+        "gram": ("gram_flops", "mfma", mma, "TFLOP/s", 1e12),
+        "rotate": ("rotate_flops", "mfma", mma, "TFLOP/s", 1e12),
+        "pass_a": ("pass_a_bytes", "hbm", HBM_PEAK_GBS, "GB/s", 1e9),
+        "pass_b": ("pass_b_bytes", "hbm", HBM_PEAK_GBS, "GB/s", 1e9),
+        "pass_c": ("pass_c_bytes", "hbm", HBM_PEAK_GBS, "GB/s", 1e9),
+        "nl_project": ("nl_project_bytes", "hbm", HBM_PEAK_GBS, "GB/s", 1e9),
+        "nl_scatter": ("nl_scatter_bytes", "hbm", HBM_PEAK_GBS, "GB/s", 1e9),
+        "hegv": ("hegv_flops", "fp64", FP64_PEAK_TFS, "TFLOP/s", 1e12),
+    }
+    out = {}
+    ideal_ms = 0.0
+    for k, (key, bound, peak, unit, sc) in spec.items():
+        ms = fam[k][0]
+        ach = w[key] / sc / (ms / 1e3) if ms > 0 else 0.0
+        out[k] = {"ms_per_step": round(ms, 4), "launches_per_step": fam[k][1], "achieved": round(ach, 3),
+                  "unit": unit, "frac": round(ach / peak, 4), "bound": bound}
+        ideal_ms += w[key] / sc / peak * 1e3
+    out["zgemm"] = {"ms_per_step": round(fam["zgemm"][0], 4), "launches_per_step": fam["zgemm"][1]}
+    # the dominant kernel: the basis Gram (S and H of [X W P]), one launch
+    # (Gram kernel plus its ordered reduction) per step
+    gb_ms, gb_n = fam["gram_basis"]
+    per_launch = w["gram_basis_flops"]
+    avg_ms = gb_ms / max(gb_n, 1)
+    ach = per_launch / 1e12 / (avg_ms / 1e3)
+    roofline = {"kernel": "gram_basis", "bound": "mfma", "achieved": round(ach, 3), "peak": mma, "unit": "TFLOP/s",
+                "frac": round(ach / mma, 4),
+                "traffic": measured_traffic(cfg.name, "mixed" if mixed else "fp64", "gram_basis"),
+                "algorithmic_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 4)}
+    flops = w["gram_flops"] + w["rotate_flops"] + w["hegv_flops"]
+    run = {"gflops": round(flops / 1e9 / (ms_per_step / 1e3), 1),
+           "flops_per_step": flops,
+           "roofline_ms_per_step": round(ideal_ms, 3),
+           "roofline_frac": round(ideal_ms / ms_per_step, 4)}
+    return out, roofline, run
+
+
+def tta_legs(b, cfg, cell, proj, x0, args, lr):
+    """Time to 1e-6 Ha from the same initial block (R-11 criterion)."""
+    import torch
+
+    from paper_2512_04447_amd import solve
+
+    out = {}
+    plan64, v64 = plan_for(b, cell, proj, cfg, False)
+    # the FP64 reference: converged to a tracked residual of 1e-8 (its Ritz
+    # values then within about (1e-8)^2 / gap of the exact ones, its
+    # subspace within about 1e-8 / gap)
+    r = solve.run_to_tolerance(plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-9, args.maxit, res_tol=1e-8,
+                               log=log)
+    lob = r.pop("lobpcg")
+    ref_all = lob.theta_host
+    k = solve.angle_cut(ref_all, cfg.ntrack)
+    ref_X = lob.X[:k].clone() if k > 0 else None
+    out["fp64_reference"] = {"iterations": r["iterations"], "seconds": round(r["seconds"], 3),
+                             "final_max_res": r["max_res"], "angle_cut": k}
+    log(f"[bench] FP64 reference: {r['iterations']} iterations, {r['seconds']:.2f}s, angle cut {k}")
+    del lob, r
+    torch.cuda.empty_cache()
+    ref = ref_all[: cfg.ntrack]
+
+    def crit():
+        return solve.Criterion(ref, ref_X, plan64, k)
+
+    def summary(r, extra=None):
+        d = {"seconds_to_1e-6_Ha": round(r["seconds"], 3), "iterations": r["iterations"], "reached": r["reached"],
+             "max_err_Ha": r["max_err"], "sin_max_angle": r["sin"],
+             "max_res_history": [float(f"{h[1]:.3e}") for h in r["history"]]}
+        d.update(extra or {})
+        return d
+
+    r = solve.run_to_tolerance(plan64, v64, x0, cfg.ntrack, b.KS_PRECOND_TPA, 1e-9, args.maxit, crit=crit(),
+                               log=log)
+    r.pop("lobpcg")
+    out["fp64_tpa"] = summary(r, {"s_per_iter": round(r["seconds"] / r["iterations"], 4)})
+    log(f"[bench] FP64+TPA: {r['iterations']} iterations, {r['seconds']:.2f}s")
+    torch.cuda.empty_cache()
+    planm, vm = plan_for(b, cell, proj, cfg, True)
+    wpath = args.weights or lr.WEIGHTS
+    params = torch.from_numpy(np.load(wpath)).cuda() if os.path.exists(wpath) else None
+    for key, kind in (("mixed_tpa_refined", b.KS_PRECOND_TPA), ("mixed_cnn_refined", b.KS_PRECOND_CNN)):
+        if kind == b.KS_PRECOND_CNN and params is None:
+            continue
+        r = solve.run_mixed_refined(planm, vm, plan64, v64, x0, cfg.ntrack, kind, args.mixed_lock, crit(),
+                                    args.maxit, cnn_params=params if kind == b.KS_PRECOND_CNN else None, log=log)
+        r.pop("lobpcg")
+        out[key] = summary(r, {"mixed_iterations": r["mixed_iterations"], "fp64_iterations": r["fp64_iterations"],
+                               "switched_to_tpa_at": r["switched_to_tpa_at"]})
+        log(f"[bench] {key}: {r['iterations']} iterations ({r['mixed_iterations']} mixed), {r['seconds']:.2f}s")
+        torch.cuda.empty_cache()
+    return out
+
+
+def c2_leg(b, steps):
+    """The 64-atom cell: FP64 iterations/s and time to 1e-6 Ha against the
+    oracle's converged eigenvalues (tests/golden/c2_eigenvalues.txt)."""
+    import torch
+
+    from paper_2512_04447_amd import solve
+
+    cfg, cell, proj, X0, x0 = make_inputs("C2")
+    plan, v = plan_for(b, cell, proj, cfg, False)
+    wall, fam = throughput(b, cfg, plan, v, x0, 2 * steps, 2, False)
+    out = {"workload": WORKLOADS["C2"] + ", complex128, TPA preconditioner",
+           "iter_per_s": round(2 * steps / wall, 3), "ms_per_step": round(1e3 * wall / (2 * steps), 3)}
+    gold = np.loadtxt(os.path.join(ROOT, "tests", "golden", "c2_eigenvalues.txt"), comments="#", usecols=1)
+    r = solve.run_to_tolerance(plan, v, x0, cfg.ntrack, b.KS_PRECOND_TPA, 0.1 * cfg.res_tol, 150,
+                               res_tol=cfg.res_tol, log=log)
+    lob = r.pop("lobpcg")
+    k = solve.angle_cut(gold, cfg.ntrack)
+    ref_X = lob.X[:k].clone()
+    out["fp64_converged_max_abs_err_vs_oracle_Ha"] = float(np.abs(lob.theta_host[: cfg.ntrack] - gold[: cfg.ntrack]).max())
+    del lob
+    r = solve.run_to_tolerance(plan, v, x0, cfg.ntrack, b.KS_PRECOND_TPA, 0.1 * cfg.res_tol, 150,
+                               crit=solve.Criterion(gold[: cfg.ntrack], ref_X, plan, k), log=log)
+    r.pop("lobpcg")
+    out["time_to_1e-6_Ha"] = {"seconds": round(r["seconds"], 4), "iterations": r["iterations"],
+                              "max_abs_err_Ha": r["max_err"], "sin_max_angle": r["sin"], "reached": r["reached"]}
+    del ref_X
+    torch.cuda.empty_cache()
+    return out, cfg, cell, X0
+
+
+def cpu_baseline(c2cfg, c2cell, c2X0):
+    """The CPU oracle timed on the host: one LOBPCG iteration of the 64-atom
+    cell (median of 3 after one warm-up), and the 216-atom cell's iteration
+    extrapolated from timed samples of its phases."""
+    from oracle import hamiltonian as oh
+    from oracle import linalg as ola
+    from oracle import lobpcg as olob
+
+    cores = len(os.sched_getaffinity(0))
+    oc = oh.oracle_cell(c2cfg, c2cell.D)
+    st = olob.initial_state(oc, c2X0)
+    pc = olob.tpa_preconditioner(oc)
+    tol = c2cfg.res_tol
+    st = olob.step(oc, st, pc, 0.1 * tol)  # warm-up
+    times = []
+    for _ in range(3):
+        c0 = time.perf_counter()
+        st = olob.step(oc, st, pc, 0.1 * tol)
+        times.append(time.perf_counter() - c0)
+    med = statistics.median(times)
+    log(f"[bench] cpu oracle C2: {med:.2f}s per iteration (median of {[round(t, 2) for t in times]}) on {cores} cores")
+    # 216-atom cell, extrapolated: H-apply and TPA per band, Gram and
+    # rotation on a slice of the grid (linear in the grid size), the dense
+    # reduction and Jacobi eigensolve at m = 240 (cubic in m)
+    import ksinputs as ki
+
+    cfg3 = ki.config("C3")
+    cell3 = ki.make_cell(cfg3)
+    c0 = time.perf_counter()
+    oc3 = oh.oracle_cell(cfg3, cell3.D)
+    t_cell = time.perf_counter() - c0
+    rng = np.random.default_rng(5)
+    nsamp = 2
+    psi = (rng.standard_normal((nsamp, cfg3.Ng)) + 1j * rng.standard_normal((nsamp, cfg3.Ng))) / np.sqrt(2)
+    c0 = time.perf_counter()
+    oh.apply_h(oc3, psi)
+    t_h = (time.perf_counter() - c0) / nsamp
+    st3 = olob.State(psi, psi, np.zeros(nsamp))
+    c0 = time.perf_counter()
+    pc3 = olob.tpa_preconditioner(oc3)
+    pc3(psi, st3)
+    t_tpa = (time.perf_counter() - c0) / nsamp
+    nb, m = cfg3.nb, 3 * cfg3.nb
+    frac = 1.0 / 512
+    ks = int(cfg3.Ng * frac)
+    V = (rng.standard_normal((m, ks)) + 1j * rng.standard_normal((m, ks)))
+    c0 = time.perf_counter()
+    olob.gram(V, V)
+    olob.gram(V, V)
+    t_gram = (time.perf_counter() - c0) / frac
+    Cm = rng.standard_normal((m, nb)) + 1j * rng.standard_normal((m, nb))
+    c0 = time.perf_counter()
+    olob.rotate(V, Cm)
+    olob.rotate(V[nb:], Cm[nb:])
+    t_rot = (time.perf_counter() - c0) / frac
+    ms = 240
+    A = rng.standard_normal((ms, ms)) + 1j * rng.standard_normal((ms, ms))
+    Hs = A + A.conj().T
+    Ss = A @ A.conj().T + ms * np.eye(ms)
+    c0 = time.perf_counter()
+    ola.hegv_two_trsm_deflate(Hs, Ss, ms // 3)
+    t_small = (time.perf_counter() - c0) * (m / ms) ** 3
+    # per iteration: 3 H-applies and one TPA pass over nb bands, the basis
+    # Gram (S and H) plus the W/P self-Grams and X^H W (about 1.3 basis
+    # Grams of V's rows in all), the rotations, the dense solve
+    t_iter = 3 * nb * t_h + nb * t_tpa + 1.3 * t_gram + 1.2 * t_rot + t_small
+    log(f"[bench] cpu oracle C3 (extrapolated): {t_iter:.0f}s per iteration "
+        f"(H-apply {t_h:.2f}s/band, TPA {t_tpa:.2f}s/band, Gram {t_gram:.0f}s, rotation {t_rot:.0f}s, "
+        f"dense solve {t_small:.0f}s; oracle cell {t_cell:.0f}s)")
+    return {"value": round(1.0 / med, 5), "unit": "LOBPCG iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"64-atom cell (48^3, 160 bands): one oracle LOBPCG iteration, median of 3 after one warm-up "
+                      f"({med:.1f} s)",
+            "c3_extrapolated": {"seconds_per_iteration": round(t_iter, 1), "kind": "extrapolated",
+                                "method": "216-atom cell: 3 nb oracle H-applies and nb TPA applications at the "
+                                          "timed per-band cost, the Gram and rotation timed on 1/512 of the grid "
+                                          "and scaled linearly, the dense reduction and Jacobi eigensolve timed "
+                                          "at m = 240 and scaled by (1440/240)^3"}}
 
 
 def main():
@@ -186,8 +410,8 @@ def main():
         sys.exit(2)
     import torch
 
-    import ksinputs as ki
     from paper_2512_04447_amd import binding as b
+    from paper_2512_04447_amd import learned as lr
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy > 0:
@@ -198,114 +422,37 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nbytes} bytes read and {nbytes} bytes written")
         del src, dst
-    if args.compare:
-        compare(args)
-        return
-    cfg = ki.config(args.config)
-    cell = ki.make_cell(cfg)
-    X0 = ki.make_x0(cfg)
-    log(f"[bench] {cfg.name}: n={cfg.n} nb={cfg.nb} atoms={cell.natoms} nproj={cell.nproj}")
     mixed = args.precision == "mixed"
-    plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell) if cell.nproj else None, cfg.nb,
-                  b.KS_MIXED_FP32 if mixed else b.KS_FP64)
-    v = torch.from_numpy(cell.V).cuda()
-    x0 = torch.from_numpy(X0).cuda()
-    if cfg.name not in ("C1", "C2"):
-        del X0  # large cells: the host copy is not needed again
-    if mixed:
-        v, x0 = v.float(), x0.to(torch.complex64)
-    lob = b.Lobpcg(plan, v, x0)
-    lob.init()
-    tol = cfg.res_tol
-    for _ in range(args.warmup):
-        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
-    torch.cuda.synchronize()
-    fams = [b.KF_GRAM, b.KF_ROTATE, b.KF_PASS_A, b.KF_PASS_B, b.KF_PASS_C, b.KF_NL_PROJECT, b.KF_HEGV, b.KF_ZGEMM]
-    names = ["gram", "rotate", "pass_a", "pass_b", "pass_c", "nl_project", "hegv", "zgemm"]
-    # timed region without event instrumentation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    log(f"[bench] {args.steps} steps in {wall:.3f}s")
-    # same number of steps again with HIP events around each kernel family
-    for f in fams:
-        b.kernel_timer(True, f)
-    for _ in range(args.steps):
-        lob.step(b.KS_PRECOND_TPA, 0.1 * tol)
-    torch.cuda.synchronize()
-    fam_ms = {}
-    for f, nm in zip(fams, names):
-        ms, n = b.kernel_timer_read(f)
-        b.kernel_timer(False, f)
-        fam_ms[nm] = (ms / args.steps, n / args.steps)
-    log("[bench] per-step ms by family: " + ", ".join(f"{k}={v[0]:.3f} ({v[1]:.0f} launches)" for k, v in fam_ms.items()))
-    work = family_work(cfg, 8 if mixed else 16)
-    mma_peak = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
-    rates = {
-        "gram": ("mfma", work["gram_flops"] / 1e12 / (fam_ms["gram"][0] / 1e3), mma_peak, "TFLOP/s",
-                 work["gram_flops"] / max(fam_ms["gram"][1], 1)),
-        "rotate": ("mfma", work["rotate_flops"] / 1e12 / (fam_ms["rotate"][0] / 1e3), mma_peak, "TFLOP/s",
-                   work["rotate_flops"] / max(fam_ms["rotate"][1], 1)),
-        "pass_a": ("hbm", work["pass_a_bytes"] / 1e9 / (fam_ms["pass_a"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
-                   work["pass_a_bytes"] / max(fam_ms["pass_a"][1], 1)),
-        "pass_b": ("hbm", work["pass_b_bytes"] / 1e9 / (fam_ms["pass_b"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
-                   work["pass_b_bytes"] / max(fam_ms["pass_b"][1], 1)),
-        "pass_c": ("hbm", work["pass_c_bytes"] / 1e9 / (fam_ms["pass_c"][0] / 1e3), HBM_PEAK_GBS, "GB/s",
-                   work["pass_c_bytes"] / max(fam_ms["pass_c"][1], 1)),
-    }
-    dom = max(rates, key=lambda k: fam_ms[k][0])
-    bound, ach, peak, unit, per_launch = rates[dom]
-    roofline = {"kernel": dom, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 4), "traffic": measured_traffic(cfg.name, args.precision, dom),
-                "algorithmic_per_launch": per_launch,
-                "avg_launch_ms": fam_ms[dom][0] / max(fam_ms[dom][1], 1)}
-    others = {k: {"achieved": round(r[1], 3), "unit": r[3], "frac": round(r[1] / r[2], 4),
-                  "ms_per_step": round(fam_ms[k][0], 4)} for k, r in rates.items()}
-    others["hegv"] = {"ms_per_step": round(fam_ms["hegv"][0], 4)}
-    others["nl_project"] = {"ms_per_step": round(fam_ms["nl_project"][0], 4)}
-
-    # time to 1e-6 Ha against the stored oracle eigenvalues
+    cfg, cell, proj, X0, x0 = make_inputs(args.config)
+    del X0
+    plan, v = plan_for(b, cell, proj, cfg, mixed)
+    wall, fam = throughput(b, cfg, plan, v, x0, args.steps, args.warmup, mixed)
+    ms_step = 1e3 * wall / args.steps
+    log(f"[bench] {args.steps} steps in {wall:.3f}s ({ms_step:.2f} ms/step)")
+    log("[bench] per-step ms by family: " + ", ".join(f"{k}={x[0]:.3f} ({x[1]:.0f} launches)" for k, x in fam.items()))
+    kernels, roofline, run = rates(cfg, fam, mixed, ms_step)
+    del plan, v
+    torch.cuda.empty_cache()
     tta = None
-    ref_path = os.path.join(ROOT, "tests", "golden", "c2_eigenvalues.txt")
-    if not args.no_tta and cfg.name == "C2" and os.path.exists(ref_path):
-        ref = np.loadtxt(ref_path, comments="#", usecols=1)[: cfg.ntrack]
-        lob2 = b.Lobpcg(plan, v, x0)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        lob2.init()
-        it = 0
-        while it < 200:
-            lob2.step(b.KS_PRECOND_TPA, 0.1 * tol)
-            it += 1
-            th = lob2.theta_host[: cfg.ntrack]
-            if np.abs(th - ref).max() <= 1e-6:
-                break
-        torch.cuda.synchronize()
-        tta = {"seconds": round(time.perf_counter() - s0, 4), "iterations": it,
-               "max_abs_err_Ha": float(np.abs(th - ref).max())}
-        log(f"[bench] time to 1e-6 Ha: {tta}")
-
+    if not args.no_tta and args.config in ("C2", "C3", "C4"):
+        tta = tta_legs(b, cfg, cell, proj, x0, args, lr)
+    del x0
+    torch.cuda.empty_cache()
+    c2 = None
+    c2cfg = c2cell = c2X0 = None
+    if not args.no_c2 and args.config != "C2":
+        c2, c2cfg, c2cell, c2X0 = c2_leg(b, args.steps)
     cpu = None
-    # the oracle step is timed on the FP64 workloads small enough for it
-    if not args.no_cpu_baseline and not mixed and cfg.name in ("C1", "C2"):
-        from oracle import hamiltonian as oh
-        from oracle import lobpcg as olob
+    if not args.no_cpu_baseline:
+        if c2cfg is None:
+            import ksinputs as ki
 
-        cores = len(os.sched_getaffinity(0))
-        oc = oh.oracle_cell(cfg, cell.D)
-        st = olob.initial_state(oc, X0)
-        pc = olob.tpa_preconditioner(oc)
-        c0 = time.perf_counter()
-        olob.step(oc, st, pc, 0.1 * tol)
-        dt = time.perf_counter() - c0
-        cpu = {"value": round(1.0 / dt, 5), "unit": "LOBPCG iter/s", "cores": cores, "kind": "oracle",
-               "sample": f"one oracle LOBPCG iteration on the same cell after its initialisation ({dt:.1f} s)"}
-        log(f"[bench] cpu oracle: {dt:.2f}s per iteration on {cores} cores")
-
+            c2cfg = ki.config("C2")
+            c2cell = ki.make_cell(c2cfg)
+            c2X0 = ki.make_x0(c2cfg)
+        cpu = cpu_baseline(c2cfg, c2cell, c2X0)
+    desc = WORKLOADS.get(cfg.name, cfg.name) + (", complex64 blocks, FP32 products, FP64 subspace solve"
+                                                 if mixed else ", complex128") + ", TPA preconditioner"
     out = {
         "metric": METRIC,
         "value": round(args.steps / wall, 4),
@@ -313,19 +460,19 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS.get(cfg.name, cfg.name) + (", complex64 blocks, FP32 products, FP64 subspace solve"
-                                                                   if mixed else ", complex128")
-                               + ", TPA preconditioner",
-                   "Ng": cfg.Ng, "bands": cfg.nb, "precision": args.precision},
+        "config": {"workload": desc, "cell": cfg.name, "Ng": cfg.Ng, "bands": cfg.nb, "tracked": cfg.ntrack,
+                   "precision": args.precision},
         "roofline": roofline,
-        "kernels": others,
+        "run": run,
+        "kernels": kernels,
         "time_to_1e-6_Ha": tta,
+        "c2": c2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -362,10 +362,12 @@ int cnn_conv16_bf16(const ks_plan* plan, int32_t nbatch, const float* x, const f
  * ks_kernel_timer(0, id) stops recording.  ks_kernel_timer_read waits for
  * the recorded events, returns the summed kernel time (ms) and launch count
  * since the last start, and releases the events.  Families:
- * 0 Gram GEMM, 1 rotation GEMM, 2 FFT pass A, 3 FFT pass B, 4 FFT pass C,
- * 5 nonlocal projection, 6 subspace solve (hegv as a whole), 7 small GEMM.
+ * 0 Gram GEMM (every Gram), 1 rotation GEMM, 2 FFT pass A, 3 FFT pass B,
+ * 4 FFT pass C, 5 nonlocal projection, 6 subspace solve (hegv as a whole),
+ * 7 small GEMM, 8 the basis Gram of lobpcg_step alone (S and H of [X W P],
+ * also counted in 0), 9 nonlocal scatter.
  * Host-side state shared by all threads; not for concurrent use. */
-#define KS_KERNEL_FAMILIES 8
+#define KS_KERNEL_FAMILIES 10
 int ks_kernel_timer(int32_t enable, int32_t family);
 int ks_kernel_timer_read(int32_t family, double* total_ms, int64_t* launches);
 

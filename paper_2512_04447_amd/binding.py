@@ -56,7 +56,8 @@ EXPORTS = (
 )
 
 # kernel families of ks_kernel_timer
-KF_GRAM, KF_ROTATE, KF_PASS_A, KF_PASS_B, KF_PASS_C, KF_NL_PROJECT, KF_HEGV, KF_ZGEMM = range(8)
+(KF_GRAM, KF_ROTATE, KF_PASS_A, KF_PASS_B, KF_PASS_C, KF_NL_PROJECT, KF_HEGV, KF_ZGEMM, KF_GRAM_BASIS,
+ KF_NL_SCATTER) = range(10)
 
 
 class KsGrid(C.Structure):

@@ -188,18 +188,121 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
   if ((rc = upload_vec(blk_proj, &p->blk_proj))) return rc;
   if ((rc = upload_vec(ell_ptr, &p->ell_ptr))) return rc;
   if ((rc = upload_vec(ell_lp, &p->ell_lp))) return rc;
+  // projection table by tiles of grid points: (tile, atom) pairs, tiles in
+  // order and atoms ascending within a tile; a pair's entries are the atom's
+  // support points inside the tile (ascending) with its np projector values
   {
-    std::vector<int32_t> spv(sp, sp + na + 1), siv(si, si + ps->n_supp), ppv(pp, pp + na + 1);
-    std::vector<int64_t> bpv(bp, bp + na + 1);
-    std::vector<T> bv(bp[na]);
-    for (int64_t i = 0; i < bp[na]; ++i) bv[i] = (T)ps->beta[i];
-    if ((rc = upload_vec(spv, &p->supp_ptr))) return rc;
-    if ((rc = upload_vec(siv, &p->supp_idx))) return rc;
-    if ((rc = upload_vec(ppv, &p->proj_ptr))) return rc;
-    if ((rc = upload_vec(bpv, &p->beta_ptr))) return rc;
-    T* b = nullptr;
-    if ((rc = upload_vec(bv, &b))) return rc;
-    p->beta = b;
+    const int n[3] = {p->fft.ax[0].n, p->fft.ax[1].n, p->fft.ax[2].n};
+    nl_tile_shape(p->prec, n, p->tdim);
+    for (int a2 = 0; a2 < 3; ++a2) p->ntile[a2] = (int32_t)ceil_div(n[a2], p->tdim[a2]);
+    const int64_t ntiles = (int64_t)p->ntile[0] * p->ntile[1] * p->ntile[2];
+    // (tile, atom, support index) triples, bucketed by tile in atom order
+    std::vector<int32_t> tcount(ntiles + 1, 0);
+    std::vector<int64_t> tile_of(ps->n_supp);
+    std::vector<uint16_t> local_of(ps->n_supp);
+    for (int a = 0; a < na; ++a) {
+      if (pp[a + 1] == pp[a]) continue;
+      for (int32_t s2 = sp[a]; s2 < sp[a + 1]; ++s2) {
+        const int64_t r = si[s2];
+        const int z = (int)(r % n[2]), y = (int)((r / n[2]) % n[1]), x = (int)(r / ((int64_t)n[1] * n[2]));
+        tile_of[s2] = ((int64_t)(x / p->tdim[0]) * p->ntile[1] + y / p->tdim[1]) * p->ntile[2] + z / p->tdim[2];
+        local_of[s2] = (uint16_t)(((x % p->tdim[0]) * p->tdim[1] + y % p->tdim[1]) * p->tdim[2] + z % p->tdim[2]);
+        tcount[tile_of[s2] + 1] += 1;
+      }
+    }
+    for (int64_t k = 0; k < ntiles; ++k) tcount[k + 1] += tcount[k];
+    std::vector<int32_t> slot(tcount[ntiles]);  // support indices grouped by tile, atoms ascending
+    {
+      std::vector<int32_t> fill(tcount.begin(), tcount.end() - 1);
+      for (int a = 0; a < na; ++a) {
+        if (pp[a + 1] == pp[a]) continue;
+        for (int32_t s2 = sp[a]; s2 < sp[a + 1]; ++s2) slot[fill[tile_of[s2]]++] = s2;
+      }
+    }
+    std::vector<int32_t> atom_of_supp(ps->n_supp);
+    for (int a = 0; a < na; ++a)
+      for (int32_t s2 = sp[a]; s2 < sp[a + 1]; ++s2) atom_of_supp[s2] = a;
+    std::vector<int32_t> tile_pair_ptr(ntiles + 1, 0), pair_ent_ptr(1, 0), pair_boff(1, 0), pair_row(1, 0),
+        pair_atom;
+    std::vector<uint16_t> ent_t;
+    std::vector<T> ent_beta;
+    ent_t.reserve(tcount[ntiles]);
+    ent_beta.reserve(nnz);
+    for (int64_t k = 0; k < ntiles; ++k) {
+      for (int32_t i = tcount[k]; i < tcount[k + 1];) {
+        const int a = atom_of_supp[slot[i]];
+        const int npa = pp[a + 1] - pp[a];
+        const int ns = sp[a + 1] - sp[a];
+        int32_t j = i;
+        // the atom's support is ascending in grid index; within a tile the
+        // local index is then ascending too only per z-run, so sort
+        std::vector<std::pair<uint16_t, int32_t>> pts;
+        for (; j < tcount[k + 1] && atom_of_supp[slot[j]] == a; ++j) pts.push_back({local_of[slot[j]], slot[j]});
+        std::sort(pts.begin(), pts.end());
+        for (const auto& pt : pts) {
+          ent_t.push_back(pt.first);
+          const int32_t s2 = pt.second - sp[a];
+          for (int jp = 0; jp < npa; ++jp) ent_beta.push_back((T)ps->beta[bp[a] + (int64_t)jp * ns + s2]);
+        }
+        pair_atom.push_back(a);
+        pair_ent_ptr.push_back((int32_t)ent_t.size());
+        pair_boff.push_back((int32_t)ent_beta.size());
+        pair_row.push_back(pair_row.back() + npa);
+        i = j;
+      }
+      tile_pair_ptr[k + 1] = (int32_t)pair_atom.size();
+    }
+    const int64_t npairs = (int64_t)pair_atom.size();
+    const int64_t nrows = pair_row.back();
+    if ((int64_t)ent_beta.size() > INT32_MAX || nrows > INT32_MAX)
+      return fail(KS_E_UNSUPPORTED, "projector table too large");
+    // projector -> its partial rows, tiles ascending
+    std::vector<int32_t> proj_pair_ptr(ps->n_proj + 1, 0), proj_pairs(std::max<int64_t>(nrows, 1));
+    for (int64_t q = 0; q < npairs; ++q)
+      for (int jp = pp[pair_atom[q]]; jp < pp[pair_atom[q] + 1]; ++jp) proj_pair_ptr[jp + 1] += 1;
+    for (int i = 0; i < ps->n_proj; ++i) proj_pair_ptr[i + 1] += proj_pair_ptr[i];
+    {
+      std::vector<int32_t> fill(proj_pair_ptr.begin(), proj_pair_ptr.end() - 1);
+      for (int64_t q = 0; q < npairs; ++q) {
+        const int a = pair_atom[q];
+        for (int jp = 0; jp < pp[a + 1] - pp[a]; ++jp) proj_pairs[fill[pp[a] + jp]++] = pair_row[q] + jp;
+      }
+    }
+    if (ent_t.empty()) {
+      ent_t.push_back(0);
+      ent_beta.push_back(T(0));
+    }
+    int maxpt = 0, maxpv = 0, maxtv = 0;
+    for (int64_t k = 0; k < ntiles; ++k) {
+      maxpt = std::max(maxpt, tile_pair_ptr[k + 1] - tile_pair_ptr[k]);
+      maxtv = std::max(maxtv, pair_boff[tile_pair_ptr[k + 1]] - pair_boff[tile_pair_ptr[k]]);
+    }
+    for (int64_t q = 0; q < npairs; ++q) maxpv = std::max(maxpv, pair_boff[q + 1] - pair_boff[q]);
+    // LDS: the orbital tile, then as many projector values (and their
+    // points) as fit; a batch always holds at least one whole pair
+    int dev = 0, maxlds = 0;
+    KS_HIP(hipGetDevice(&dev));
+    KS_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int P = p->tdim[0] * p->tdim[1] * p->tdim[2];
+    const size_t fixed = nl_project_lds(P, sizeof(T), maxpt, 0);
+    if (fixed >= (size_t)maxlds) return fail(KS_E_UNSUPPORTED, "too many atoms touch one tile of grid points");
+    const int64_t room = (int64_t)(((size_t)maxlds - fixed) / (sizeof(T) + 2)) & ~int64_t(7);
+    const int budget = (int)std::min<int64_t>(room, std::max(maxtv, 8));
+    if (budget < maxpv) return fail(KS_E_UNSUPPORTED, "one atom's projector values in a tile exceed the LDS");
+    p->npairs = npairs;
+    p->nrows = nrows;
+    p->maxpt = maxpt;
+    p->budget = budget;
+    if ((rc = upload_vec(tile_pair_ptr, &p->tile_pair_ptr))) return rc;
+    if ((rc = upload_vec(pair_ent_ptr, &p->pair_ent_ptr))) return rc;
+    if ((rc = upload_vec(pair_boff, &p->pair_boff))) return rc;
+    if ((rc = upload_vec(pair_row, &p->pair_row))) return rc;
+    if ((rc = upload_vec(ent_t, &p->ent_t))) return rc;
+    T* eb2 = nullptr;
+    if ((rc = upload_vec(ent_beta, &eb2))) return rc;
+    p->ent_beta = eb2;
+    if ((rc = upload_vec(proj_pair_ptr, &p->proj_pair_ptr))) return rc;
+    if ((rc = upload_vec(proj_pairs, &p->proj_pairs))) return rc;
   }
   T* d = nullptr;
   if ((rc = upload_vec(D, &d))) return rc;
@@ -382,7 +485,7 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.wnew = reinterpret_cast<double*>(take((size_t)m * 8));
   w.info = reinterpret_cast<int32_t*>(take(16));
   w.summary = take(summary_bytes(nb));
-  w.dc = take((size_t)nb * std::max(p.nproj, 1) * es);
+  w.dc = take(nl_dc_bytes(p, nb));
   w.gram = take(gram_work_bytes(m, p.Ng));
   w.hegv = take(hegv_work(m, nb));
   w.potrf = take(potrf_work(nb));
@@ -658,7 +761,10 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   const int m = st->has_p ? 3 * nb : 2 * nb;
   auto LV = blist<T>(st->X, st->W, st->P, ld, nb);
   auto LAV = blist<T>(st->AX, st->AW, st->AP, ld, nb);
-  if ((rc = gram<T>(LV, LV, &LAV, m, p.Ng, w.S, m, w.H, m, w.gram, s))) return rc;
+  {
+    TimerScope tb(KF_GRAM_BASIS, s);
+    if ((rc = gram<T>(LV, LV, &LAV, m, p.Ng, w.S, m, w.H, m, w.gram, s))) return rc;
+  }
   hipLaunchKernelGGL(k_decouple, dim3(1), dim3(256), 0, s, w.S, m, w.H, m, m);
   KS_LAUNCH_CHECK("decouple");
   // 6. reduction and eigensolve; basis vectors that depend numerically on
@@ -832,8 +938,9 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
 int ks_plan_destroy(ks_plan* p) {
   if (!p) return 0;
   for (int a = 0; a < 3; ++a) (void)hipFree(p->tw[a]);
-  void* bufs[] = {p->Dcoef,   p->blk_ptr,  p->blk_proj, p->ell_ptr,  p->ell_lp, p->ell_beta,
-                  p->supp_ptr, p->supp_idx, p->proj_ptr, p->beta_ptr, p->beta};
+  void* bufs[] = {p->Dcoef,         p->blk_ptr,      p->blk_proj, p->ell_ptr,   p->ell_lp,
+                  p->ell_beta,      p->tile_pair_ptr, p->pair_ent_ptr, p->pair_boff, p->pair_row,
+                  p->ent_t,         p->ent_beta,     p->proj_pair_ptr, p->proj_pairs};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -870,7 +977,7 @@ int ks_apply_h(const ks_plan* p, const void* v_loc, const void* psi, int64_t ld_
   if (work_bytes < need) return fail(KS_E_WORKSPACE, "workspace too small");
   const size_t es = p->prec == KS_FP64 ? 16 : 8;
   char* tmp = static_cast<char*>(work);
-  char* dc = tmp + al((size_t)p->Ng * nb * es);
+  char* dc = tmp + al((size_t)p->Ng * nb * es);  // coefficients, then projection partials
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->prec == KS_FP64)
     return apply_h<double>(*p, static_cast<const double*>(v_loc), static_cast<const double2*>(psi), ld_psi,

@@ -182,7 +182,7 @@ static CgWs cg_ws(const ks_plan& p, void* work, int nb) {
   w.Ap = take(blk);
   w.tmp = take(blk);
   w.fft = take(blk);
-  w.dc = take((size_t)nb * std::max(p.nproj, 1) * es);
+  w.dc = take(nl_dc_bytes(p, nb));
   w.G = reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
   w.C = take((size_t)2 * nb * nb * es);
   w.partial = reinterpret_cast<double*>(take((size_t)nb * kChunks * 8));

@@ -63,8 +63,6 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
         int32_t* __restrict__ ndead) {
   __shared__ double2 a[NB][NB + 1];
   __shared__ double sq[NB];
-  __shared__ int sdead[NB];
-  if (threadIdx.x < NB) sdead[threadIdx.x] = 0;
   // the block: unconditional loads (indices clamped into the block), issued
   // together with the flag and the tolerance's scale; padding zeroed
   // afterwards, four in flight per thread
@@ -89,29 +87,21 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
   __syncthreads();
   // thread t owns row i = t % NB of columns p = t / NB + 8u (u = 0..3)
   const int ri = threadIdx.x % NB, pc = threadIdx.x / NB;
+  // dead columns of this block as a bit mask (the same value in every thread)
+  unsigned deadmask = 0u;
   for (int j = 0; j < kb; ++j) {
     const double d = a[j][j].x;
-    if (!(d > tol)) {
-      if (dead == nullptr) {
-        if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
-        return;  // uniform: every thread read the same d
-      }
-      // deflate column j (uniform branch); no thread reads column j again
-      // in this step, and the barrier orders these writes before the next
-      if (pc == 0 && ri > j && ri < kb) a[ri][j] = make_double2(0.0, 0.0);
-      if (threadIdx.x == 0) {
-        a[j][j] = make_double2(1.0, 0.0);
-        sdead[j] = 1;
-        dead[k0 + j] = 1;
-        if (ndead) atomicAdd(ndead, 1);
-      }
-      __syncthreads();
-      continue;
+    const bool dj = !(d > tol);
+    if (dj && dead == nullptr) {
+      if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
+      return;  // uniform: every thread read the same d
     }
+    deadmask |= dj ? (1u << j) : 0u;
     // a[i][p] -= a[i][j] conj(a[p][j]) / d for j < p <= i < kb: every read
     // first (in range: the padding is zero), then the guarded writes; no
-    // entry written here is read in this step
-    const double rd = 1.0 / d;
+    // entry written here is read in this step.  A deflated column updates
+    // nothing (1/d taken as 0); its entries are replaced after the loop.
+    const double rd = dj ? 0.0 : 1.0 / d;
     const double2 x = a[ri][j];
     double2 y[4], z[4];
 #pragma unroll
@@ -129,8 +119,14 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     }
     __syncthreads();
   }
-  // L: column j scaled by 1/sqrt(d_j), the diagonal sqrt(d_j)
-  if (threadIdx.x < kb) sq[threadIdx.x] = sqrt(a[threadIdx.x][threadIdx.x].x);
+  // L: column j scaled by 1/sqrt(d_j), the diagonal sqrt(d_j); a deflated
+  // column becomes the unit vector (pivot 1, zeros below)
+  if (dead != nullptr && threadIdx.x == 0 && deadmask != 0u) {
+    for (int j = 0; j < kb; ++j)
+      if ((deadmask >> j) & 1u) dead[k0 + j] = 1;
+    if (ndead) atomicAdd(ndead, __popc(deadmask));
+  }
+  if (threadIdx.x < kb) sq[threadIdx.x] = ((deadmask >> threadIdx.x) & 1u) ? 1.0 : sqrt(a[threadIdx.x][threadIdx.x].x);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -140,6 +136,8 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
       const double ljj = sq[j];
       if (i == j) {
         a[j][j] = make_double2(ljj, 0.0);
+      } else if ((deadmask >> j) & 1u) {
+        a[i][j] = make_double2(0.0, 0.0);
       } else {
         const double rl = 1.0 / ljj;
         a[i][j].x *= rl;
@@ -169,7 +167,7 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
         accr += l.x * y.x - l.y * y.y;
         acci += l.x * y.y + l.y * y.x;
       }
-      const bool live = c <= i && i < kb && c < kb && sdead[i] == 0;
+      const bool live = c <= i && i < kb && c < kb && ((deadmask >> i) & 1u) == 0u;
       const double inv = 1.0 / a[i][i].x;
       const double dr = ((i == c ? 1.0 : 0.0) - accr) * inv, di = -acci * inv;
       xc[i] = make_double2(live ? dr : 0.0, live ? di : 0.0);

@@ -560,93 +560,207 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
 // ---------------------------------------------------------------- nonlocal
 // Deterministic (no atomics, fixed summation orders).
 
-// Projection c[band][p] = sum_{s in S_a} beta_p(s) psi_band(s), scaled by D_p.
-// One block per (atom, tile of NBT bands); the support list is streamed
-// once per tile and every psi value feeds all projectors of the atom.
-// The block reduction is a fixed tree (deterministic).
-template <typename T, int MAXP, int NBT>
-__global__ void __launch_bounds__(kThreads)
-k_nl_project(const c2<T>* __restrict__ psi, int64_t ld, int nb, const int32_t* __restrict__ supp_ptr,
-             const int32_t* __restrict__ supp_idx, const int32_t* __restrict__ proj_ptr,
-             const int64_t* __restrict__ beta_ptr, const T* __restrict__ beta,
-             const T* __restrict__ D, c2<T>* __restrict__ dc, int nproj) {
+// Projection with every orbital value read once.  Block (tile k, slice of
+// band tiles) keeps the tile's (tile, atom) pairs in LDS: each pair lists
+// the atom's support points inside the tile (tile-local point, then the np
+// values of the atom's projectors there), loaded once for all band tiles of
+// the slice (in batches of whole pairs if they do not fit).  For each band
+// tile of NBS bands the orbital values of the tile's points are staged in
+// LDS (z-runs of the box, coalesced), the next band tile's values loaded
+// into registers meanwhile.  Each wave takes pairs in turn: lanes split into
+// NBS bands x (64 / NBS) entry groups, each group sums beta_j * psi over
+// every (64 / NBS)-th entry of the pair (four entries in flight, two with
+// nine projectors per atom; a fixed order), the groups are combined by a
+// fixed shuffle tree, and the pair's partial coefficients part[row + j][band]
+// (j < np) are written.  The partials of a projector are summed over its
+// tiles by k_nl_reduce (tiles ascending): the result does not depend on
+// scheduling.
+constexpr int kProjThreads = 1024;
+template <typename T, int NBS, int MAXP, int PV>
+__global__ void __launch_bounds__(kProjThreads)
+k_nl_project_tile(const c2<T>* __restrict__ psi, int64_t ld, int nb, int n1, int n2, int tx, int ty, int tz,
+                  int nty, int ntz, int nx, int bt_per_block, const int32_t* __restrict__ tile_pair_ptr,
+                  const int32_t* __restrict__ pair_ent_ptr, const int32_t* __restrict__ pair_boff,
+                  const int32_t* __restrict__ pair_row, const uint16_t* __restrict__ ent_t,
+                  const T* __restrict__ ent_beta, int budget, int maxpt, c2<T>* __restrict__ part) {
   using T2 = c2<T>;
-  __shared__ double red[kThreads / kWave][MAXP * NBT * 2];
-  const int a = blockIdx.x;
-  const int b0 = blockIdx.y * NBT;
-  const int s0 = supp_ptr[a];
-  const int ns = supp_ptr[a + 1] - s0;
-  const int p0 = proj_ptr[a];
-  const int np = proj_ptr[a + 1] - p0;
-  // an atom without projectors has no coefficients to form (and no
-  // projector table to read)
-  if (np == 0) return;
-  const T* bet = beta + beta_ptr[a];
-  double acc[MAXP][NBT][2];
+  constexpr int ROW = NBS + 1;
+  constexpr int G = kWave / NBS;  // entry groups per wave
+  extern __shared__ __align__(16) unsigned char proj_raw[];
+  const int k = blockIdx.x;
+  const int kz = k % ntz, ky = (k / ntz) % nty, kx = k / (ntz * nty);
+  const int x0 = kx * tx, y0 = ky * ty, z0 = kz * tz;
+  const int P = tx * ty * tz;
+  const int total = P * NBS;  // <= PV * blockDim.x (checked on the host)
+  T2* sp = reinterpret_cast<T2*>(proj_raw);             // P x ROW
+  T* sb = reinterpret_cast<T*>(sp + (size_t)P * ROW);   // values of a batch
+  int32_t* spe = reinterpret_cast<int32_t*>(sb + budget);  // 3 (maxpt + 1): entry, value offsets, rows
+  int32_t* sbo = spe + maxpt + 1;
+  int32_t* srow = sbo + maxpt + 1;
+  uint16_t* st = reinterpret_cast<uint16_t*>(srow + maxpt + 1);  // points of a batch
+  const int q0 = tile_pair_ptr[k], npair = tile_pair_ptr[k + 1] - q0;
+  for (int i = threadIdx.x; i <= npair; i += blockDim.x) {
+    spe[i] = pair_ent_ptr[q0 + i];
+    sbo[i] = pair_boff[q0 + i];
+    srow[i] = pair_row[q0 + i];
+  }
+  // this thread's share of a band tile: element e = threadIdx.x + u blockDim
+  // -> band e / P, tile point e % P (z fastest); points outside the grid (a
+  // partial last tile) and bands past nb read a clamped valid address and
+  // are stored as zero
+  // per element: its grid point (roff, below 2^31 points) and code = band
+  // << 16 | LDS slot, or -1 for a point outside the grid or past total
+  int32_t roff[PV], code[PV];
 #pragma unroll
-  for (int j = 0; j < MAXP; ++j)
+  for (int u = 0; u < PV; ++u) {
+    const int e = min((int)threadIdx.x + u * (int)blockDim.x, total - 1);
+    const int b = e / P, t = e - b * P;
+    const int iz = t % tz, iy = (t / tz) % ty, ix = t / (tz * ty);
+    const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
+    const bool in = (int)threadIdx.x + u * (int)blockDim.x < total && x < nx && y < n1 && z < n2;
+    roff[u] = (int32_t)(((int64_t)min(x, nx - 1) * n1 + min(y, n1 - 1)) * n2 + min(z, n2 - 1));
+    code[u] = in ? (b << 16) | (t * ROW + b) : -1;
+  }
+  const int bt0 = blockIdx.y * bt_per_block;
+  const int bt1 = min(bt0 + bt_per_block, (nb + NBS - 1) / NBS);
+  T2 v[PV];
+  auto load_tile = [&](int bt) {
+    const int b0 = bt * NBS, nbl = min(NBS, nb - b0);
 #pragma unroll
-    for (int b = 0; b < NBT; ++b) acc[j][b][0] = acc[j][b][1] = 0.0;
-  // SB support points per thread per step, all their loads issued before
-  // any is used: unconditional, from indices clamped into range (band nb - 1,
-  // projector np - 1, point ns - 1); the terms of a point past ns or a
-  // projector past np get a zero coefficient, and bands past nb are never
-  // written.  The per-thread summation order is that of one point at a time.
-  constexpr int SB = 2;
-  for (int sb = threadIdx.x; sb < ns; sb += blockDim.x * SB) {
-    int sp[SB], idx[SB];
+    for (int u = 0; u < PV; ++u) {
+      const int b = code[u] >> 16;  // -1 for outside points
+      const T2 x = psi[(int64_t)(b0 + min(max(b, 0), nbl - 1)) * ld + roff[u]];
+      v[u] = (code[u] >= 0 && b < nbl) ? x : cmake<T2>(T(0), T(0));
+    }
+  };
+  if (bt0 < bt1) load_tile(bt0);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int b = lane % NBS, g = lane / NBS;
+  // one batch holds every pair of the tile unless their values exceed the
+  // budget; then the batches are staged again for every band tile
+  const bool one_batch = npair == 0 || sbo[npair] - sbo[0] <= budget;
+  auto stage_batch = [&](int qa, int qb) {
+    const int ea = spe[qa], ne = spe[qb] - ea;
+    const int va = sbo[qa], nv = sbo[qb] - va;
+    for (int i0 = threadIdx.x; i0 < nv; i0 += blockDim.x * 4) {
+      T bv[4];
 #pragma unroll
-    for (int u = 0; u < SB; ++u) sp[u] = min(sb + u * (int)blockDim.x, ns - 1);
+      for (int u = 0; u < 4; ++u) bv[u] = ent_beta[va + min(i0 + u * (int)blockDim.x, nv - 1)];
 #pragma unroll
-    for (int u = 0; u < SB; ++u) idx[u] = supp_idx[s0 + sp[u]];
-    T bv[SB][MAXP];
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * (int)blockDim.x < nv) sb[i0 + u * blockDim.x] = bv[u];
+    }
+    for (int i = threadIdx.x; i < ne; i += blockDim.x) st[i] = ent_t[ea + i];
+  };
+  __syncthreads();  // pair pointers visible
+  if (one_batch && npair > 0) stage_batch(0, npair);
+  for (int bt = bt0; bt < bt1; ++bt) {
+    const int b0 = bt * NBS, nbl = min(NBS, nb - b0);
+    // every slot of the tile is written (points outside the grid with zero)
 #pragma unroll
-    for (int u = 0; u < SB; ++u)
+    for (int u = 0; u < PV; ++u) {
+      const int e = (int)threadIdx.x + u * (int)blockDim.x;
+      if (e < total) {
+        const int b = e / P, t = e - b * P;
+        sp[t * ROW + b] = v[u];
+      }
+    }
+    __syncthreads();
+    if (bt + 1 < bt1) load_tile(bt + 1);  // in flight during this band tile's sums
+    int qa = 0;
+    while (qa < npair) {
+      int qb = npair;
+      if (!one_batch) {
+        // pairs qa .. qb - 1, as many whole pairs as the budget holds (one
+        // pair always fits: checked on the host)
+        qb = qa + 1;
+        while (qb < npair && sbo[qb + 1] - sbo[qa] <= budget) ++qb;
+        stage_batch(qa, qb);
+        __syncthreads();
+      }
+      const int ea = spe[qa], va = sbo[qa];
+      for (int q = qa + wv; q < qb; q += nw) {
+        const int e0 = spe[q] - ea, e1 = spe[q + 1] - ea;
+        const int np = (sbo[q + 1] - sbo[q]) / max(e1 - e0, 1);
+        const T* bq = sb + (sbo[q] - va);
+        // sums in the plan's precision within a tile (FP32 for the mixed
+        // plans, whose H-apply is FP32 by design); tiles are summed in FP64
+        T ar[MAXP], ai[MAXP];
 #pragma unroll
-      for (int j = 0; j < MAXP; ++j) bv[u][j] = bet[(int64_t)min(j, np - 1) * ns + sp[u]];
-    T2 pv[SB][NBT];
+        for (int j = 0; j < MAXP; ++j) ar[j] = ai[j] = T(0);
+        // entries in flight per group (fewer with nine accumulators)
+        constexpr int UE = MAXP > 4 ? 2 : 4;
+        for (int e = e0 + g; e < e1; e += UE * G) {
+          int tt[UE];
+          bool okk[UE];
 #pragma unroll
-    for (int u = 0; u < SB; ++u)
+          for (int u = 0; u < UE; ++u) {
+            okk[u] = e + u * G < e1;
+            tt[u] = st[min(e + u * G, e1 - 1)];
+          }
+          T2 w[UE];
 #pragma unroll
-      for (int b = 0; b < NBT; ++b) pv[u][b] = psi[(int64_t)min(b0 + b, nb - 1) * ld + idx[u]];
+          for (int u = 0; u < UE; ++u) w[u] = sp[tt[u] * ROW + b];
 #pragma unroll
-    for (int u = 0; u < SB; ++u) {
-      const bool valid = sb + u * (int)blockDim.x < ns;
+          for (int u = 0; u < UE; ++u) {
+            const int el = min(e + u * G, e1 - 1) - e0;
 #pragma unroll
-      for (int j = 0; j < MAXP; ++j) {
-        const double c = (valid && j < np) ? (double)bv[u][j] : 0.0;
+            for (int j = 0; j < MAXP; ++j) {
+              const T be = (okk[u] && j < np) ? bq[el * np + min(j, np - 1)] : T(0);
+              ar[j] += be * w[u].x;
+              ai[j] += be * w[u].y;
+            }
+          }
+        }
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) {
-          acc[j][b][0] += c * (double)pv[u][b].x;
-          acc[j][b][1] += c * (double)pv[u][b].y;
+        for (int j = 0; j < MAXP; ++j) {
+#pragma unroll
+          for (int off = NBS; off < kWave; off <<= 1) {
+            ar[j] += __shfl_xor(ar[j], off, kWave);
+            ai[j] += __shfl_xor(ai[j], off, kWave);
+          }
+        }
+        if (g == 0 && b < nbl) {
+          const int row = srow[q];
+#pragma unroll
+          for (int j = 0; j < MAXP; ++j)
+            if (j < np) part[(int64_t)(row + j) * nb + b0 + b] = cmake<T2>(T(ar[j]), T(ai[j]));
         }
       }
+      if (!one_batch) __syncthreads();
+      qa = qb;
     }
+    __syncthreads();  // sums done before the next band tile overwrites sp
   }
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
+}
+
+// dc[p][b] = D_p * sum over the tiles of projector p (ascending) of its
+// partial rows part[row][b].
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_nl_reduce(const c2<T>* __restrict__ part, int nb, int nproj, const int32_t* __restrict__ proj_pair_ptr,
+            const int32_t* __restrict__ proj_pairs, const T* __restrict__ D, c2<T>* __restrict__ dc) {
+  using T2 = c2<T>;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nproj * nb) return;
+  const int p = (int)(i / nb), b = (int)(i - (int64_t)p * nb);
+  const int j0 = proj_pair_ptr[p], j1 = proj_pair_ptr[p + 1];
+  double re = 0.0, im = 0.0;
+  for (int j = j0; j < j1; j += 4) {
+    T2 v[4];
 #pragma unroll
-  for (int j = 0; j < MAXP; ++j)
+    for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)proj_pairs[min(j + u, j1 - 1)] * nb + b];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        double v = wave_sum(acc[j][b][c]);
-        if (lane == 0) red[wid][(j * NBT + b) * 2 + c] = v;
+    for (int u = 0; u < 4; ++u)
+      if (j + u < j1) {
+        re += (double)v[u].x;
+        im += (double)v[u].y;
       }
-  __syncthreads();
-  const int nw = blockDim.x / kWave;
-  for (int t = threadIdx.x; t < np * NBT; t += blockDim.x) {
-    const int j = t / NBT, b = t - j * NBT;
-    if (b0 + b >= nb) continue;
-    double re = 0.0, im = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      re += red[w][(j * NBT + b) * 2 + 0];
-      im += red[w][(j * NBT + b) * 2 + 1];
-    }
-    const double d = (double)D[p0 + j];
-    dc[(int64_t)(p0 + j) * nb + b0 + b] = cmake<T2>(T(d * re), T(d * im));
   }
+  const double d = (double)D[p];
+  dc[(int64_t)p * nb + b] = cmake<T2>(T(d * re), T(d * im));
 }
 
 // Nonlocal scatter: hpsi[b][r] += sum over the entries of point r of
@@ -901,29 +1015,57 @@ static int pass_b(const ks_plan& p, int mode, c2<T>* buf, int64_t ld, int nb, co
   return 0;
 }
 
+// Band-tile width of the tiled projection: 16 bands over tiles of 256 points
+// in FP64 and 512 in FP32 (70 KB of LDS either way); the rest of the LDS
+// holds the tile's entries.
+constexpr int kProjBands = 16;
+
+void nl_tile_shape(int prec, const int n[3], int tdim[3]) {
+  const int want[3] = {prec == KS_FP64 ? 4 : 8, 8, 8};
+  for (int a = 0; a < 3; ++a) tdim[a] = std::min(want[a], n[a]);
+}
+
+size_t nl_project_lds(int tile_points, size_t real_bytes, int maxpt, int budget) {
+  return (size_t)tile_points * (kProjBands + 1) * 2 * real_bytes + (size_t)budget * real_bytes +
+         (size_t)3 * (maxpt + 1) * 4 + (size_t)budget * 2;
+}
+
+size_t nl_dc_bytes(const ks_plan& p, int nb) {
+  const size_t es = p.prec == KS_FP64 ? 16 : 8;
+  return (size_t)nb * (std::max<int64_t>(p.nproj, 1) + p.nrows) * es;
+}
+
 template <typename T>
 static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2<T>* dc, hipStream_t s) {
-  constexpr int NBT = 4;
-  // FP32 orbitals with at most 4 projectors per atom: 8 bands per tile, so
-  // that the support list and the projector values (20 B per point, against
-  // 32 B of orbital values for 4 FP32 bands) are read once per 8 bands
-  constexpr int NBT4 = sizeof(T) == 4 ? 8 : 4;
-  dim3 grid(p.natoms, (unsigned)ceil_div(nb, NBT));
   TimerScope ts(KF_NL_PROJECT, s);
-  const T* beta = static_cast<const T*>(p.beta);
-  const T* D = static_cast<const T*>(p.Dcoef);
+  c2<T>* part = dc + (int64_t)p.nproj * nb;
+  const int P = p.tdim[0] * p.tdim[1] * p.tdim[2];
+  const size_t lds = nl_project_lds(P, sizeof(T), p.maxpt, p.budget);
+  // blocks: every tile, its band tiles split into slices so that there are
+  // at least two blocks per compute unit
+  const int ntl = p.ntile[0] * p.ntile[1] * p.ntile[2];
+  const int nbt = (int)ceil_div(nb, kProjBands);
+  const int slices = std::max(1, std::min(nbt, (int)ceil_div(512, ntl)));
+  const int per = (int)ceil_div(nbt, slices);
+  dim3 grid((unsigned)ntl, (unsigned)ceil_div(nbt, per));
+  // P x 16 values per block over 1024 threads: 4 (FP64 tiles of 256) or 8
+#define KS_PROJ_LAUNCH(MAXP)                                                                                       \
+  hipLaunchKernelGGL((k_nl_project_tile<T, kProjBands, MAXP, sizeof(T) == 8 ? 4 : 8>), grid, dim3(kProjThreads),  \
+                     lds, s, psi, ld, nb, p.fft.ax[1].n, p.fft.ax[2].n, p.tdim[0], p.tdim[1], p.tdim[2],          \
+                     p.ntile[1], p.ntile[2], p.fft.ax[0].n, per, p.tile_pair_ptr, p.pair_ent_ptr, p.pair_boff,  \
+                     p.pair_row, p.ent_t, static_cast<const T*>(p.ent_beta), p.budget, p.maxpt, part)
   if (p.maxp <= 1)
-    hipLaunchKernelGGL((k_nl_project<T, 1, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
-                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+    KS_PROJ_LAUNCH(1);
   else if (p.maxp <= 4)
-    hipLaunchKernelGGL((k_nl_project<T, 4, NBT4>), dim3(p.natoms, (unsigned)ceil_div(nb, NBT4)), dim3(kThreads), 0,
-                       s, psi, ld, nb, p.supp_ptr, p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
-  else if (p.maxp <= 9)
-    hipLaunchKernelGGL((k_nl_project<T, 9, NBT>), grid, dim3(kThreads), 0, s, psi, ld, nb, p.supp_ptr,
-                       p.supp_idx, p.proj_ptr, p.beta_ptr, beta, D, dc, p.nproj);
+    KS_PROJ_LAUNCH(4);
   else
-    return fail(KS_E_UNSUPPORTED, "more than 9 projectors per atom");
-  KS_LAUNCH_CHECK("nl_project");
+    KS_PROJ_LAUNCH(9);
+#undef KS_PROJ_LAUNCH
+  KS_LAUNCH_CHECK("nl_project_tile");
+  const int64_t tot = (int64_t)p.nproj * nb;
+  hipLaunchKernelGGL((k_nl_reduce<T>), dim3((unsigned)ceil_div(tot, kThreads)), dim3(kThreads), 0, s, part, nb,
+                     p.nproj, p.proj_pair_ptr, p.proj_pairs, static_cast<const T*>(p.Dcoef), dc);
+  KS_LAUNCH_CHECK("nl_reduce");
   return 0;
 }
 
@@ -939,7 +1081,7 @@ static void launch_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, c
 // projector rows fit in 64 KB of LDS.
 template <typename T>
 static int nl_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
-  TimerScope ts(KF_NL_PROJECT, s);
+  TimerScope ts(KF_NL_SCATTER, s);
   const size_t row = (size_t)p.maxl * sizeof(c2<T>);
   constexpr size_t kMax = 64 * 1024;
   if (sizeof(T) == 4 && row * 33 <= kMax)
@@ -1005,7 +1147,7 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
 size_t apply_h_work_bytes(const ks_plan& p, int nb) {
   const size_t es = p.prec == KS_FP64 ? 16 : 8;
   size_t tmp = (size_t)p.Ng * nb * es;
-  size_t dc = (size_t)nb * (p.nproj > 0 ? p.nproj : 1) * es;
+  size_t dc = nl_dc_bytes(p, nb);
   return ((tmp + 255) / 256) * 256 + ((dc + 255) / 256) * 256;
 }
 

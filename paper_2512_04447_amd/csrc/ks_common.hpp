@@ -31,7 +31,10 @@ int hip_fail(hipError_t e, const char* what);
 // ------------------------------------------------------------------ timing
 // Event pair around launches of one kernel family when enabled (see
 // ks_kernel_timer in ksh.h); no-ops otherwise.
-enum KernelFamily { KF_GRAM = 0, KF_ROTATE, KF_PASS_A, KF_PASS_B, KF_PASS_C, KF_NL_PROJECT, KF_HEGV, KF_ZGEMM };
+enum KernelFamily {
+  KF_GRAM = 0, KF_ROTATE, KF_PASS_A, KF_PASS_B, KF_PASS_C, KF_NL_PROJECT, KF_HEGV, KF_ZGEMM, KF_GRAM_BASIS,
+  KF_NL_SCATTER
+};
 void timer_begin(int family, hipStream_t s);
 void timer_end(int family, hipStream_t s);
 

@@ -49,14 +49,6 @@ struct ks_plan {
   int64_t nnz = 0;              // (point, projector) pairs with a support value
   int64_t nblk = 0;             // point blocks
   void* Dcoef = nullptr;        // nproj couplings, plan precision
-  // projection tables, atom-major: support points of atom a at
-  // supp_idx[supp_ptr[a]..], its projectors proj_ptr[a].., values beta
-  // (atom, then projector, then point) from beta_ptr[a]
-  int32_t* supp_ptr = nullptr;
-  int32_t* supp_idx = nullptr;
-  int32_t* proj_ptr = nullptr;
-  int64_t* beta_ptr = nullptr;
-  void* beta = nullptr;         // plan precision
   int32_t* blk_ptr = nullptr;   // nblk + 1: projectors blk_ptr[k].. touch block k
   int32_t* blk_proj = nullptr;  // global projector ids, ascending within a block
   int32_t maxl = 0;             // largest per-block projector count
@@ -66,6 +58,28 @@ struct ks_plan {
   int32_t* ell_ptr = nullptr;   // nblk + 1
   uint16_t* ell_lp = nullptr;
   void* ell_beta = nullptr;     // plan precision
+  // projection table by boxes of grid points (tiles of tdim[0] x tdim[1] x
+  // tdim[2], ntile[a] per axis, the last one per axis possibly partial):
+  // tile k owns the (tile, atom) pairs tile_pair_ptr[k]..; pair q has the
+  // entries pair_ent_ptr[q].. (tile-local points ascending, ent_t) and, from
+  // pair_boff[q], the atom's np projector values at each of them (entry-major,
+  // ent_beta); its partial coefficients are rows pair_row[q] .. + np of the
+  // projection's partial buffer; projector p's rows, tiles ascending, are
+  // proj_pairs[proj_pair_ptr[p]..]
+  int32_t tdim[3] = {0, 0, 0};
+  int32_t ntile[3] = {0, 0, 0};
+  int64_t npairs = 0;
+  int64_t nrows = 0;                 // partial rows (tile, projector)
+  int32_t maxpt = 0;                 // most pairs in one tile
+  int32_t budget = 0;                // projector values staged per batch
+  int32_t* tile_pair_ptr = nullptr;  // ntiles + 1
+  int32_t* pair_ent_ptr = nullptr;   // npairs + 1
+  int32_t* pair_boff = nullptr;      // npairs + 1
+  int32_t* pair_row = nullptr;       // npairs + 1
+  uint16_t* ent_t = nullptr;
+  void* ent_beta = nullptr;          // plan precision
+  int32_t* proj_pair_ptr = nullptr;  // nproj + 1
+  int32_t* proj_pairs = nullptr;     // nrows
 };
 
 namespace ks {
@@ -89,6 +103,15 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
                   double* partial, double* E, hipStream_t s);
 
 size_t apply_h_work_bytes(const ks_plan& p, int nb);
+// Bytes of the nonlocal coefficient buffer of an H-apply (the coefficients
+// and the per-tile partial sums of the projection).
+size_t nl_dc_bytes(const ks_plan& p, int nb);
+// Tile shape of the projection table for the plan's precision (each block
+// stages tile x 16 bands of orbital values in LDS), and the kernel's LDS
+// bytes for tiles of `tile_points` points, reals of `real_bytes`, at most
+// maxpt pairs per tile and `budget` projector values staged at once.
+void nl_tile_shape(int prec, const int n[3], int tdim[3]);
+size_t nl_project_lds(int tile_points, size_t real_bytes, int maxpt, int budget);
 size_t precond_work_bytes(const ks_plan& p, int nb);
 
 // ---- projected CG for training targets (cg.hip) ----
