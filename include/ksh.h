@@ -240,6 +240,25 @@ int hegv_reduce_solve(int32_t n, int32_t nev, void* H, int32_t ldh, void* S, int
                       int32_t* info_dev, void* stream);
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes);
 
+/* The reduction step of the generalised eigensolve alone, by one of three
+ * methods (the comparison behind the paper's choice of two triangular solves
+ * over a two-sided reduction, paragraph after Eq. 1 and its eigensolver
+ * figure): S = L L^H (lower, in place; info_dev as hegv_reduce_solve), then
+ * K = L^-1 H L^-H, Hermitised, into K (n x n, ldk; H is not modified):
+ *   KS_REDUCE_INVERSE: L^-1 by one blocked solve on the identity, then two
+ *     products (what hegv_reduce_solve uses);
+ *   KS_REDUCE_TWO_TRSM: Y = L^-1 H and K = L^-1 Y^H by two blocked
+ *     triangular solves;
+ *   KS_REDUCE_TWO_SIDED: a blocked two-sided reduction of the xHEGST type
+ *     (per 32-column block: the diagonal block two-sided, the panel by one
+ *     solve and two products, the trailing matrix by a rank-2k update).
+ * Workspace: hegv_workspace_size(n, 1). */
+#define KS_REDUCE_INVERSE 0
+#define KS_REDUCE_TWO_TRSM 1
+#define KS_REDUCE_TWO_SIDED 2
+int hegv_reduce_variant(int32_t variant, int32_t n, const void* H, int32_t ldh, void* S, int32_t lds, void* K,
+                        int32_t ldk, void* work, size_t work_bytes, int32_t* info_dev, void* stream);
+
 /* hegv_reduce_solve for callers that cannot allocate memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same computation and the same results, with the workspace taken from a
@@ -295,6 +314,21 @@ int lobpcg_step(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st,
 #define KS_OP_ANGLE 6
 int ks_subspace_sin(const ks_plan* plan, const void* A, const void* B, int64_t ld, int32_t k, double* sin_max,
                     void* work, size_t work_bytes, void* stream);
+
+/* The dense products of the path as building blocks (also what the GEMM
+ * sweeps time): complex blocks of K rows (column-major, leading dimension
+ * ld), complex128 for precision KS_FP64 and complex64 for KS_MIXED_FP32.
+ * ks_gram_general: G = A^H B, m x m FP64 complex column-major (ldg >= m),
+ * every tile computed (not Hermitised), products on the matrix cores
+ * (FP64, or FP32 with FP64 sums of the K chunks).  Workspace:
+ * ks_gram_workspace_size.  ks_rotate_block: Y = V C, V of m columns, C an
+ * m x ncol matrix of the block precision (ldc >= m), Y of ncol columns
+ * (ldy >= K); Y must not overlap V. */
+int ks_gram_workspace_size(int64_t K, int32_t m, size_t* bytes);
+int ks_gram_general(int32_t precision, int64_t K, int32_t m, const void* A, const void* B, int64_t ld, void* G,
+                    int32_t ldg, void* work, size_t work_bytes, void* stream);
+int ks_rotate_block(int32_t precision, int64_t K, int32_t m, const void* V, int64_t ld, const void* C, int32_t ldc,
+                    int32_t ncol, void* Y, int64_t ldy, void* stream);
 
 /* Training targets for the learned preconditioner: for every column i at
  * once, solve the Jacobi-Davidson correction equation

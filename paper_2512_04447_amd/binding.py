@@ -35,9 +35,13 @@ EXPORTS = (
     "ks_apply_h",
     "ks_precond_apply",
     "ks_subspace_sin",
+    "ks_gram_workspace_size",
+    "ks_gram_general",
+    "ks_rotate_block",
     "hegv_reduce_solve",
     "hegv_workspace_size",
     "hegv_reduce_solve_noalloc",
+    "hegv_reduce_variant",
     "lobpcg_init",
     "lobpcg_step",
     "ks_jd_correction",
@@ -142,9 +146,13 @@ def load() -> C.CDLL:
     lib.ks_apply_h.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, sz, vp]
     lib.ks_precond_apply.argtypes = [vp, C.POINTER(KsLobpcgOpts), vp, vp, vp, vp, i64, i32, vp, vp, vp, sz, vp]
     lib.ks_subspace_sin.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
+    lib.ks_gram_workspace_size.argtypes = [i64, i32, C.POINTER(sz)]
+    lib.ks_gram_general.argtypes = [i32, i64, i32, vp, vp, i64, vp, i32, vp, sz, vp]
+    lib.ks_rotate_block.argtypes = [i32, i64, i32, vp, i64, vp, i32, i32, vp, i64, vp]
     lib.hegv_reduce_solve.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp, vp]
     lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
     lib.hegv_reduce_solve_noalloc.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, vp]
+    lib.hegv_reduce_variant.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
     lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
     lib.lobpcg_step.argtypes = [vp, vp, C.POINTER(KsLobpcgState), C.POINTER(KsLobpcgOpts), vp, sz, vp]
     f32 = C.c_float
@@ -339,6 +347,29 @@ def ks_subspace_sin(plan: Plan, A, B, k: int, out=None, work=None, stream=None):
     return out
 
 
+def ks_gram_general(precision: int, A, B, G, work=None, stream=None):
+    """G (m x m complex128, column-major: a tensor whose transpose is
+    contiguous) = A^H B for blocks A, B of shape (m, K) (rows are columns)."""
+    m, K = A.shape
+    if work is None:
+        n = C.c_size_t()
+        check(load().ks_gram_workspace_size(K, m, C.byref(n)), "ks_gram_workspace_size")
+        work = _work(n.value, A.device)
+    check(load().ks_gram_general(precision, K, m, _ptr(A), _ptr(B), A.stride(0), _ptr(G), G.stride(1), _ptr(work),
+                                 work.numel(), C.c_void_p(_stream(stream))), "ks_gram_general")
+    return G
+
+
+def ks_rotate_block(precision: int, V, Cm, Y, stream=None):
+    """Y (ncol, K) = (V^T C)^T for V of shape (m, K) and C (m x ncol,
+    column-major, the block precision)."""
+    m, K = V.shape
+    ncol = Y.shape[0]
+    check(load().ks_rotate_block(precision, K, m, _ptr(V), V.stride(0), _ptr(Cm), Cm.stride(1), ncol, _ptr(Y),
+                                 Y.stride(0), C.c_void_p(_stream(stream))), "ks_rotate_block")
+    return Y
+
+
 def kernel_timer(enable: bool, family: int) -> None:
     check(load().ks_kernel_timer(1 if enable else 0, family), "ks_kernel_timer")
 
@@ -366,6 +397,21 @@ def hegv_reduce_solve(H, S, nev: int, w, Cmat, info, work=None, stream=None):
     rc = load().hegv_reduce_solve(n, nev, _ptr(H), H.stride(1), _ptr(S), S.stride(1), _ptr(w), _ptr(Cmat),
                                   Cmat.stride(1), _ptr(work), work.numel(), _ptr(info), C.c_void_p(_stream(stream)))
     check(rc, "hegv_reduce_solve")
+
+
+KS_REDUCE_INVERSE, KS_REDUCE_TWO_TRSM, KS_REDUCE_TWO_SIDED = 0, 1, 2
+
+
+def hegv_reduce_variant(variant: int, H, S, K, info, work=None, stream=None):
+    """S <- chol(S) (lower) and K = L^-1 H L^-H by the chosen method;
+    column-major n x n complex128 device matrices (transposes contiguous)."""
+    n = H.shape[0]
+    if work is None:
+        work = _work(hegv_workspace_size(n, 1), H.device)
+    check(load().hegv_reduce_variant(variant, n, _ptr(H), H.stride(1), _ptr(S), S.stride(1), _ptr(K), K.stride(1),
+                                     _ptr(work), work.numel(), _ptr(info), C.c_void_p(_stream(stream))),
+          "hegv_reduce_variant")
+    return K
 
 
 class Lobpcg:

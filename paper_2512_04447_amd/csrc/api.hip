@@ -1095,6 +1095,75 @@ int hegv_reduce_solve_noalloc(int32_t n, int32_t nev, void* H, int32_t ldh, void
   return rc;
 }
 
+int ks_gram_workspace_size(int64_t K, int32_t m, size_t* bytes) {
+  if (K <= 0) return fail(-1, "K must be positive");
+  if (m <= 0) return fail(-2, "m must be positive");
+  if (!bytes) return fail(-3, "bytes is null");
+  *bytes = gram_work_bytes(m, K);
+  return 0;
+}
+
+int ks_gram_general(int32_t precision, int64_t K, int32_t m, const void* A, const void* B, int64_t ld, void* G,
+                    int32_t ldg, void* work, size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (precision != KS_FP64 && precision != KS_MIXED_FP32) return fail(-1, "precision must be KS_FP64 or KS_MIXED_FP32");
+  if (K <= 0) return fail(-2, "K must be positive");
+  if (m <= 0) return fail(-3, "m must be positive");
+  if (!A) return fail(-4, "A is null");
+  if (!B) return fail(-5, "B is null");
+  if (ld < K) return fail(-6, "ld < K");
+  if (!G) return fail(-7, "G is null");
+  if (ldg < m) return fail(-8, "ldg < m");
+  if (!work) return fail(-9, "work is null");
+  if (work_bytes < gram_work_bytes(m, K)) return fail(KS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == KS_FP64)
+    return gram_general<double>(blist<double>(A, nullptr, nullptr, ld, m), blist<double>(B, nullptr, nullptr, ld, m),
+                                m, K, static_cast<double2*>(G), ldg, work, s);
+  return gram_general<float>(blist<float>(A, nullptr, nullptr, ld, m), blist<float>(B, nullptr, nullptr, ld, m), m,
+                             K, static_cast<double2*>(G), ldg, work, s);
+}
+
+int ks_rotate_block(int32_t precision, int64_t K, int32_t m, const void* V, int64_t ld, const void* C, int32_t ldc,
+                    int32_t ncol, void* Y, int64_t ldy, void* stream) {
+  g_last_error.clear();
+  if (precision != KS_FP64 && precision != KS_MIXED_FP32) return fail(-1, "precision must be KS_FP64 or KS_MIXED_FP32");
+  if (K <= 0) return fail(-2, "K must be positive");
+  if (m <= 0) return fail(-3, "m must be positive");
+  if (!V) return fail(-4, "V is null");
+  if (ld < K) return fail(-5, "ld < K");
+  if (!C) return fail(-6, "C is null");
+  if (ldc < m) return fail(-7, "ldc < m");
+  if (ncol <= 0) return fail(-8, "ncol must be positive");
+  if (!Y) return fail(-9, "Y is null");
+  if (ldy < K) return fail(-10, "ldy < K");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision == KS_FP64)
+    return rotate<double>(blist<double>(V, nullptr, nullptr, ld, m), m, m, static_cast<const double2*>(C), ldc, ncol,
+                          K, static_cast<double2*>(Y), nullptr, ldy, s);
+  return rotate<float>(blist<float>(V, nullptr, nullptr, ld, m), m, m, static_cast<const float2*>(C), ldc, ncol, K,
+                       static_cast<float2*>(Y), nullptr, ldy, s);
+}
+
+int hegv_reduce_variant(int32_t variant, int32_t n, const void* H, int32_t ldh, void* S, int32_t lds, void* K,
+                        int32_t ldk, void* work, size_t work_bytes, int32_t* info_dev, void* stream) {
+  g_last_error.clear();
+  if (variant < KS_REDUCE_INVERSE || variant > KS_REDUCE_TWO_SIDED) return fail(-1, "unknown reduction variant");
+  if (n <= 0 || n > kHegvMaxN) return fail(-2, "n out of range");
+  if (!H) return fail(-3, "H is null");
+  if (ldh < n) return fail(-4, "ldh < n");
+  if (!S) return fail(-5, "S is null");
+  if (lds < n) return fail(-6, "lds < n");
+  if (!K) return fail(-7, "K is null");
+  if (ldk < n) return fail(-8, "ldk < n");
+  if (K == H || K == S) return fail(-7, "K must not alias H or S");
+  if (!work) return fail(-9, "work is null");
+  if (work_bytes < hegv_work(n, 1)) return fail(KS_E_WORKSPACE, "workspace too small");
+  if (!info_dev) return fail(-11, "info is null");
+  return reduce_variant(variant, n, static_cast<const double2*>(H), ldh, static_cast<double2*>(S), lds,
+                        static_cast<double2*>(K), ldk, work, info_dev, static_cast<hipStream_t>(stream));
+}
+
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
   if (n <= 0 || n > kHegvMaxN) return fail(-1, "n out of range (1..3700: the inverse iteration stages 44 bytes per row in LDS)");
   if (nev <= 0 || nev > n) return fail(-2, "nev out of range");

@@ -264,11 +264,14 @@ int potrf_deflate(int n, double2* S, int lds, void* work, int32_t* info, int32_t
 
 // B <- op(L)^-1 B using the inverted diagonal blocks from potrf.
 // tmp: NB x ncol.
+// blk0: index of L's first diagonal block among the factor's blocks (a
+// trailing factor L22 starts at block blk0 of the inverted diagonal blocks).
 int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ldb, void* potrf_workspace, void* tmp,
-         const int32_t* info, hipStream_t s) {
+         const int32_t* info, hipStream_t s, int blk0) {
   (void)info;
   if (n <= 0 || ncol <= 0) return 0;
-  PotrfWs w = potrf_ws(potrf_workspace, n);
+  PotrfWs w = potrf_ws(potrf_workspace, n + blk0 * NB);
+  w.linv += (size_t)blk0 * NB * NB;
   double2* T = static_cast<double2*>(tmp);
   int rc;
   const int nblk = (int)ceil_div(n, NB);
@@ -1673,7 +1676,7 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   hipLaunchKernelGGL(k_set_identity, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096)),
                      dim3(256), 0, s, ws.X, n, n);
   KS_LAUNCH_CHECK("identity");
-  if ((rc = trsm('N', n, n, S, lds_, ws.X, n, ws.potrf, ws.tmp, info, s))) return rc;
+  if ((rc = trsm('N', n, n, S, lds_, ws.X, n, ws.potrf, ws.tmp, info, s, 0))) return rc;
   // Y = X H (in K's buffer), K = Y X^H (in H), then K <- (K + K^H)/2
   if ((rc = zgemm('N', 'N', n, n, n, 1.0, ws.X, n, H, ldh, 0.0, ws.K, n, s))) return rc;
   if ((rc = zgemm('N', 'C', n, n, n, 1.0, ws.K, n, ws.X, n, 0.0, H, ldh, s))) return rc;
@@ -1788,6 +1791,97 @@ int hegv(int n, int nev, double2* H, int ldh, double2* S, int lds_, double* w, d
   hipLaunchKernelGGL(k_commit_results, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)n * nev, 256), 2048)),
                      dim3(256), 0, s, ws.wev, w, nev, ws.K, n, C, ldc, n, info);
   KS_LAUNCH_CHECK("commit");
+  return 0;
+}
+
+// ---------------------------------------------------------------- reduction variants
+// K = L^-1 H L^-H, three ways, for the comparison of the paper's choice (two
+// triangular solves instead of a two-sided reduction) on the GPU:
+//   0: L^-1 once (the blocked solve on the identity), then K = (L^-1 H) L^-H
+//      as two products (the form the eigensolve uses);
+//   1: the two triangular solves: Y = L^-1 H, then K = L^-1 Y^H (H Hermitian);
+//   2: a blocked two-sided reduction of the HEGST type: for each diagonal
+//      block, A11 <- L11^-1 A11 L11^-H, A21 <- A21 L11^-H - L21 A11 / 2,
+//      A22 <- A22 - A21 L21^H - L21 A21^H, A21 <- A21 - L21 A11 / 2,
+//      A21 <- L22^-1 A21 (the trailing blocks are reduced by the later
+//      steps); the lower triangle holds K, the upper is set from it.
+// Each ends with K <- (K + K^H)/2.
+
+// B = A^H (n x n)
+__global__ void k_conj_transpose(const double2* __restrict__ A, int lda, double2* __restrict__ B, int ldb, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const double2 a = A[j + (int64_t)i * lda];
+    B[i + (int64_t)j * ldb] = make_double2(a.x, -a.y);
+  }
+}
+
+// upper triangle from the lower one: K_ij = conj(K_ji) for i < j
+__global__ void k_upper_from_lower(double2* __restrict__ K, int ldk, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i < j) {
+      const double2 a = K[j + (int64_t)i * ldk];
+      K[i + (int64_t)j * ldk] = make_double2(a.x, -a.y);
+    } else if (i == j) {
+      K[i + (int64_t)j * ldk].y = 0.0;
+    }
+  }
+}
+
+static unsigned grid_nn(int n) { return (unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 4096); }
+
+int reduce_variant(int variant, int n, const double2* H, int ldh, double2* S, int lds_, double2* K, int ldk,
+                   void* work, int32_t* info, hipStream_t s) {
+  HegvWs ws = hegv_ws(work, n, 1);
+  PotrfWs pw = potrf_ws(ws.potrf, n);
+  int rc;
+  if ((rc = potrf_impl(n, S, lds_, ws.potrf, info, n, false, nullptr, s))) return rc;
+  const double2* L = S;
+  if (variant == 0) {
+    hipLaunchKernelGGL(k_set_identity, dim3(grid_nn(n)), dim3(256), 0, s, ws.X, n, n);
+    if ((rc = trsm('N', n, n, L, lds_, ws.X, n, ws.potrf, ws.tmp, info, s, 0))) return rc;
+    if ((rc = zgemm('N', 'N', n, n, n, 1.0, ws.X, n, H, ldh, 0.0, ws.K, n, s))) return rc;
+    if ((rc = zgemm('N', 'C', n, n, n, 1.0, ws.K, n, ws.X, n, 0.0, K, ldk, s))) return rc;
+  } else if (variant == 1) {
+    if ((rc = copy_block(H, ldh, ws.X, n, n, n, s))) return rc;
+    if ((rc = trsm('N', n, n, L, lds_, ws.X, n, ws.potrf, ws.tmp, info, s, 0))) return rc;
+    hipLaunchKernelGGL(k_conj_transpose, dim3(grid_nn(n)), dim3(256), 0, s, ws.X, n, K, ldk, n);
+    if ((rc = trsm('N', n, n, L, lds_, K, ldk, ws.potrf, ws.tmp, info, s, 0))) return rc;
+  } else {
+    if ((rc = copy_block(H, ldh, K, ldk, n, n, s))) return rc;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+      const int kb = std::min(NB, n - k0);
+      const int r0 = k0 + kb, rest = n - r0;
+      const double2* linv = pw.linv + (size_t)(k0 / NB) * NB * NB;
+      double2* A11 = K + k0 + (int64_t)k0 * ldk;
+      // A11 <- L11^-1 A11 L11^-H
+      if ((rc = zgemm('N', 'N', kb, kb, kb, 1.0, linv, NB, A11, ldk, 0.0, ws.K, n, s))) return rc;
+      if ((rc = zgemm('N', 'C', kb, kb, kb, 1.0, ws.K, n, linv, NB, 0.0, A11, ldk, s))) return rc;
+      if (rest <= 0) break;
+      double2* A21 = K + r0 + (int64_t)k0 * ldk;
+      double2* A22 = K + r0 + (int64_t)r0 * ldk;
+      const double2* L21 = L + r0 + (int64_t)k0 * lds_;
+      const double2* L22 = L + r0 + (int64_t)r0 * lds_;
+      // A21 <- A21 L11^-H - L21 A11 / 2
+      if ((rc = zgemm('N', 'C', rest, kb, kb, 1.0, A21, ldk, linv, NB, 0.0, ws.X, n, s))) return rc;
+      if ((rc = zgemm('N', 'N', rest, kb, kb, -0.5, L21, lds_, A11, ldk, 1.0, ws.X, n, s))) return rc;
+      // A22 <- A22 - A21 L21^H - L21 A21^H
+      if ((rc = zgemm('N', 'C', rest, rest, kb, -1.0, ws.X, n, L21, lds_, 1.0, A22, ldk, s))) return rc;
+      if ((rc = zgemm('N', 'C', rest, rest, kb, -1.0, L21, lds_, ws.X, n, 1.0, A22, ldk, s))) return rc;
+      // A21 <- A21 - L21 A11 / 2, then L22^-1 A21
+      if ((rc = zgemm('N', 'N', rest, kb, kb, -0.5, L21, lds_, A11, ldk, 1.0, ws.X, n, s))) return rc;
+      if ((rc = trsm('N', rest, kb, L22, lds_, ws.X, n, ws.potrf, ws.tmp, info, s, r0 / NB))) return rc;
+      if ((rc = copy_block(ws.X, n, A21, ldk, rest, kb, s))) return rc;
+    }
+    hipLaunchKernelGGL(k_upper_from_lower, dim3(grid_nn(n)), dim3(256), 0, s, K, ldk, n);
+  }
+  // K <- (K + K^H)/2 (out of place through X)
+  hipLaunchKernelGGL(k_hermitise_to, dim3((unsigned)n), dim3(256), 0, s, K, ldk, ws.X, n, n, nullptr);
+  if ((rc = copy_block(ws.X, n, K, ldk, n, n, s))) return rc;
+  KS_LAUNCH_CHECK("reduce_variant");
   return 0;
 }
 

@@ -81,6 +81,11 @@ int potrf_deflate(int n, double2* S, int lds, void* work, int32_t* info, int32_t
 // B <- op(L)^-1 B for the lower factor L from potrf (its workspace holds
 // the inverted diagonal blocks); op 'N' or 'C'.
 int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ldb, void* potrf_ws, void* tmp,
-         const int32_t* info, hipStream_t s);
+         const int32_t* info, hipStream_t s, int blk0 = 0);
+// K = L^-1 H L^-H after the Cholesky S = L L^H (S overwritten by L; info as
+// hegv), by variant 0 (L^-1 and two products), 1 (two triangular solves) or
+// 2 (blocked two-sided reduction); workspace hegv_work(n, 1).
+int reduce_variant(int variant, int n, const double2* H, int ldh, double2* S, int lds, double2* K, int ldk,
+                   void* work, int32_t* info, hipStream_t s);
 
 }  // namespace ks

@@ -416,3 +416,40 @@ def test_apply_h_with_an_atom_without_projectors(ks):
     err = np.abs(hx.cpu().numpy() - ref).max() / np.abs(ref).max()
     _say("  rel err", err)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, 5, 33, 64, 100, 257])
+def test_reduction_variants_match_oracle(ks, variant, n):
+    """K = L^-1 H L^-H by the explicit inverse, by two triangular solves and
+    by the blocked two-sided reduction, each against the oracle's two
+    forward substitutions; the factor against the oracle's Cholesky."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    _say("reduce variant", variant, n)
+    rng = np.random.default_rng(3000 + n)
+    # the reduction's rounding error grows like eps cond(S) (L^-1 on both
+    # sides); with cond(S) = 1e4 two correct orderings agree to about 1e-12
+    S = random_hpd(n, rng, cond=1e4)
+    Hm = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Hm = 0.5 * (Hm + Hm.conj().T)
+    L, info = ola.cholesky_lower(S)
+    assert info == 0
+    Y = ola.solve_lower(L, Hm)
+    Kref = ola.solve_lower(L, np.conj(Y.T))
+    Kref = 0.5 * (Kref + Kref.conj().T)
+    dH, dS = colmajor(Hm), colmajor(S)
+    dK = torch.zeros((n, n), dtype=torch.complex128, device="cuda").T
+    dinfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.hegv_reduce_variant(variant, dH, dS, dK, dinfo)
+    torch.cuda.synchronize()
+    assert int(dinfo.item()) == 0
+    Lg = np.tril(dS.cpu().numpy())
+    assert np.abs(Lg - L).max() <= 1e-12 * np.abs(L).max()
+    err = np.abs(dK.cpu().numpy() - Kref).max() / np.abs(Kref).max()
+    _say("  rel err", err)
+    assert err <= 5e-12
+    # H is not modified
+    assert np.array_equal(dH.cpu().numpy(), Hm)
