@@ -330,6 +330,36 @@ int ks_gram_general(int32_t precision, int64_t K, int32_t m, const void* A, cons
 int ks_rotate_block(int32_t precision, int64_t K, int32_t m, const void* V, int64_t ld, const void* C, int32_t ldc,
                     int32_t ncol, void* Y, int64_t ldy, void* stream);
 
+/* The self-consistent loop's steps around the eigensolve (the "Others" of
+ * the paper's SCF cost breakdown), for plans of either precision; fields
+ * are Ng FP64 values on the plan's grid.
+ * ks_density: n(r) = sum_{i < nocc} f_i |x_i(r)|^2, electrons per grid point
+ *   (sum_r n = sum_i f_i for orthonormal columns), from nocc columns of X
+ *   (ld); occ: device array of nocc occupations, or NULL for 2 each.
+ * ks_hartree: V_H from the periodic Poisson equation for rho = n / dV
+ *   (dV = L0 L1 L2 / Ng): V_H(G) = 4 pi rho(G) / |G|^2, V_H(0) = 0 (uniform
+ *   neutralising background), on the plan's FFT passes.
+ * ks_lda_xc: exchange-correlation potential v_xc and energy per electron
+ *   e_xc (may be NULL) of the local density approximation: Slater exchange
+ *   and the Perdew-Zunger parametrisation of the Ceperley-Alder correlation;
+ *   zero where rho <= 1e-30.
+ * ks_scf_potential: v_eff = v_ion + V_H[n] + v_xc[n] (Ng reals in the
+ *   plan's precision, ready for ks_apply_h and lobpcg_step) and terms[4] =
+ *   (sum V_H n, sum v_xc n, sum e_xc n, sum n) on the device.
+ * ks_mix_density: n_next = (1 - alpha) n_in + alpha n_out and
+ *   resid[0] = ||n_out - n_in||_2 on the device.
+ * Workspace (ks_hartree, ks_scf_potential, ks_mix_density):
+ * ks_workspace_size(KS_OP_SCF, 1). */
+#define KS_OP_SCF 7
+int ks_density(const ks_plan* plan, const void* X, int64_t ld, int32_t nocc, const double* occ, double* n,
+               void* stream);
+int ks_hartree(const ks_plan* plan, const double* n, double* v_h, void* work, size_t work_bytes, void* stream);
+int ks_lda_xc(const ks_plan* plan, const double* n, double* v_xc, double* e_xc, void* stream);
+int ks_scf_potential(const ks_plan* plan, const double* n, const double* v_ion, void* v_eff, double* terms,
+                     void* work, size_t work_bytes, void* stream);
+int ks_mix_density(const ks_plan* plan, double alpha, const double* n_in, const double* n_out, double* n_next,
+                   double* resid, void* work, size_t work_bytes, void* stream);
+
 /* Training targets for the learned preconditioner: for every column i at
  * once, solve the Jacobi-Davidson correction equation
  *   P (H - theta_i) P t_i = P r_i,  P = I - X X^H,  t_i in range(P)

@@ -23,4 +23,8 @@ What it computes, and where the paper defines it:
 * ``cnn``: a 3-layer periodic 3x3x3 convolutional network with its analytic
   backward pass.
 * ``cg``: the projected conjugate-gradient solve that makes training pairs.
+* ``scf``: the self-consistent loop around the eigensolve (density, the
+  Hartree potential by the periodic Poisson equation, a local density
+  approximation, linear mixing), the "Others" of the paper's SCF cost
+  breakdown.
 """

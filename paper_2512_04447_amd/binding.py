@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libksh.so")
 KS_FP64, KS_MIXED_FP32, KS_MIXED_BF16X3 = 0, 1, 2
 KS_PRECOND_NONE, KS_PRECOND_TPA, KS_PRECOND_CNN, KS_PRECOND_CNN_TPA = 0, 1, 2, 3
 KS_CNN_NPARAM = 9106
-KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD, KS_OP_PRECOND_CNN, KS_OP_ANGLE = 1, 2, 3, 4, 5, 6
+KS_OP_APPLY_H, KS_OP_PRECOND, KS_OP_LOBPCG, KS_OP_JD, KS_OP_PRECOND_CNN, KS_OP_ANGLE, KS_OP_SCF = 1, 2, 3, 4, 5, 6, 7
 # status words of a LOBPCG step
 KS_STATUS_WORDS = 8
 KS_ST_FLAGS, KS_ST_DEAD_W, KS_ST_DEAD_P, KS_ST_DEAD_BASIS, KS_ST_DEAD_X, KS_ST_INFO = range(6)
@@ -38,6 +38,11 @@ EXPORTS = (
     "ks_gram_workspace_size",
     "ks_gram_general",
     "ks_rotate_block",
+    "ks_density",
+    "ks_hartree",
+    "ks_lda_xc",
+    "ks_scf_potential",
+    "ks_mix_density",
     "hegv_reduce_solve",
     "hegv_workspace_size",
     "hegv_reduce_solve_noalloc",
@@ -147,6 +152,11 @@ def load() -> C.CDLL:
     lib.ks_precond_apply.argtypes = [vp, C.POINTER(KsLobpcgOpts), vp, vp, vp, vp, i64, i32, vp, vp, vp, sz, vp]
     lib.ks_subspace_sin.argtypes = [vp, vp, vp, i64, i32, vp, vp, sz, vp]
     lib.ks_gram_workspace_size.argtypes = [i64, i32, C.POINTER(sz)]
+    lib.ks_density.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.ks_hartree.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.ks_lda_xc.argtypes = [vp, vp, vp, vp, vp]
+    lib.ks_scf_potential.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.ks_mix_density.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, sz, vp]
     lib.ks_gram_general.argtypes = [i32, i64, i32, vp, vp, i64, vp, i32, vp, sz, vp]
     lib.ks_rotate_block.argtypes = [i32, i64, i32, vp, i64, vp, i32, i32, vp, i64, vp]
     lib.hegv_reduce_solve.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, sz, vp, vp]
@@ -345,6 +355,45 @@ def ks_subspace_sin(plan: Plan, A, B, k: int, out=None, work=None, stream=None):
                                 work.numel(), C.c_void_p(_stream(stream)))
     check(rc, "ks_subspace_sin")
     return out
+
+
+def _scf_work(plan: Plan, device):
+    return _work(plan.workspace_size(KS_OP_SCF, 1), device)
+
+
+def ks_density(plan: Plan, X, nocc: int, n, occ=None, stream=None):
+    """n (Ng float64) = electrons per grid point of the first nocc rows of X."""
+    check(load().ks_density(plan.handle, _ptr(X), X.stride(0), int(nocc), None if occ is None else _ptr(occ), _ptr(n),
+                            C.c_void_p(_stream(stream))), "ks_density")
+    return n
+
+
+def ks_hartree(plan: Plan, n, v_h, work=None, stream=None):
+    work = _scf_work(plan, n.device) if work is None else work
+    check(load().ks_hartree(plan.handle, _ptr(n), _ptr(v_h), _ptr(work), work.numel(), C.c_void_p(_stream(stream))),
+          "ks_hartree")
+    return v_h
+
+
+def ks_lda_xc(plan: Plan, n, v_xc, e_xc=None, stream=None):
+    check(load().ks_lda_xc(plan.handle, _ptr(n), _ptr(v_xc), None if e_xc is None else _ptr(e_xc),
+                           C.c_void_p(_stream(stream))), "ks_lda_xc")
+    return v_xc
+
+
+def ks_scf_potential(plan: Plan, n, v_ion, v_eff, terms, work=None, stream=None):
+    """v_eff = v_ion + V_H[n] + v_xc[n] (plan precision); terms (4 float64)."""
+    work = _scf_work(plan, n.device) if work is None else work
+    check(load().ks_scf_potential(plan.handle, _ptr(n), _ptr(v_ion), _ptr(v_eff), _ptr(terms), _ptr(work),
+                                  work.numel(), C.c_void_p(_stream(stream))), "ks_scf_potential")
+    return v_eff
+
+
+def ks_mix_density(plan: Plan, alpha: float, n_in, n_out, n_next, resid, work=None, stream=None):
+    work = _scf_work(plan, n_in.device) if work is None else work
+    check(load().ks_mix_density(plan.handle, float(alpha), _ptr(n_in), _ptr(n_out), _ptr(n_next), _ptr(resid),
+                                _ptr(work), work.numel(), C.c_void_p(_stream(stream))), "ks_mix_density")
+    return n_next
 
 
 def ks_gram_general(precision: int, A, B, G, work=None, stream=None):

@@ -956,6 +956,7 @@ int ks_workspace_size(const ks_plan* p, int32_t op, int32_t nb, size_t* bytes) {
     case KS_OP_PRECOND: *bytes = precond_full_work_bytes(*p, nb, false); return 0;
     case KS_OP_PRECOND_CNN: *bytes = precond_full_work_bytes(*p, nb, true); return 0;
     case KS_OP_ANGLE: *bytes = angle_work_bytes(*p, nb); return 0;
+    case KS_OP_SCF: *bytes = scf_work_bytes(*p); return 0;
     case KS_OP_LOBPCG: *bytes = lobpcg_work_bytes(*p, nb); return 0;
     case KS_OP_JD: *bytes = jd_work_bytes(*p, nb); return 0;
     default: return fail(-2, "unknown op");
@@ -1093,6 +1094,62 @@ int hegv_reduce_solve_noalloc(int32_t n, int32_t nev, void* H, int32_t ldh, void
             work, info_dev, nullptr, static_cast<hipStream_t>(stream));
   g_timers_suppressed = false;
   return rc;
+}
+
+int ks_density(const ks_plan* p, const void* X, int64_t ld, int32_t nocc, const double* occ, double* n,
+               void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!X) return fail(-2, "X is null");
+  if (ld < p->Ng) return fail(-3, "ld < Ng");
+  if (nocc <= 0 || nocc > p->nb_max) return fail(-4, "nocc out of range");
+  if (!n) return fail(-6, "n is null");
+  return density_impl(*p, X, ld, nocc, occ, n, static_cast<hipStream_t>(stream));
+}
+
+int ks_hartree(const ks_plan* p, const double* n, double* v_h, void* work, size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!n) return fail(-2, "n is null");
+  if (!v_h) return fail(-3, "v_h is null");
+  if (!work) return fail(-4, "work is null");
+  if (work_bytes < scf_work_bytes(*p)) return fail(KS_E_WORKSPACE, "workspace too small");
+  return hartree_impl(*p, n, v_h, work, static_cast<hipStream_t>(stream));
+}
+
+int ks_lda_xc(const ks_plan* p, const double* n, double* v_xc, double* e_xc, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!n) return fail(-2, "n is null");
+  if (!v_xc) return fail(-3, "v_xc is null");
+  return lda_impl(*p, n, v_xc, e_xc, static_cast<hipStream_t>(stream));
+}
+
+int ks_scf_potential(const ks_plan* p, const double* n, const double* v_ion, void* v_eff, double* terms, void* work,
+                     size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!n) return fail(-2, "n is null");
+  if (!v_ion) return fail(-3, "v_ion is null");
+  if (!v_eff) return fail(-4, "v_eff is null");
+  if (!terms) return fail(-5, "terms is null");
+  if (!work) return fail(-6, "work is null");
+  if (work_bytes < scf_work_bytes(*p)) return fail(KS_E_WORKSPACE, "workspace too small");
+  return scf_potential_impl(*p, n, v_ion, v_eff, terms, work, static_cast<hipStream_t>(stream));
+}
+
+int ks_mix_density(const ks_plan* p, double alpha, const double* n_in, const double* n_out, double* n_next,
+                   double* resid, void* work, size_t work_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(-1, "plan is null");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(-2, "alpha must lie in [0, 1]");
+  if (!n_in) return fail(-3, "n_in is null");
+  if (!n_out) return fail(-4, "n_out is null");
+  if (!n_next) return fail(-5, "n_next is null");
+  if (!resid) return fail(-6, "resid is null");
+  if (!work) return fail(-7, "work is null");
+  if (work_bytes < scf_work_bytes(*p)) return fail(KS_E_WORKSPACE, "workspace too small");
+  return mix_impl(*p, alpha, n_in, n_out, n_next, resid, work, static_cast<hipStream_t>(stream));
 }
 
 int ks_gram_workspace_size(int64_t K, int32_t m, size_t* bytes) {

@@ -405,6 +405,8 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
 // ---------------------------------------------------------------- pass B
 // MODE 0: multiply by T(G) = |G|^2/2.  MODE 1: multiply by the TPA factor
 // K(T(G)/E_band).  MODE 2: no inverse; partial[block] = sum T(G)|f(G)|^2.
+// MODE 3: multiply by the periodic Poisson kernel 4 pi / |G|^2 = 2 pi / T(G)
+// (0 at G = 0).
 template <typename T>
 __device__ inline T kinetic_of(const Fft3& f, int kx, int ky, int kz) {
   const T gx = T(f.twopi_over_L[0]) * T(wrap_m(kx, f.ax[0].n));
@@ -473,7 +475,9 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int kx = i / zc, z = i - kx * zc;
     const T t = kinetic_of<T>(f, kx, y, z0 + z);
-    const T fac = (MODE == 0) ? t : tpa_factor<T>(t * einv);
+    const T fac = (MODE == 0)   ? t
+                  : (MODE == 3) ? (t > T(0) ? T(2.0 * 3.14159265358979323846) / t : T(0))
+                                : tpa_factor<T>(t * einv);
     T2 v = s[i];
     s[i] = cmake<T2>(v.x * fac, -v.y * fac);  // conj for the inverse transform
   }
@@ -989,6 +993,10 @@ static void launch_pencil(const ks_plan& p, int mode, dim3 grid, c2<T>* buf, int
       hipLaunchKernelGGL((k_pass_b<T, 16, 1, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
                          tw0, E, partial);
       break;
+    case 3:
+      hipLaunchKernelGGL((k_pass_b<T, 16, 3, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
+                         tw0, E, partial);
+      break;
     default:
       hipLaunchKernelGGL((k_pass_b<T, 16, 2, CN, CZC>), grid, dim3(kThreads), p.lds_pencil, s, p.fft, buf, ld, p.zc,
                          tw0, E, partial);
@@ -1143,6 +1151,20 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
   }
   return pass_c<T>(p, 1, tmp, ldt, W, ld, nb, nullptr, nullptr, 0, nullptr, res, lock_tol, s);
 }
+
+// Periodic Poisson solve of one real field: out = IFFT(2 pi / T(G) FFT(in))
+// on complex buffers (imaginary part of in zero), through the three passes;
+// `one` is a device double holding 1 (the unmasked inverse of pass C).
+template <typename T>
+int poisson(const ks_plan& p, const c2<T>* in, c2<T>* tmp, c2<T>* out, const double* one, hipStream_t s) {
+  int rc;
+  const int64_t ld = p.Ng;
+  if ((rc = pass_a<T>(p, 0, in, nullptr, nullptr, ld, tmp, ld, 1, nullptr, s))) return rc;
+  if ((rc = pass_b<T>(p, 3, tmp, ld, 1, nullptr, nullptr, s))) return rc;
+  return pass_c<T>(p, 1, tmp, ld, out, ld, 1, nullptr, nullptr, 0, nullptr, one, 0.0, s);
+}
+template int poisson<double>(const ks_plan&, const double2*, double2*, double2*, const double*, hipStream_t);
+template int poisson<float>(const ks_plan&, const float2*, float2*, float2*, const double*, hipStream_t);
 
 size_t apply_h_work_bytes(const ks_plan& p, int nb) {
   const size_t es = p.prec == KS_FP64 ? 16 : 8;

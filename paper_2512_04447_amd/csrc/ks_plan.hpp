@@ -103,6 +103,10 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
                   double* partial, double* E, hipStream_t s);
 
 size_t apply_h_work_bytes(const ks_plan& p, int nb);
+// One real field through the periodic Poisson kernel 4 pi / |G|^2 (G = 0
+// dropped): out = IFFT(4 pi / |G|^2 FFT(in)), complex buffers of Ng.
+template <typename T>
+int poisson(const ks_plan& p, const c2<T>* in, c2<T>* tmp, c2<T>* out, const double* one, hipStream_t s);
 // Bytes of the nonlocal coefficient buffer of an H-apply (the coefficients
 // and the per-tile partial sums of the projection).
 size_t nl_dc_bytes(const ks_plan& p, int nb);
@@ -113,6 +117,16 @@ size_t nl_dc_bytes(const ks_plan& p, int nb);
 void nl_tile_shape(int prec, const int n[3], int tdim[3]);
 size_t nl_project_lds(int tile_points, size_t real_bytes, int maxpt, int budget);
 size_t precond_work_bytes(const ks_plan& p, int nb);
+
+// ---- the SCF loop's steps around the eigensolve (scf.hip) ----
+size_t scf_work_bytes(const ks_plan& p);
+int density_impl(const ks_plan& p, const void* X, int64_t ld, int nocc, const double* occ, double* n, hipStream_t s);
+int hartree_impl(const ks_plan& p, const double* n, double* vh, void* work, hipStream_t s);
+int lda_impl(const ks_plan& p, const double* n, double* vxc, double* exc, hipStream_t s);
+int scf_potential_impl(const ks_plan& p, const double* n, const double* v_ion, void* v_eff, double* terms,
+                       void* work, hipStream_t s);
+int mix_impl(const ks_plan& p, double alpha, const double* n_in, const double* n_out, double* n_next, double* resid,
+             void* work, hipStream_t s);
 
 // ---- projected CG for training targets (cg.hip) ----
 size_t jd_work_bytes(const ks_plan& p, int nb);

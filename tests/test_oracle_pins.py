@@ -627,3 +627,86 @@ def test_projector_values_follow_the_gaussian_and_solid_harmonic_shapes():
     assert np.abs(bxy[plane]).max() <= 1e-15
     for v in vals:
         assert abs(float(np.sum(v * v)) - 1.0) <= 1e-13
+
+
+# ---------------------------------------------------------------- SCF pieces
+from oracle import scf as oscf  # noqa: E402
+
+
+def test_hartree_of_a_plane_wave_density_is_four_pi_over_g2():
+    """rho = c + a cos(G.r) gives V_H = 4 pi a / |G|^2 cos(G.r) (the constant
+    is removed by the neutralising background)."""
+    n, L = 10, 6.0
+    h = L / n
+    idx = np.arange(n) * h
+    X, Y, Z = np.meshgrid(idx, idx, idx, indexing="ij")
+    G = 2 * math.pi / L * np.array([1, 2, -1])
+    ph = G[0] * X + G[1] * Y + G[2] * Z
+    c, a = 0.3, 0.05
+    dV = h ** 3
+    nper = ((c + a * np.cos(ph)) * dV).ravel()
+    vh = oscf.hartree(nper, n, L)
+    expect = (4 * math.pi * a / float(G @ G) * np.cos(ph)).ravel()
+    assert np.abs(vh - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_lda_exchange_is_the_electron_gas_constant_and_potentials_are_derivatives():
+    """Slater exchange per electron is -0.458165/r_s (the uniform electron
+    gas, 3/4 (9/(4 pi^2))^(1/3)); the potentials are the density derivatives
+    of rho * e_xc (central differences), on both sides of r_s = 1."""
+    rs = np.array([0.3, 0.7, 0.99, 1.01, 2.0, 5.0, 12.0])
+    rho = 3.0 / (4.0 * math.pi * rs ** 3)
+    exc, vxc = oscf.lda_xc(rho)
+    ex = -0.75 * np.cbrt(3.0 * rho / math.pi)
+    np.testing.assert_allclose(ex * rs, -0.458165293283143, rtol=1e-12)
+    h = 1e-6 * rho
+    ep, _ = oscf.lda_xc(rho + h)
+    em, _ = oscf.lda_xc(rho - h)
+    deriv = ((rho + h) * ep - (rho - h) * em) / (2 * h)
+    np.testing.assert_allclose(vxc, deriv, rtol=1e-7)
+    e0, v0 = oscf.lda_xc(np.array([0.0, 1e-40]))
+    assert np.all(e0 == 0.0) and np.all(v0 == 0.0)
+
+
+def test_density_counts_the_electrons():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((5, 300)) + 1j * rng.standard_normal((5, 300))
+    Q, _ = np.linalg.qr(A.T)
+    X = Q.T
+    occ = np.array([2.0, 2.0, 2.0, 1.0, 0.5])
+    n = oscf.density(X, occ)
+    assert abs(n.sum() - occ.sum()) <= 1e-12
+    assert np.all(n >= 0)
+
+
+def _dense_eigensolver(nb):
+    def solve(cell, X0):
+        Hd = np.stack([oh.apply_h(cell, e[None])[0] for e in np.eye(cell.Ng, dtype=complex)], axis=1)
+        w, V = np.linalg.eigh(0.5 * (Hd + Hd.conj().T))
+        return w[:nb], V[:, :nb].T.copy()
+    return solve
+
+
+def test_scf_with_lobpcg_reaches_the_fixed_point_of_the_scf_with_dense_eigh():
+    """The SCF loop's fixed point does not depend on the eigensolver: with the
+    oracle's LOBPCG inside it reaches the density and energy of the same loop
+    with a dense library eigensolve (8^3 grid, one atom with s and p
+    projectors, 5 occupied bands closing a shell: the bare spectrum has a
+    gap of 0.18 Ha above the fifth level)."""
+    cfg = ki.custom_config("scf8", 5.0, 8, ((0.3, 0.4, 0.5),), 8, lmax=1, rc=0.5)
+    cell = ki.make_cell(cfg)
+    oc = oh.oracle_cell(cfg, cell.D)
+    nocc = 5
+    dense = _dense_eigensolver(cfg.nb)
+    ref = oscf.run(oc, nocc, dense, None, alpha=0.3, tol=1e-9, maxit=80)
+
+    def lob(cell_v, X0):
+        X0 = ki.make_x0(cfg) if X0 is None else X0
+        st, _ = olob.run(cell_v, X0, cfg.nb, 1e-10, 300, olob.tpa_preconditioner(cell_v))
+        return st.theta, st.X
+
+    got = oscf.run(oc, nocc, lob, None, alpha=0.3, tol=1e-9, maxit=80)
+    assert ref.iterations < 80 and got.iterations < 80
+    assert np.abs(got.n - ref.n).max() <= 1e-8
+    assert abs(got.energy - ref.energy) <= 1e-9
+    assert np.abs(got.theta[:nocc] - ref.theta[:nocc]).max() <= 1e-9
