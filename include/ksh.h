@@ -259,6 +259,19 @@ int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes);
 int hegv_reduce_variant(int32_t variant, int32_t n, const void* H, int32_t ldh, void* S, int32_t lds, void* K,
                         int32_t ldk, void* work, size_t work_bytes, int32_t* info_dev, void* stream);
 
+/* The same three reductions for real symmetric H and S (the Gamma-point
+ * case, where orbitals and subspace matrices are real: the real-versus-
+ * complex comparison of the paper's eigensolver figure).  H, S, K: n x n
+ * real FP64, column-major, device; S <- L (lower, in place; the strict
+ * upper triangle does not enter the result and is left undefined), H is not modified, K receives
+ * L^-1 H L^-T symmetrised.  info_dev (device int32): 0, or n + k when the
+ * leading minor k of S is not positive definite (pivot <= 1e-14 max diag(S));
+ * K is then meaningless.  Workspace: sygv_reduce_workspace_size(n)
+ * (about 2 n^2 doubles).  Errors: -i for argument i before any launch. */
+int sygv_reduce_variant(int32_t variant, int32_t n, const double* H, int32_t ldh, double* S, int32_t lds,
+                        double* K, int32_t ldk, void* work, size_t work_bytes, int32_t* info_dev, void* stream);
+int sygv_reduce_workspace_size(int32_t n, size_t* bytes);
+
 /* hegv_reduce_solve for callers that cannot allocate memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same computation and the same results, with the workspace taken from a
@@ -374,8 +387,11 @@ int ks_jd_correction(const ks_plan* plan, const void* v_loc, const void* X, cons
                      const void* R, int64_t ld, int32_t nb, int32_t maxit, double rtol, void* T,
                      int32_t* iters, void* work, size_t work_bytes, void* stream);
 
-/* Learned-preconditioner training kernels (FP32 activations and weights,
- * FP64 reductions).  cnn_workspace_size: floats of forward activations kept
+/* Learned-preconditioner training kernels.  Every convolution (forward,
+ * backward-data, weight gradient) runs on the bfloat16 matrix cores: its two
+ * operands are rounded to the nearest bfloat16 (ties to even), products and
+ * sums are FP32; parameters, activations, bias gradients and Adam are FP32,
+ * sums over tiles and samples FP64.  cnn_workspace_size: floats of forward activations kept
  * for backward (act_floats) and bytes of backward workspace for nbatch
  * samples on the plan's grid. */
 int cnn_workspace_size(const ks_plan* plan, int32_t nbatch, size_t* act_floats, size_t* work_bytes);
@@ -405,9 +421,8 @@ int cnn_make_input(const ks_plan* plan, const void* R, int64_t ld, const double*
  * to y, so cnn_backward is unchanged. */
 int cnn_add_skip(const ks_plan* plan, int32_t nbatch, const float* x, float* y, void* stream);
 /* Inference of the network as lobpcg_step applies it (KS_PRECOND_CNN and
- * KS_PRECOND_CNN_TPA): y[nbatch][2][Ng] = net(x[nbatch][3][Ng]) with the
- * 16 -> 16 layer computed by cnn_conv16_bf16 (bfloat16 products) and the two
- * other layers in FP32.  buf: 32 * nbatch * Ng floats of scratch (the
+ * KS_PRECOND_CNN_TPA): y[nbatch][2][Ng] = net(x[nbatch][3][Ng]), every
+ * layer on the bfloat16 matrix cores exactly as in cnn_forward.  buf: 32 * nbatch * Ng floats of scratch (the
  * act_floats of cnn_workspace_size suffice). */
 int cnn_infer(const ks_plan* plan, const float* params, int32_t nbatch, const float* x, float* y,
               float* buf, void* stream);

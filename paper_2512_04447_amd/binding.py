@@ -47,6 +47,8 @@ EXPORTS = (
     "hegv_workspace_size",
     "hegv_reduce_solve_noalloc",
     "hegv_reduce_variant",
+    "sygv_reduce_variant",
+    "sygv_reduce_workspace_size",
     "lobpcg_init",
     "lobpcg_step",
     "ks_jd_correction",
@@ -163,6 +165,8 @@ def load() -> C.CDLL:
     lib.hegv_workspace_size.argtypes = [i32, i32, C.POINTER(sz)]
     lib.hegv_reduce_solve_noalloc.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp, i32, vp, vp]
     lib.hegv_reduce_variant.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
+    lib.sygv_reduce_variant.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, sz, vp, vp]
+    lib.sygv_reduce_workspace_size.argtypes = [i32, C.POINTER(sz)]
     lib.lobpcg_init.argtypes = [vp, vp, C.POINTER(KsLobpcgState), vp, sz, vp]
     lib.lobpcg_step.argtypes = [vp, vp, C.POINTER(KsLobpcgState), C.POINTER(KsLobpcgOpts), vp, sz, vp]
     f32 = C.c_float
@@ -463,6 +467,24 @@ def hegv_reduce_variant(variant: int, H, S, K, info, work=None, stream=None):
     return K
 
 
+def sygv_reduce_workspace_size(n: int) -> int:
+    out = C.c_size_t()
+    check(load().sygv_reduce_workspace_size(n, C.byref(out)), "sygv_reduce_workspace_size")
+    return out.value
+
+
+def sygv_reduce_variant(variant: int, H, S, K, info, work=None, stream=None):
+    """The real-symmetric reduction: S <- chol(S) (lower) and K = L^-1 H L^-T;
+    column-major n x n float64 device matrices (transposes contiguous)."""
+    n = H.shape[0]
+    if work is None:
+        work = _work(sygv_reduce_workspace_size(n), H.device)
+    check(load().sygv_reduce_variant(variant, n, _ptr(H), H.stride(1), _ptr(S), S.stride(1), _ptr(K), K.stride(1),
+                                     _ptr(work), work.numel(), _ptr(info), C.c_void_p(_stream(stream))),
+          "sygv_reduce_variant")
+    return K
+
+
 class Lobpcg:
     """Device buffers of one LOBPCG run and the calls that advance it.
 
@@ -604,8 +626,10 @@ class Cnn:
         return self.y[:nb]
 
     def infer(self, x, nb=None, stream=None):
-        """y = net(x) as lobpcg_step applies it (16 -> 16 layer on bfloat16
-        MFMA); uses the activation buffer as scratch."""
+        """y = net(x) as lobpcg_step applies it (the same bfloat16
+        matrix-core layers as ``forward``, no activations kept); uses the
+        activation buffer as scratch and returns the same buffer as
+        ``forward``."""
         nb = x.shape[0] if nb is None else nb
         check(load().cnn_infer(self.plan.handle, _ptr(self.params), nb, _ptr(x), _ptr(self.y), _ptr(self.acts),
                                C.c_void_p(_stream(stream))), "cnn_infer")

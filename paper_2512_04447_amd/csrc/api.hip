@@ -1221,6 +1221,31 @@ int hegv_reduce_variant(int32_t variant, int32_t n, const void* H, int32_t ldh, 
                         static_cast<double2*>(K), ldk, work, info_dev, static_cast<hipStream_t>(stream));
 }
 
+int sygv_reduce_variant(int32_t variant, int32_t n, const double* H, int32_t ldh, double* S, int32_t lds, double* K,
+                        int32_t ldk, void* work, size_t work_bytes, int32_t* info_dev, void* stream) {
+  g_last_error.clear();
+  if (variant < KS_REDUCE_INVERSE || variant > KS_REDUCE_TWO_SIDED) return fail(-1, "unknown reduction variant");
+  if (n <= 0 || n > kHegvMaxN) return fail(-2, "n out of range");
+  if (!H) return fail(-3, "H is null");
+  if (ldh < n) return fail(-4, "ldh < n");
+  if (!S) return fail(-5, "S is null");
+  if (lds < n) return fail(-6, "lds < n");
+  if (!K) return fail(-7, "K is null");
+  if (ldk < n) return fail(-8, "ldk < n");
+  if (K == H || K == S) return fail(-7, "K must not alias H or S");
+  if (!work) return fail(-9, "work is null");
+  if (work_bytes < real_reduce_work(n)) return fail(KS_E_WORKSPACE, "workspace too small");
+  if (!info_dev) return fail(-11, "info is null");
+  return real_reduce_variant(variant, n, H, ldh, S, lds, K, ldk, work, info_dev, static_cast<hipStream_t>(stream));
+}
+
+int sygv_reduce_workspace_size(int32_t n, size_t* bytes) {
+  if (n <= 0 || n > kHegvMaxN) return fail(-1, "n out of range");
+  if (!bytes) return fail(-2, "bytes is null");
+  *bytes = real_reduce_work(n);
+  return 0;
+}
+
 int hegv_workspace_size(int32_t n, int32_t nev, size_t* bytes) {
   if (n <= 0 || n > kHegvMaxN) return fail(-1, "n out of range (1..3700: the inverse iteration stages 44 bytes per row in LDS)");
   if (nev <= 0 || nev > n) return fail(-2, "nev out of range");

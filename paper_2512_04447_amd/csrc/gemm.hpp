@@ -87,5 +87,10 @@ int trsm(char op, int n, int ncol, const double2* L, int ldl, double2* B, int ld
 // 2 (blocked two-sided reduction); workspace hegv_work(n, 1).
 int reduce_variant(int variant, int n, const double2* H, int ldh, double2* S, int lds, double2* K, int ldk,
                    void* work, int32_t* info, hipStream_t s);
+// The real-symmetric form of reduce_variant (dense_real.hip): S = L L^T,
+// K = L^-1 H L^-T, real FP64; workspace real_reduce_work(n).
+size_t real_reduce_work(int n);
+int real_reduce_variant(int variant, int n, const double* H, int ldh, double* S, int lds, double* K, int ldk,
+                        void* work, int32_t* info, hipStream_t s);
 
 }  // namespace ks

@@ -46,6 +46,15 @@ def test_host_validation_rejects_bad_arguments_without_a_gpu():
     # the dense eigensolve's size limit (LDS of the inverse iteration)
     assert lib.hegv_workspace_size(3701, 10, C.byref(n)) == -1
     assert lib.hegv_workspace_size(3700, 10, C.byref(n)) == 0
+    # the real-symmetric reduction
+    assert lib.sygv_reduce_workspace_size(0, C.byref(n)) == -1
+    assert lib.sygv_reduce_workspace_size(100, C.byref(n)) == 0 and n.value >= 2 * 100 * 100 * 8
+    fake = C.c_void_p(16)  # never dereferenced: the calls below fail their checks first
+    assert lib.sygv_reduce_variant(3, 4, fake, 4, fake, 4, C.c_void_p(32), 4, fake, 1 << 20, fake, None) == -1
+    assert lib.sygv_reduce_variant(0, 4, None, 4, fake, 4, C.c_void_p(32), 4, fake, 1 << 20, fake, None) == -3
+    assert lib.sygv_reduce_variant(0, 4, fake, 3, fake, 4, C.c_void_p(32), 4, fake, 1 << 20, fake, None) == -4
+    assert lib.sygv_reduce_variant(0, 4, fake, 4, fake, 4, fake, 4, fake, 1 << 20, fake, None) == -7
+    assert lib.sygv_reduce_variant(0, 4, fake, 4, fake, 4, C.c_void_p(32), 4, fake, 8, fake, None) == -2001
     assert lib.ks_workspace_size(None, 1, 1, C.byref(n)) == -1
     assert lib.ks_apply_h(None, None, None, 0, None, 0, 1, None, 0, None) == -1
     assert lib.lobpcg_step(None, None, None, None, None, 0, None) == -1

@@ -420,6 +420,72 @@ def test_apply_h_with_an_atom_without_projectors(ks):
 
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n", [1, 5, 33, 64, 100, 257])
+def test_real_symmetric_reduction_variants_match_oracle(ks, variant, n):
+    """The Gamma-point (real symmetric) reduction by its three methods
+    against the oracle's Cholesky and two forward substitutions, which on a
+    real pencil return real values (imaginary parts exactly zero)."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    _say("real reduce variant", variant, n)
+    rng = np.random.default_rng(4000 + n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    S = (Q * np.logspace(0, -4, n)) @ Q.T
+    S = 0.5 * (S + S.T)
+    Hm = rng.standard_normal((n, n))
+    Hm = 0.5 * (Hm + Hm.T)
+    L, info = ola.cholesky_lower(S)
+    assert info == 0 and not np.any(L.imag)
+    Y = ola.solve_lower(L, Hm)
+    Kref = ola.solve_lower(L, Y.T)
+    assert not np.any(Kref.imag)
+    Kref = 0.5 * (Kref.real + Kref.real.T)
+    dH, dS = colmajor(Hm), colmajor(S)
+    dK = torch.zeros((n, n), dtype=torch.float64, device="cuda").T
+    dinfo = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    b.sygv_reduce_variant(variant, dH, dS, dK, dinfo)
+    torch.cuda.synchronize()
+    assert int(dinfo.item()) == 0
+    Lg = np.tril(dS.cpu().numpy())
+    assert np.abs(Lg - L.real).max() <= 1e-12 * np.abs(L).max()
+    Kg = dK.cpu().numpy()
+    assert np.array_equal(Kg, Kg.T)
+    err = np.abs(Kg - Kref).max() / np.abs(Kref).max()
+    _say("  rel err", err)
+    assert err <= 5e-12
+    assert np.array_equal(dH.cpu().numpy(), Hm)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_real_symmetric_reduction_reports_indefinite_overlap(ks, variant):
+    """A real S whose leading minor 37 is singular: info = n + 37, as the
+    oracle's Cholesky reports 37."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    n = 70
+    rng = np.random.default_rng(77)
+    A = rng.standard_normal((n, n))
+    S = A @ A.T + n * np.eye(n)
+    S[36, :36] = S[35, :36]
+    S[:36, 36] = S[:36, 35]
+    S[36, 36] = S[35, 35]
+    S[36, 35] = S[35, 36] = S[35, 35]
+    _, info = ola.cholesky_lower(S)
+    assert info == 37
+    dH = colmajor(np.eye(n))
+    dS = colmajor(S)
+    dK = torch.zeros((n, n), dtype=torch.float64, device="cuda").T
+    dinfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.sygv_reduce_variant(variant, dH, dS, dK, dinfo)
+    torch.cuda.synchronize()
+    assert int(dinfo.item()) == n + 37
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, 5, 33, 64, 100, 257])
 def test_reduction_variants_match_oracle(ks, variant, n):
     """K = L^-1 H L^-H by the explicit inverse, by two triangular solves and
     by the blocked two-sided reduction, each against the oracle's two
