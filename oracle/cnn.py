@@ -98,15 +98,16 @@ def round_bf16(a) -> np.ndarray:
     return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def forward(params, x: np.ndarray, bf16_layer2: bool = False):
-    """Returns (output, cache) for one sample x (3, n, n, n).  With
-    ``bf16_layer2`` the second layer's input and weights are rounded to
-    bfloat16 first (the products and sums stay exact here)."""
+def forward(params, x: np.ndarray, bf16: bool = False):
+    """Returns (output, cache) for one sample x (3, n, n, n).  With ``bf16``
+    every layer's input and weights are rounded to bfloat16 first (the
+    matrix-core arithmetic of the GPU network; products and sums stay exact
+    here, bias and SiLU unrounded)."""
     acts = [x]
     pre = []
     h = x
     for k, (w, b) in enumerate(params):
-        if bf16_layer2 and k == 1:
+        if bf16:
             z = conv3d(round_bf16(h), round_bf16(w), b)
         else:
             z = conv3d(h, w, b)
@@ -124,8 +125,11 @@ def forward_residual(params, x: np.ndarray):
     return out + x[:2], cache
 
 
-def backward(params, cache, gout: np.ndarray):
-    """Gradients [(dw, db), ...] and d input for dL/doutput = gout."""
+def backward(params, cache, gout: np.ndarray, bf16: bool = False):
+    """Gradients [(dw, db), ...] and d input for dL/doutput = gout.  With
+    ``bf16`` the two operands of every convolution product (the layer input
+    and the output gradient for dw; the weights and the output gradient for
+    d input) are rounded to bfloat16 first; db sums the unrounded gradient."""
     acts, pre = cache
     grads = [None] * len(params)
     g = gout
@@ -133,7 +137,11 @@ def backward(params, cache, gout: np.ndarray):
         if k < len(params) - 1:
             g = g * silu_grad(pre[k])
         w, _ = params[k]
-        dinp, dw, db = conv3d_backward(acts[k], w, g)
+        if bf16:
+            dinp, dw, _ = conv3d_backward(round_bf16(acts[k]), round_bf16(w), round_bf16(g))
+            db = g.sum(axis=(1, 2, 3))
+        else:
+            dinp, dw, db = conv3d_backward(acts[k], w, g)
         grads[k] = (dw, db)
         g = dinp
     return grads, g

@@ -55,14 +55,25 @@ def test_cnn_forward_matches_oracle(ks, n, nbatch):
     params = rand_params(2)
     rng = np.random.default_rng(n)
     x = rng.standard_normal((nbatch, 3, n, n, n))
-    ref = np.stack([ocnn.forward(params, x[s])[0] for s in range(nbatch)])
+    ref = np.stack([ocnn.forward(params, x[s], bf16=True)[0] for s in range(nbatch)])
+    plain = np.stack([ocnn.forward(params, x[s])[0] for s in range(nbatch)])
     plan = plan_for(n)
     net = b.Cnn(plan, dev(flat_params(params)), nbatch)
-    y = net.forward(dev(x.reshape(nbatch, 3, -1), torch.float32))
+    xd = dev(x.reshape(nbatch, 3, -1), torch.float32)
+    y = net.forward(xd).clone()
     got = y.cpu().numpy().reshape(ref.shape)
-    err = np.abs(got - ref).max() / np.abs(ref).max()
-    _say("  rel err", err)
-    assert err <= 2e-5
+    # both sides round the same operands to bfloat16; a layer input computed
+    # in FP32 (GPU) and FP64 (oracle) within FP32 error of a rounding
+    # midpoint can round to neighbouring bfloat16 values (one ulp, 2^-8
+    # relative), which moves nearby outputs by about 1e-4 of their scale
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    _say("  max err", err.max() / scale, "median", np.median(err) / scale,
+         "bf16 vs fp64 network", np.abs(plain - ref).max() / scale)
+    assert err.max() <= 2e-3 * scale
+    assert np.median(err) <= 2e-5 * scale
+    # inference inside the iteration runs the same kernels: identical output
+    assert torch.equal(net.infer(xd), y)
 
 
 @pytest.mark.parametrize("n,nbatch,silu", [(10, 2, True), (16, 2, False), (48, 1, True)])
@@ -102,9 +113,9 @@ def test_conv16_bf16_matches_oracle(ks, n, nbatch, silu):
     assert np.all(err <= bound)
 
 
-def test_cnn_infer_matches_oracle_with_bf16_second_layer(ks):
-    """The network as lobpcg_step applies it against the oracle with the
-    second layer's input and weights rounded to bfloat16.  The two sides
+def test_cnn_infer_matches_oracle_bf16(ks):
+    """The network as lobpcg_step applies it against the oracle with every
+    layer's input and weights rounded to bfloat16.  The two sides
     round that input from activations computed in FP32 (GPU) and FP64
     (oracle): an activation within the FP32 error of a rounding midpoint can
     round to neighbouring bfloat16 values (one bfloat16 ulp, 2^-8 relative),
@@ -118,7 +129,7 @@ def test_cnn_infer_matches_oracle_with_bf16_second_layer(ks):
     params = rand_params(4)
     rng = np.random.default_rng(5)
     x = rng.standard_normal((nbatch, 3, n, n, n))
-    ref = np.stack([ocnn.forward(params, x[s_], bf16_layer2=True)[0] for s_ in range(nbatch)])
+    ref = np.stack([ocnn.forward(params, x[s_], bf16=True)[0] for s_ in range(nbatch)])
     plain = np.stack([ocnn.forward(params, x[s_])[0] for s_ in range(nbatch)])
     plan = plan_for(n)
     net = b.Cnn(plan, dev(flat_params(params)), nbatch)
@@ -145,10 +156,10 @@ def test_cnn_backward_matches_oracle(ks, n, nbatch):
     gref = [np.zeros_like(w) for w, _ in params] + [np.zeros_like(bb) for _, bb in params]
     loss_ref = []
     for s in range(nbatch):
-        y, cache = ocnn.forward(params, x[s])
+        y, cache = ocnn.forward(params, x[s], bf16=True)
         loss, gy = ocnn.normalised_loss(y, t[s])
         loss_ref.append(loss)
-        grads, _ = ocnn.backward(params, cache, gy / nbatch)
+        grads, _ = ocnn.backward(params, cache, gy / nbatch, bf16=True)
         for k, (dw, db) in enumerate(grads):
             gref[k] += dw
             gref[3 + k] += db
@@ -159,16 +170,20 @@ def test_cnn_backward_matches_oracle(ks, n, nbatch):
     net.forward(xd)
     loss = net.loss_grad(dev(t.reshape(nbatch, 2, -1), torch.float32))
     g = net.backward(xd).cpu().numpy()
-    assert np.abs(loss.cpu().numpy() - np.array(loss_ref)).max() <= 1e-5
+    assert np.abs(loss.cpu().numpy() - np.array(loss_ref)).max() <= 1e-4
+    # sums of thousands of bfloat16 products: FP32 accumulation error plus
+    # the rare operand that rounds to the neighbouring bfloat16 value on the
+    # two sides (see the forward test)
     err = np.abs(g - ref).max() / np.abs(ref).max()
     _say("  grad rel err", err)
-    assert err <= 1e-4
-    # per-block check: each parameter group within 1e-3 of its own scale
+    assert err <= 5e-4
     off = 0
     for k in range(3):
         for arr in (gref[k], gref[3 + k]):
             seg = g[off:off + arr.size]
-            assert np.abs(seg - arr.ravel()).max() <= 1e-3 * max(np.abs(arr).max(), 1e-12)
+            e = np.abs(seg - arr.ravel()).max() / max(np.abs(arr).max(), 1e-12)
+            _say("  block", k, arr.shape, "rel err", e)
+            assert e <= 5e-3
             off += arr.size
 
 
@@ -293,36 +308,58 @@ def test_jd_correction_matches_oracle(ks):
     assert np.abs(np.conj(st.X) @ got.T).max() <= 1e-10 * np.abs(got).max()
 
 
-def test_trained_network_first_step_beats_tpa_and_no_preconditioner(ks):
-    """What the trained network (weights/cnn_precond.npy, trained on the GPU
-    by learned.py on 8- and 64-atom cells) gains: from the same initial
-    block of the 64-atom cell, one LOBPCG step preconditioned by it lowers
-    the largest tracked residual norm more than a TPA step and more than an
-    unpreconditioned step (measured 5.8 vs 19.8 vs larger)."""
+def _c2_golden():
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_eigenvalues.txt")
+    return np.loadtxt(path, comments="#")
+
+
+def test_learned_preconditioner_iterations_to_1e6_against_tpa(ks):
+    """What the trained networks (weights/, trained on the GPU by learned.py
+    on 8- and 64-atom cells, every convolution on the bfloat16 matrix cores)
+    are worth by the measure that counts: LOBPCG iterations from the same
+    initial block of the 64-atom cell (FP64) until every tracked eigenvalue
+    is within 1e-6 Ha of the oracle's, against TPA, with the switch to TPA
+    turned off.  The network on the TPA output with the skip connection
+    (KS_PRECOND_CNN_TPA) converges, more slowly than TPA; the network on the
+    plain residual (KS_PRECOND_CNN) gives the largest first-step drop but
+    stalls.  The bounds below are the measured results (a negative result
+    for the learned preconditioner), asserted so that a regression in the
+    kernels or the weights shows."""
     import os
 
     import torch
 
     from paper_2512_04447_amd import binding as b
     from paper_2512_04447_amd import learned as lr
+    from paper_2512_04447_amd import solve
 
-    assert os.path.exists(lr.WEIGHTS), "trained weights missing"
-    params = torch.from_numpy(np.load(lr.WEIGHTS)).cuda()
+    for w in (lr.WEIGHTS, lr.WEIGHTS_TPA):
+        assert os.path.exists(w), "trained weights missing"
     cfg = ki.config("C2")
     cell = ki.make_cell(cfg)
     plan = b.Plan(cell.n, cell.L, b.ProjectorArrays.from_cell(cell), cfg.nb, b.KS_FP64)
     v = dev(cell.V)
     x0 = dev(ki.make_x0(cfg))
+    gold = _c2_golden()[: cfg.ntrack]
     out = {}
-    for name, kind in (("none", b.KS_PRECOND_NONE), ("tpa", b.KS_PRECOND_TPA), ("cnn", b.KS_PRECOND_CNN)):
-        lob = b.Lobpcg(plan, v, x0)
-        lob.init()
-        lob.step(kind, 0.0, params if kind == b.KS_PRECOND_CNN else None)
-        # the residual of the new block is formed at the start of the next step
-        lob.step(b.KS_PRECOND_NONE, 0.0)
-        out[name] = float(lob.res[: cfg.ntrack].max())
-        del lob
+    for name, kind, wpath, maxit in (("tpa", b.KS_PRECOND_TPA, None, 40),
+                                     ("cnn_tpa", b.KS_PRECOND_CNN_TPA, lr.WEIGHTS_TPA, 60),
+                                     ("cnn", b.KS_PRECOND_CNN, lr.WEIGHTS, 30)):
+        params = None if wpath is None else torch.from_numpy(np.load(wpath)).cuda()
+        r = solve.run_to_tolerance(plan, v, x0, cfg.ntrack, kind, 1e-7, maxit, ref=gold, cnn_params=params,
+                                   switch_to_tpa=False, log=lambda *a: None)
+        first = r["history"][1][1] if len(r["history"]) > 1 else float("nan")
+        out[name] = (r["reached"], r["iterations"], r["seconds"], first, r["max_res"])
+        _say(name, "reached", r["reached"], "iterations", r["iterations"], "seconds", round(r["seconds"], 3),
+             "first-step max res", first, "final max res", r["max_res"])
+        del r
         torch.cuda.empty_cache()
-    _say("max tracked residual after one preconditioned step:", out)
-    assert out["cnn"] < 0.75 * out["tpa"]
-    assert out["cnn"] < out["none"]
+    assert out["tpa"][0] and out["tpa"][1] <= 20
+    assert out["cnn_tpa"][0]
+    assert out["cnn_tpa"][1] <= 3 * out["tpa"][1]
+    # every run stays finite
+    assert all(np.isfinite(o[4]) for o in out.values())
+
+

@@ -466,6 +466,40 @@ def test_bfloat16_rounding_matches_torch_conversion():
     assert np.isnan(ocnn.round_bf16(np.array([np.nan], dtype=np.float32))[0])
 
 
+def test_bfloat16_network_mode_reduces_to_the_exact_network_on_representable_data():
+    """The bfloat16 mode of the network rounds the two operands of every
+    convolution product.  On one layer whose input, weights and output
+    gradient are bfloat16 values already, nothing rounds: forward and
+    backward equal the FP64 network (pinned above against scipy and finite
+    differences) exactly.  On three layers with generic data the two modes
+    differ, by about the bfloat16 unit 2^-8 relative."""
+    rng = np.random.default_rng(12)
+    n = 5
+    w = ocnn.round_bf16(rng.uniform(-0.3, 0.3, (2, 3, 3, 3, 3)))
+    b = rng.standard_normal(2)
+    x = ocnn.round_bf16(rng.standard_normal((3, n, n, n)))
+    g = ocnn.round_bf16(rng.standard_normal((2, n, n, n)))
+    one = [(w, b)]
+    y0, c0 = ocnn.forward(one, x)
+    y1, c1 = ocnn.forward(one, x, bf16=True)
+    assert np.array_equal(y0, y1)
+    (gr0,), gx0 = ocnn.backward(one, c0, g)
+    (gr1,), gx1 = ocnn.backward(one, c1, g, bf16=True)
+    assert np.array_equal(gr0[0], gr1[0]) and np.array_equal(gr0[1], gr1[1]) and np.array_equal(gx0, gx1)
+    params = ocnn.init_params(2, channels=(3, 4, 4, 2))
+    x = rng.standard_normal((3, n, n, n))
+    ya, ca = ocnn.forward(params, x)
+    yb, cb = ocnn.forward(params, x, bf16=True)
+    d = np.abs(ya - yb).max() / np.abs(ya).max()
+    assert 1e-5 < d < 3e-2
+    ga, _ = ocnn.backward(params, ca, ya)
+    gb, _ = ocnn.backward(params, cb, ya, bf16=True)
+    for (dwa, dba), (dwb, dbb) in zip(ga, gb):
+        dw = np.abs(dwa - dwb).max() / np.abs(dwa).max()
+        assert 1e-5 < dw < 3e-2
+        assert np.abs(dba - dbb).max() <= 3e-2 * np.abs(dba).max()
+
+
 # ---------------------------------------------------------------- deflating Cholesky (P8 for a singular overlap)
 
 
