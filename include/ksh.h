@@ -187,6 +187,24 @@ typedef struct ks_lobpcg_opts {
  * memory; synchronises `stream` once at the end. */
 int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj,
                    int32_t nb_max, int32_t precision, void* stream);
+
+/* A plan for the periodic part u of Bloch orbitals psi = exp(i k.r) u at a
+ * Bloch vector k (the k-point variant of the same iteration; k = 0 gives
+ * the plan of ks_plan_create).  Every entry point then applies
+ * H_k = exp(-i k.r) H exp(i k.r): kinetic energy |G + k|^2 / 2 in the
+ * FFT passes (the TPA preconditioner and the kinetic energies use it too;
+ * the Hartree solve of ks_hartree does not), the local potential unchanged,
+ * and the projectors seen by u at support point s of an atom
+ * b_j(s) exp(-i k.d_s), d_s the displacement of the point from the atom
+ * (the image nearest the atom), so that
+ *   V_NL u = sum_j b_j exp(-i k.d) D_j <b_j exp(-i k.d) | u>.
+ * kvec: host, 3 doubles, Cartesian (1/bohr).  supp_disp: host, 3 * n_supp
+ * doubles (x, y, z of d_s in bohr, in the order of supp_idx), read once;
+ * required when k != 0 and the set has projectors.  Internally each
+ * projector becomes the real pair b cos(k.d), b sin(k.d), so an atom may
+ * carry at most 4 projectors (s and p; KS_E_UNSUPPORTED otherwise). */
+int ks_plan_create_k(ks_plan** out, const ks_grid* grid, const double* kvec, const ks_projset* proj,
+                     const double* supp_disp, int32_t nb_max, int32_t precision, void* stream);
 int ks_plan_destroy(ks_plan* plan);
 
 /* Bytes of caller workspace that `op` needs for blocks of nb columns. */

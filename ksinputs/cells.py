@@ -162,6 +162,9 @@ class Cell:
     proj_atom: np.ndarray  # (nproj,) int32
     proj_l: np.ndarray  # (nproj,) int32
     beta_ptr: np.ndarray  # (natoms+1,) int64 offsets of each atom's beta slab
+    # (nsupp, 3) float64: displacement of each support point from its atom
+    # (the image of the point nearest the atom), in bohr
+    supp_disp: np.ndarray = None
 
     @property
     def Ng(self) -> int:
@@ -227,11 +230,12 @@ def _projectors(cfg: CellConfig, pos: np.ndarray, rng: np.random.Generator):
     if cfg.lmax < 0:
         z32 = np.zeros(natoms + 1, dtype=np.int32)
         return (z32, np.zeros(0, np.int32), z32.copy(), np.zeros(0), np.zeros(0),
-                np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(natoms + 1, np.int64))
+                np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(natoms + 1, np.int64), np.zeros((0, 3)))
     if 2.0 * rcut >= L:
         raise ValueError("projector support must be smaller than half the cell")
     supp_ptr = [0]
     supp_all = []
+    disp_all = []
     beta_all = []
     beta_ptr = [0]
     proj_ptr = [0]
@@ -259,6 +263,7 @@ def _projectors(cfg: CellConfig, pos: np.ndarray, rng: np.random.Generator):
         x, y, z = DX[mask][order], DY[mask][order], DZ[mask][order]
         g = np.exp(-(x * x + y * y + z * z) * inv2rc2)
         supp_all.append(lin.astype(np.int32))
+        disp_all.append(np.stack([x, y, z], axis=1))
         supp_ptr.append(supp_ptr[-1] + len(lin))
         npa = 0
         for l in range(cfg.lmax + 1):
@@ -282,6 +287,7 @@ def _projectors(cfg: CellConfig, pos: np.ndarray, rng: np.random.Generator):
         np.array(proj_atom, dtype=np.int32),
         np.array(proj_l, dtype=np.int32),
         np.array(beta_ptr, dtype=np.int64),
+        np.concatenate(disp_all).astype(np.float64),
     )
 
 
@@ -289,8 +295,8 @@ def make_cell(cfg: CellConfig, seed: int = 0) -> Cell:
     pos = atom_positions(cfg)
     V = _gaussian_potential(cfg, pos)
     rng = np.random.default_rng(seed)
-    (sp, si, pp, beta, D, pa, pl, bp) = _projectors(cfg, pos, rng)
-    return Cell(cfg, cfg.L, cfg.n, cfg.h, pos, V, sp, si, pp, beta, D, pa, pl, bp)
+    (sp, si, pp, beta, D, pa, pl, bp, disp) = _projectors(cfg, pos, rng)
+    return Cell(cfg, cfg.L, cfg.n, cfg.h, pos, V, sp, si, pp, beta, D, pa, pl, bp, disp)
 
 
 def make_x0(cfg: CellConfig, seed: int = 1, nb: Optional[int] = None) -> np.ndarray:

@@ -64,12 +64,22 @@ def kinetic_diag(n: int, L: float) -> np.ndarray:
     return 0.5 * g2
 
 
-def apply_t(psi: np.ndarray, n: int, L: float) -> np.ndarray:
-    """T psi for psi of shape (nb, Ng)."""
+def kinetic_diag_k(n: int, L: float, k) -> np.ndarray:
+    """|G + k|^2 / 2 on the (n, n, n) reciprocal grid (k Cartesian, 1/bohr)."""
+    m = wrapped_m(n).astype(np.float64)
+    g = 2.0 * math.pi / L * m
+    gx, gy, gz = g + k[0], g + k[1], g + k[2]
+    return 0.5 * (gx[:, None, None] ** 2 + gy[None, :, None] ** 2 + gz[None, None, :] ** 2)
+
+
+def apply_t(psi: np.ndarray, n: int, L: float, k=None) -> np.ndarray:
+    """T psi for psi of shape (nb, Ng); with a Bloch vector k, the kinetic
+    operator of the periodic part u of psi = exp(i k.r) u, |G + k|^2 / 2."""
     nb = psi.shape[0]
     p = psi.reshape(nb, n, n, n)
     ph = dft3(p, n)
-    ph = ph * kinetic_diag(n, L)[None]
+    t = kinetic_diag(n, L) if k is None else kinetic_diag_k(n, L, k)
+    ph = ph * t[None]
     return dft3(ph, n, inverse=True).reshape(nb, n ** 3)
 
 
@@ -87,6 +97,11 @@ class OracleCell:
     proj_supp: list  # per projector: int array of grid indices
     proj_val: list  # per projector: float array of b values
     D: np.ndarray  # (nproj,)
+    # Bloch vector (Cartesian, 1/bohr) and, per projector, the displacement
+    # of each support point from the atom (nearest image, bohr); both None
+    # at the Gamma point
+    k: np.ndarray = None
+    proj_disp: list = None
 
     @property
     def Ng(self) -> int:
@@ -145,14 +160,15 @@ def _real_solid_harmonics(l: int, x, y, z):
     return [x * y, y * z, z * x, (x * x - y * y) / 2.0, (3.0 * z * z - r2) / (2.0 * math.sqrt(3.0))]
 
 
-def oracle_projectors(cfg, pos: np.ndarray):
-    """Per projector: (support indices ascending, normalised values)."""
+def oracle_projectors(cfg, pos: np.ndarray, with_disp: bool = False):
+    """Per projector: (support indices ascending, normalised values), and
+    with ``with_disp`` the support points' displacements from the atom."""
     if cfg.lmax < 0:
-        return [], []
+        return ([], [], []) if with_disp else ([], [])
     n, L = cfg.n, cfg.L
     rcut = cfg.rcut_factor * cfg.rc
     r = grid_points(n, L)
-    supp, vals = [], []
+    supp, vals, disp = [], [], []
     for R in pos:
         d = r - R
         d = d - L * np.floor(d / L + 0.5)  # minimum image
@@ -166,7 +182,8 @@ def oracle_projectors(cfg, pos: np.ndarray):
                 b = b / math.sqrt(float(np.sum(b * b)))
                 supp.append(idx)
                 vals.append(b)
-    return supp, vals
+                disp.append(d[idx])
+    return (supp, vals, disp) if with_disp else (supp, vals)
 
 
 def oracle_cell(cfg, D: np.ndarray) -> OracleCell:
@@ -179,8 +196,9 @@ def oracle_cell(cfg, D: np.ndarray) -> OracleCell:
     return OracleCell(cfg.n, cfg.L, V, supp, vals, np.asarray(D, dtype=np.float64))
 
 
-def from_arrays(n: int, L: float, V: np.ndarray, supp: list, vals: list, D) -> OracleCell:
-    return OracleCell(n, L, np.asarray(V, np.float64), list(supp), list(vals), np.asarray(D, np.float64))
+def from_arrays(n: int, L: float, V: np.ndarray, supp: list, vals: list, D, k=None, disp=None) -> OracleCell:
+    return OracleCell(n, L, np.asarray(V, np.float64), list(supp), list(vals), np.asarray(D, np.float64),
+                      None if k is None else np.asarray(k, np.float64), None if disp is None else list(disp))
 
 
 def _atom_groups(cell: OracleCell):
@@ -200,16 +218,23 @@ def _atom_groups(cell: OracleCell):
 
 
 def apply_nl(cell: OracleCell, psi: np.ndarray) -> np.ndarray:
-    """sum over projectors p of b_p D_p (b_p^T psi).
+    """sum over projectors p of b_p D_p (b_p^H psi).
 
     Projectors of one atom share a support, so their terms are formed
-    together: c = psi_S B^T, then psi_S += (c * D) B with B the rows b_p.
-    """
+    together: c = psi_S B^H, then psi_S += (c * D) B with B the rows b_p.
+
+    With a Bloch vector k the operator acts on the periodic part u of
+    psi = exp(i k.r) u: the projector seen by u at a support point with
+    displacement d from its atom is b(d) exp(-i k.d) (the orbital at the
+    image of the point nearest the atom carries exp(i k.(R + d)), and
+    H u = exp(-i k.r) H psi; the common factor exp(i k.R) cancels)."""
     out = np.zeros_like(psi)
     for p, q in _atom_groups(cell):
         idx = cell.proj_supp[p]
-        B = np.array(cell.proj_val[p:q])  # (np_a, |S|)
-        c = psi[:, idx] @ B.T  # (nb, np_a)
+        B = np.array(cell.proj_val[p:q], dtype=np.complex128)  # (np_a, |S|)
+        if cell.k is not None:
+            B = B * np.exp(-1j * (cell.proj_disp[p] @ cell.k))[None, :]
+        c = psi[:, idx] @ np.conj(B).T  # (nb, np_a)
         out[:, idx] += (c * cell.D[p:q]) @ B
     return out
 
@@ -222,7 +247,7 @@ def project(cell: OracleCell, psi: np.ndarray) -> np.ndarray:
 def apply_h(cell: OracleCell, psi: np.ndarray) -> np.ndarray:
     """H psi for psi of shape (nb, Ng), complex128."""
     psi = np.asarray(psi, dtype=np.complex128)
-    out = apply_t(psi, cell.n, cell.L)
+    out = apply_t(psi, cell.n, cell.L, cell.k)
     out = out + cell.V[None, :] * psi
     if cell.proj_supp:
         out = out + apply_nl(cell, psi)

@@ -186,8 +186,8 @@ def step(cell: OracleCell, st: State, precond: Optional[Callable] = None,
 
 def tpa_preconditioner(cell: OracleCell):
     def apply(R: np.ndarray, st: State) -> np.ndarray:
-        E = band_kinetic_energy(st.X, cell.n, cell.L)
-        return tpa_apply(R, E, cell.n, cell.L)
+        E = band_kinetic_energy(st.X, cell.n, cell.L, cell.k)
+        return tpa_apply(R, E, cell.n, cell.L, cell.k)
 
     return apply
 

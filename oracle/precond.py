@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .hamiltonian import apply_t, dft3, kinetic_diag
+from .hamiltonian import apply_t, dft3, kinetic_diag, kinetic_diag_k
 
 
 def tpa_polynomial(x: np.ndarray) -> np.ndarray:
@@ -24,17 +24,19 @@ def tpa_polynomial(x: np.ndarray) -> np.ndarray:
     return num / (num + 16.0 * x ** 4)
 
 
-def band_kinetic_energy(X: np.ndarray, n: int, L: float) -> np.ndarray:
-    """E_i = <x_i | T | x_i> for the rows x_i of X (nb, Ng)."""
-    TX = apply_t(X, n, L)
+def band_kinetic_energy(X: np.ndarray, n: int, L: float, k=None) -> np.ndarray:
+    """E_i = <x_i | T | x_i> for the rows x_i of X (nb, Ng); T = T_k with a
+    Bloch vector k."""
+    TX = apply_t(X, n, L, k)
     return np.real(np.einsum("ij,ij->i", np.conj(X), TX))
 
 
-def tpa_apply(R: np.ndarray, E: np.ndarray, n: int, L: float) -> np.ndarray:
-    """w_i = IDFT( K(T(G)/E_i) * DFT(r_i) ) for the rows r_i of R (nb, Ng)."""
+def tpa_apply(R: np.ndarray, E: np.ndarray, n: int, L: float, k=None) -> np.ndarray:
+    """w_i = IDFT( K(T(G)/E_i) * DFT(r_i) ) for the rows r_i of R (nb, Ng),
+    T(G) = |G + k|^2 / 2 with a Bloch vector k."""
     nb = R.shape[0]
     rh = dft3(R.reshape(nb, n, n, n), n)
-    T = kinetic_diag(n, L)
+    T = kinetic_diag(n, L) if k is None else kinetic_diag_k(n, L, k)
     x = T[None] / E[:, None, None, None]
     wh = rh * tpa_polynomial(x)
     return dft3(wh, n, inverse=True).reshape(nb, n ** 3)

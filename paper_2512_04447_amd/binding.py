@@ -30,6 +30,7 @@ KS_E_HIP, KS_E_WORKSPACE, KS_E_NUMERIC, KS_E_UNSUPPORTED = -1000, -2001, -2002, 
 
 EXPORTS = (
     "ks_plan_create",
+    "ks_plan_create_k",
     "ks_plan_destroy",
     "ks_workspace_size",
     "ks_apply_h",
@@ -148,6 +149,8 @@ def load() -> C.CDLL:
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.ks_plan_create.argtypes = [C.POINTER(vp), C.POINTER(KsGrid), C.POINTER(KsProjset), i32, i32, vp]
+    lib.ks_plan_create_k.argtypes = [C.POINTER(vp), C.POINTER(KsGrid), C.POINTER(C.c_double), C.POINTER(KsProjset),
+                                     C.POINTER(C.c_double), i32, i32, vp]
     lib.ks_plan_destroy.argtypes = [vp]
     lib.ks_workspace_size.argtypes = [vp, i32, i32, C.POINTER(sz)]
     lib.ks_apply_h.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, sz, vp]
@@ -223,9 +226,13 @@ class ProjectorArrays:
     beta_ptr: np.ndarray
     beta: np.ndarray
     D: np.ndarray
+    # (n_supp, 3) displacements of the support points from their atoms
+    # (plans with a Bloch vector only)
+    supp_disp: np.ndarray = None
 
     @classmethod
     def from_cell(cls, cell):
+        disp = getattr(cell, "supp_disp", None)
         return cls(
             np.ascontiguousarray(cell.atom_supp_ptr, np.int32),
             np.ascontiguousarray(cell.supp_idx, np.int32),
@@ -233,6 +240,7 @@ class ProjectorArrays:
             np.ascontiguousarray(cell.beta_ptr, np.int64),
             np.ascontiguousarray(cell.beta, np.float64),
             np.ascontiguousarray(cell.D, np.float64),
+            None if disp is None else np.ascontiguousarray(disp, np.float64),
         )
 
     def struct(self) -> KsProjset:
@@ -250,9 +258,12 @@ class ProjectorArrays:
 
 
 class Plan:
-    """Owns a ks_plan*."""
+    """Owns a ks_plan*.  With ``k`` (3 floats, 1/bohr) the plan acts on the
+    periodic part of Bloch orbitals at that vector (ks_plan_create_k; the
+    projector set then needs its support displacements)."""
 
-    def __init__(self, n, L, proj: ProjectorArrays | None, nb_max: int, precision: int = KS_FP64, stream=None):
+    def __init__(self, n, L, proj: ProjectorArrays | None, nb_max: int, precision: int = KS_FP64, stream=None,
+                 k=None):
         lib = load()
         g = KsGrid()
         for a in range(3):
@@ -265,9 +276,18 @@ class Plan:
         self._proj = proj
         ps = proj.struct() if proj is not None and len(proj.D) > 0 else None
         h = C.c_void_p()
-        rc = lib.ks_plan_create(C.byref(h), C.byref(g), C.byref(ps) if ps is not None else None, self.nb_max,
-                                self.precision, C.c_void_p(_stream(stream)))
-        check(rc, "ks_plan_create")
+        self.k = None if k is None else np.ascontiguousarray(k, np.float64).reshape(3)
+        if self.k is None:
+            rc = lib.ks_plan_create(C.byref(h), C.byref(g), C.byref(ps) if ps is not None else None, self.nb_max,
+                                    self.precision, C.c_void_p(_stream(stream)))
+            check(rc, "ks_plan_create")
+        else:
+            disp = None if proj is None or proj.supp_disp is None else proj.supp_disp
+            dp = None if disp is None else disp.ctypes.data_as(C.POINTER(C.c_double))
+            rc = lib.ks_plan_create_k(C.byref(h), C.byref(g), self.k.ctypes.data_as(C.POINTER(C.c_double)),
+                                      C.byref(ps) if ps is not None else None, dp, self.nb_max, self.precision,
+                                      C.c_void_p(_stream(stream)))
+            check(rc, "ks_plan_create_k")
         self.handle = h
         _live_plans.add(self)
 

@@ -820,6 +820,63 @@ static const char* check_projset(const ks_projset& ps, int64_t Ng) {
   return nullptr;
 }
 
+// A projector set with Bloch phases folded in: projector j of atom a
+// becomes the real pair 2j (values b cos(k.d_s)) and 2j + 1 (b sin(k.d_s)),
+// d_s the displacement of support point s from the atom; both keep D_j.
+struct BlochProjset {
+  std::vector<int32_t> pp;
+  std::vector<int64_t> bp;
+  std::vector<double> beta, D;
+  ks_projset ps;
+};
+
+static void bloch_projset(const ks_projset& in, const double* disp, const double* k, BlochProjset& o) {
+  const int na = in.n_atoms;
+  o.pp.assign(na + 1, 0);
+  o.bp.assign(na + 1, 0);
+  for (int a = 0; a < na; ++a) {
+    const int np = in.atom_proj_ptr[a + 1] - in.atom_proj_ptr[a];
+    const int64_t ns = in.atom_supp_ptr[a + 1] - in.atom_supp_ptr[a];
+    o.pp[a + 1] = o.pp[a] + 2 * np;
+    o.bp[a + 1] = o.bp[a] + 2 * np * ns;
+  }
+  o.beta.assign((size_t)o.bp[na], 0.0);
+  o.D.assign((size_t)2 * in.n_proj, 0.0);
+  std::vector<double> c, sn;
+  for (int a = 0; a < na; ++a) {
+    const int np = in.atom_proj_ptr[a + 1] - in.atom_proj_ptr[a];
+    const int64_t s0 = in.atom_supp_ptr[a], ns = in.atom_supp_ptr[a + 1] - s0;
+    c.resize(ns);
+    sn.resize(ns);
+    for (int64_t s = 0; s < ns; ++s) {
+      const double* d = disp + 3 * (s0 + s);
+      const double kd = k[0] * d[0] + k[1] * d[1] + k[2] * d[2];
+      c[s] = cos(kd);
+      sn[s] = sin(kd);
+    }
+    for (int j = 0; j < np; ++j) {
+      const double* src = in.beta + in.beta_ptr[a] + (int64_t)j * ns;
+      double* dc = o.beta.data() + o.bp[a] + (int64_t)(2 * j) * ns;
+      double* ds = dc + ns;
+      for (int64_t s = 0; s < ns; ++s) {
+        dc[s] = src[s] * c[s];
+        ds[s] = src[s] * sn[s];
+      }
+      const int P = in.atom_proj_ptr[a] + j;
+      o.D[2 * P] = o.D[2 * P + 1] = in.D[P];
+    }
+  }
+  o.ps = in;
+  o.ps.n_proj = 2 * in.n_proj;
+  o.ps.atom_proj_ptr = o.pp.data();
+  o.ps.beta_ptr = o.bp.data();
+  o.ps.beta = o.beta.data();
+  o.ps.D = o.D.data();
+}
+
+static int plan_create(ks_plan** out, const ks_grid* grid, const double* kvec, const ks_projset* proj,
+                       const double* supp_disp, int32_t nb_max, int32_t precision, void* stream);
+
 }  // namespace ks
 
 using namespace ks;
@@ -862,6 +919,26 @@ int ks_kernel_timer_read(int32_t family, double* total_ms, int64_t* launches) {
 int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, int32_t nb_max, int32_t precision,
                    void* stream) {
   g_last_error.clear();
+  return plan_create(out, grid, nullptr, proj, nullptr, nb_max, precision, stream);
+}
+
+int ks_plan_create_k(ks_plan** out, const ks_grid* grid, const double* kvec, const ks_projset* proj,
+                     const double* supp_disp, int32_t nb_max, int32_t precision, void* stream) {
+  g_last_error.clear();
+  if (!kvec) return fail(-3, "kvec is null");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(kvec[a])) return fail(-3, "kvec must be finite");
+  const bool nonzero = kvec[0] != 0.0 || kvec[1] != 0.0 || kvec[2] != 0.0;
+  if (nonzero && proj && proj->n_proj > 0 && !supp_disp) return fail(-5, "supp_disp is null");
+  return plan_create(out, grid, nonzero ? kvec : nullptr, proj, supp_disp, nb_max, precision, stream);
+}
+
+}  // extern "C"
+
+namespace ks {
+
+static int plan_create(ks_plan** out, const ks_grid* grid, const double* kvec, const ks_projset* proj,
+                       const double* supp_disp, int32_t nb_max, int32_t precision, void* stream) {
   if (!out) return fail(-1, "out is null");
   if (!grid) return fail(-2, "grid is null");
   if (nb_max <= 0) return fail(-4, "nb_max must be positive");
@@ -879,6 +956,7 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
       return fail(-2, "grid sizes must be positive products of 2, 3, 5, 7 and L positive");
     }
     p->fft.twopi_over_L[a] = 2.0 * M_PI / grid->L[a];
+    p->fft.kvec[a] = kvec ? kvec[a] : 0.0;
     p->Ng *= grid->n[a];
   }
   // the projector set is checked before any device work
@@ -892,6 +970,12 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
       delete p;
       return fail(-3, why);
     }
+    if (kvec)
+      for (int a = 0; a < proj->n_atoms; ++a)
+        if (2 * (proj->atom_proj_ptr[a + 1] - proj->atom_proj_ptr[a]) > 9) {
+          delete p;
+          return fail(KS_E_UNSUPPORTED, "a plan with a Bloch vector takes at most 4 projectors per atom (s and p)");
+        }
   }
   const size_t es = precision == KS_FP64 ? 16 : 8;
   const int n0 = grid->n[0], n1 = grid->n[1], n2 = grid->n[2];
@@ -924,7 +1008,14 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   for (int a = 0; a < 3 && rc == 0; ++a)
     rc = precision == KS_FP64 ? upload_twiddles<double>(grid->n[a], &p->tw[a]) : upload_twiddles<float>(grid->n[a], &p->tw[a]);
   if (rc == 0 && proj && proj->n_proj > 0) {
-    rc = precision == KS_FP64 ? upload_proj<double>(p, proj) : upload_proj<float>(p, proj);
+    const ks_projset* use = proj;
+    BlochProjset bl;
+    if (kvec) {
+      bloch_projset(*proj, supp_disp, kvec, bl);
+      use = &bl.ps;
+      p->kpairs = 1;
+    }
+    rc = precision == KS_FP64 ? upload_proj<double>(p, use) : upload_proj<float>(p, use);
   }
   if (rc) {
     ks_plan_destroy(p);
@@ -934,6 +1025,10 @@ int ks_plan_create(ks_plan** out, const ks_grid* grid, const ks_projset* proj, i
   *out = p;
   return 0;
 }
+
+}  // namespace ks
+
+extern "C" {
 
 int ks_plan_destroy(ks_plan* p) {
   if (!p) return 0;

@@ -403,15 +403,16 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
 }
 
 // ---------------------------------------------------------------- pass B
-// MODE 0: multiply by T(G) = |G|^2/2.  MODE 1: multiply by the TPA factor
-// K(T(G)/E_band).  MODE 2: no inverse; partial[block] = sum T(G)|f(G)|^2.
-// MODE 3: multiply by the periodic Poisson kernel 4 pi / |G|^2 = 2 pi / T(G)
+// MODE 0: multiply by T(G) = |G + k|^2/2 (k the plan's Bloch vector, zero
+// at the Gamma point).  MODE 1: multiply by the TPA factor K(T(G)/E_band).
+// MODE 2: no inverse; partial[block] = sum T(G)|f(G)|^2.  MODE 3: multiply
+// by the periodic Poisson kernel 4 pi / |G|^2 = 2 pi / T0(G), T0 without k
 // (0 at G = 0).
-template <typename T>
+template <typename T, bool WITHK = true>
 __device__ inline T kinetic_of(const Fft3& f, int kx, int ky, int kz) {
-  const T gx = T(f.twopi_over_L[0]) * T(wrap_m(kx, f.ax[0].n));
-  const T gy = T(f.twopi_over_L[1]) * T(wrap_m(ky, f.ax[1].n));
-  const T gz = T(f.twopi_over_L[2]) * T(wrap_m(kz, f.ax[2].n));
+  const T gx = T(f.twopi_over_L[0]) * T(wrap_m(kx, f.ax[0].n)) + (WITHK ? T(f.kvec[0]) : T(0));
+  const T gy = T(f.twopi_over_L[1]) * T(wrap_m(ky, f.ax[1].n)) + (WITHK ? T(f.kvec[1]) : T(0));
+  const T gz = T(f.twopi_over_L[2]) * T(wrap_m(kz, f.ax[2].n)) + (WITHK ? T(f.kvec[2]) : T(0));
   return T(0.5) * (gx * gx + gy * gy + gz * gz);
 }
 
@@ -474,7 +475,7 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   const T einv = (MODE == 1) ? T(1.0 / E[band]) : T(0);
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int kx = i / zc, z = i - kx * zc;
-    const T t = kinetic_of<T>(f, kx, y, z0 + z);
+    const T t = kinetic_of<T, MODE != 3>(f, kx, y, z0 + z);
     const T fac = (MODE == 0)   ? t
                   : (MODE == 3) ? (t > T(0) ? T(2.0 * 3.14159265358979323846) / t : T(0))
                                 : tpa_factor<T>(t * einv);
@@ -740,18 +741,16 @@ k_nl_project_tile(const c2<T>* __restrict__ psi, int64_t ld, int nb, int n1, int
   }
 }
 
-// dc[p][b] = D_p * sum over the tiles of projector p (ascending) of its
-// partial rows part[row][b].
+// Sum over the tiles of projector p (ascending) of its partial rows
+// part[row][b], in FP64.
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_nl_reduce(const c2<T>* __restrict__ part, int nb, int nproj, const int32_t* __restrict__ proj_pair_ptr,
-            const int32_t* __restrict__ proj_pairs, const T* __restrict__ D, c2<T>* __restrict__ dc) {
+__device__ inline void nl_row_sum(const c2<T>* __restrict__ part, int nb, int p, int b,
+                                  const int32_t* __restrict__ proj_pair_ptr, const int32_t* __restrict__ proj_pairs,
+                                  double& re, double& im) {
   using T2 = c2<T>;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nproj * nb) return;
-  const int p = (int)(i / nb), b = (int)(i - (int64_t)p * nb);
   const int j0 = proj_pair_ptr[p], j1 = proj_pair_ptr[p + 1];
-  double re = 0.0, im = 0.0;
+  re = 0.0;
+  im = 0.0;
   for (int j = j0; j < j1; j += 4) {
     T2 v[4];
 #pragma unroll
@@ -763,8 +762,36 @@ k_nl_reduce(const c2<T>* __restrict__ part, int nb, int nproj, const int32_t* __
         im += (double)v[u].y;
       }
   }
-  const double d = (double)D[p];
-  dc[(int64_t)p * nb + b] = cmake<T2>(T(d * re), T(d * im));
+}
+
+// dc[p][b] = D_p * (row sum of projector p).  With kpairs, thread (q, b)
+// takes the pair (2q, 2q + 1) of real projectors b cos(k.d), b sin(k.d):
+// the coefficient of the complex projector b exp(-i k.d) is
+// c = s_cos + i s_sin, and its scatter b exp(-i k.d) D c splits into
+// dc[2q] = D c on the cosine part and dc[2q + 1] = -i D c on the sine part.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_nl_reduce(const c2<T>* __restrict__ part, int nb, int nproj, const int32_t* __restrict__ proj_pair_ptr,
+            const int32_t* __restrict__ proj_pairs, const T* __restrict__ D, int kpairs, c2<T>* __restrict__ dc) {
+  using T2 = c2<T>;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int nrow = kpairs ? nproj / 2 : nproj;
+  if (i >= (int64_t)nrow * nb) return;
+  const int q = (int)(i / nb), b = (int)(i - (int64_t)q * nb);
+  if (!kpairs) {
+    double re, im;
+    nl_row_sum<T>(part, nb, q, b, proj_pair_ptr, proj_pairs, re, im);
+    const double d = (double)D[q];
+    dc[(int64_t)q * nb + b] = cmake<T2>(T(d * re), T(d * im));
+    return;
+  }
+  double cr, ci, sr, si;
+  nl_row_sum<T>(part, nb, 2 * q, b, proj_pair_ptr, proj_pairs, cr, ci);
+  nl_row_sum<T>(part, nb, 2 * q + 1, b, proj_pair_ptr, proj_pairs, sr, si);
+  const double d = (double)D[2 * q];
+  const double re = d * (cr - si), im = d * (ci + sr);
+  dc[(int64_t)(2 * q) * nb + b] = cmake<T2>(T(re), T(im));
+  dc[(int64_t)(2 * q + 1) * nb + b] = cmake<T2>(T(im), T(-re));
 }
 
 // Nonlocal scatter: hpsi[b][r] += sum over the entries of point r of
@@ -1070,9 +1097,9 @@ static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2
     KS_PROJ_LAUNCH(9);
 #undef KS_PROJ_LAUNCH
   KS_LAUNCH_CHECK("nl_project_tile");
-  const int64_t tot = (int64_t)p.nproj * nb;
+  const int64_t tot = (int64_t)(p.kpairs ? p.nproj / 2 : p.nproj) * nb;
   hipLaunchKernelGGL((k_nl_reduce<T>), dim3((unsigned)ceil_div(tot, kThreads)), dim3(kThreads), 0, s, part, nb,
-                     p.nproj, p.proj_pair_ptr, p.proj_pairs, static_cast<const T*>(p.Dcoef), dc);
+                     p.nproj, p.proj_pair_ptr, p.proj_pairs, static_cast<const T*>(p.Dcoef), p.kpairs, dc);
   KS_LAUNCH_CHECK("nl_reduce");
   return 0;
 }

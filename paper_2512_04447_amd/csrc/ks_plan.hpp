@@ -25,6 +25,7 @@ struct AxisPlan {
 struct Fft3 {
   AxisPlan ax[3];
   double twopi_over_L[3];
+  double kvec[3];  // Bloch vector (Cartesian, 1/bohr): kinetic |G + k|^2 / 2
 };
 
 }  // namespace ks
@@ -46,6 +47,10 @@ struct ks_plan {
   int32_t natoms = 0;
   int32_t nproj = 0;
   int32_t maxp = 0;             // max projectors per atom
+  // Bloch vector != 0: every projector j of the caller's set is held as the
+  // pair (2j, 2j + 1) of real projectors b cos(k.d), b sin(k.d), which the
+  // reduction combines into the complex coefficient of b exp(-i k.d)
+  int32_t kpairs = 0;
   int64_t nnz = 0;              // (point, projector) pairs with a support value
   int64_t nblk = 0;             // point blocks
   void* Dcoef = nullptr;        // nproj couplings, plan precision

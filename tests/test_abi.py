@@ -119,6 +119,36 @@ def test_plan_create_rejects_inconsistent_projector_sets_on_the_host():
         assert frag in lib.ks_last_error().decode(), (frag, lib.ks_last_error())
 
 
+def test_bloch_plan_validates_on_the_host():
+    """ks_plan_create_k: a null Bloch vector, missing support displacements
+    for a set with projectors, and an atom with more than 4 projectors (its
+    cosine and sine pairs exceed the 9-projector tables) are refused before
+    any device work."""
+    import numpy as np
+
+    from paper_2512_04447_amd import binding
+
+    lib = binding.load()
+    g = binding.KsGrid()
+    g.n[0] = g.n[1] = g.n[2] = 8
+    g.L[0] = g.L[1] = g.L[2] = 5.0
+    out = C.c_void_p()
+    k = np.array([0.1, 0.0, 0.2])
+    kp = k.ctypes.data_as(C.POINTER(C.c_double))
+    disp = np.zeros((2, 3))
+    dp = disp.ctypes.data_as(C.POINTER(C.c_double))
+    keep, ps = _projset(binding, [0, 2], [0, 1], [0, 4], [0, 8], 8, 4)
+    assert lib.ks_plan_create_k(C.byref(out), C.byref(g), None, C.byref(ps), dp, 4, binding.KS_FP64, None) == -3
+    assert lib.ks_plan_create_k(C.byref(out), C.byref(g), kp, C.byref(ps), None, 4, binding.KS_FP64, None) == -5
+    assert "supp_disp" in lib.ks_last_error().decode()
+    keep5, ps5 = _projset(binding, [0, 2], [0, 1], [0, 5], [0, 10], 10, 5)
+    assert lib.ks_plan_create_k(C.byref(out), C.byref(g), kp, C.byref(ps5), dp, 4, binding.KS_FP64, None) == -2003
+    assert "at most 4 projectors" in lib.ks_last_error().decode()
+    bad = np.array([np.nan, 0.0, 0.0])
+    assert lib.ks_plan_create_k(C.byref(out), C.byref(g), bad.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ps),
+                                dp, 4, binding.KS_FP64, None) == -3
+
+
 def test_precond_apply_validates_its_options_on_the_host():
     from paper_2512_04447_amd import binding
 

@@ -101,6 +101,106 @@ def test_oracle_recomputes_generator_potential_and_projectors():
             np.testing.assert_array_equal(oc.proj_supp[j], cell.supp_idx[s0:s1])
             b = cell.beta[cell.beta_ptr[a] + jj * ns: cell.beta_ptr[a] + (jj + 1) * ns]
             assert np.abs(oc.proj_val[j] - b).max() <= 1e-12
+    # the displacements the Bloch phases use: the oracle's own minimum image
+    _, _, disp = oh.oracle_projectors(cfg, oh.oracle_positions(cfg), with_disp=True)
+    for a in range(cell.natoms):
+        s0, s1 = cell.atom_supp_ptr[a], cell.atom_supp_ptr[a + 1]
+        assert np.abs(disp[cell.atom_proj_ptr[a]] - cell.supp_disp[s0:s1]).max() <= 1e-12
+
+
+# ---------------------------------------------------------------- Bloch vectors (k-points)
+
+
+def _dense_h(oc):
+    Ng = oc.n ** 3
+    return oh.apply_h(oc, np.eye(Ng, dtype=np.complex128)).T
+
+
+def _tiny_cfg(n, L, lmax, rc=0.35, pos=((1.3, 0.7, 2.1),)):
+    from types import SimpleNamespace
+
+    return SimpleNamespace(n=n, L=L, v_sigma=0.6, v_depth=-2.0, rcut_factor=4.0, rc=rc, lmax=lmax,
+                           lattice="custom", positions=[x / L for p in pos for x in p], a=L, nsc=1)
+
+
+def _tiny_cell(cfg, D, k=None):
+    pos = np.array(cfg.positions, dtype=np.float64).reshape(-1, 3) * cfg.L
+    V = oh.oracle_potential(cfg, pos)
+    supp, vals, disp = oh.oracle_projectors(cfg, pos, with_disp=True)
+    return oh.from_arrays(cfg.n, cfg.L, V, supp, vals, D, k=k, disp=disp)
+
+
+def test_free_electrons_at_a_bloch_vector_have_the_shifted_spectrum():
+    """V = 0, no projectors: H_k is diagonal in G with |G + k|^2 / 2 over the
+    grid's wave vectors (closed form), and Hermitian."""
+    n, L = 6, 5.0
+    k = np.array([0.31, -0.17, 0.05])
+    oc = oh.from_arrays(n, L, np.zeros(n ** 3), [], [], [], k=k)
+    H = _dense_h(oc)
+    assert np.abs(H - H.conj().T).max() <= 1e-12
+    m = oh.wrapped_m(n)
+    g = 2 * math.pi / L * m
+    ref = np.sort((0.5 * ((g[:, None, None] + k[0]) ** 2 + (g[None, :, None] + k[1]) ** 2
+                          + (g[None, None, :] + k[2]) ** 2)).ravel())
+    assert np.abs(np.linalg.eigvalsh(H) - ref).max() <= 1e-10
+
+
+def test_supercell_at_gamma_is_the_union_of_the_cell_at_eight_bloch_vectors():
+    """Bloch's theorem on the grid: the 2x2x2 supercell (8^3 grid, L = 8) at
+    k = 0 has exactly the eigenvalues of the primitive cell (4^3, L = 4, one
+    atom with a Gaussian well and s+p projectors) at the eight vectors
+    k = (pi / L)(n1, n2, n3), n_i in {0, 1}: the kinetic sets |G + k|^2 / 2
+    tile the supercell's wave vectors and the projector phases exp(-i k.d)
+    carry the images.  A wrong sign or a dropped phase breaks it."""
+    L = 4.0
+    cfg = _tiny_cfg(4, L, 1)
+    rng = np.random.default_rng(21)
+    D = rng.uniform(-1, 1, 4)
+    ev = []
+    for n1 in (0, 1):
+        for n2 in (0, 1):
+            for n3 in (0, 1):
+                k = math.pi / L * np.array([n1, n2, n3], dtype=np.float64)
+                H = _dense_h(_tiny_cell(cfg, D, k))
+                assert np.abs(H - H.conj().T).max() <= 1e-12
+                ev.append(np.linalg.eigvalsh(H))
+    ev = np.sort(np.concatenate(ev))
+    R = np.array([1.3, 0.7, 2.1])
+    pos = [tuple(R + L * np.array([i, j, q])) for i in (0, 1) for j in (0, 1) for q in (0, 1)]
+    scfg = _tiny_cfg(8, 2 * L, 1, pos=pos)
+    sup = _tiny_cell(scfg, np.tile(D, 8))
+    es = np.linalg.eigvalsh(_dense_h(sup))
+    assert np.abs(es - ev).max() <= 1e-10
+
+
+def test_spectrum_at_minus_k_equals_spectrum_at_k():
+    """A real potential and real projector radial parts give
+    H_{-k} = conj(H_k): the same eigenvalues at k and -k, different from the
+    Gamma point's."""
+    cfg = _tiny_cfg(5, 4.5, 1)
+    D = np.array([0.7, -0.4, -0.4, -0.4])
+    k = np.array([0.4, 0.1, -0.25])
+    Hp = _dense_h(_tiny_cell(cfg, D, k))
+    Hm = _dense_h(_tiny_cell(cfg, D, -k))
+    assert np.abs(Hm - np.conj(Hp)).max() <= 1e-12
+    ep, em = np.linalg.eigvalsh(Hp), np.linalg.eigvalsh(Hm)
+    e0 = np.linalg.eigvalsh(_dense_h(_tiny_cell(cfg, D)))
+    assert np.abs(ep - em).max() <= 1e-10
+    assert np.abs(ep - e0).max() > 1e-3
+
+
+def test_oracle_lobpcg_at_a_bloch_vector_matches_dense_eigh():
+    """The oracle's LOBPCG (TPA on |G + k|^2 / 2) at k on a 6^3 cell with s+p
+    projectors: lowest eigenvalues against a dense eigensolve of H_k."""
+    cfg = _tiny_cfg(6, 5.0, 1, rc=0.4)
+    D = np.array([0.9, -0.5, -0.5, -0.5])
+    k = np.array([0.2, -0.35, 0.1])
+    oc = _tiny_cell(cfg, D, k)
+    ref = np.linalg.eigvalsh(_dense_h(oc))
+    rng = np.random.default_rng(5)
+    X0 = rng.standard_normal((8, 216)) + 1j * rng.standard_normal((8, 216))
+    st, _ = olob.run(oc, X0, 6, 1e-9, 300, olob.tpa_preconditioner(oc))
+    assert np.abs(st.theta[:6] - ref[:6]).max() <= 1e-10
 
 
 def test_config_sizes_match_derived_table():
