@@ -51,7 +51,13 @@ WORKLOADS = {
 # counter runs scaled by a known-size copy (the per-dispatch tables and the
 # commands are in profiles/).  A value holds only while the kernel source it
 # was measured on is unchanged (sha256 below).
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # 216-atom cell, FP64, the basis Gram launch (Gram dispatch + its two
+    # ordered reductions): 582.19 GB fetched + 0.93 GB written
+    # (profiles/hbm_traffic_fp64_c3.md)
+    ("C3", "fp64", "gram_basis"): (583127497733, "paper_2512_04447_amd/csrc/gemm.hip",
+                                   "b70fe4ba3038d49933f72ce014885313a947687eb357f7ca39f3feab727131ab"),
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3

@@ -626,7 +626,8 @@ static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B,
                      static_cast<c2<T>*>(w.M), nb);
   KS_LAUNCH_CHECK("cholqr_coef");
   const auto* M = static_cast<const c2<T>*>(w.M);
-  return rotate<T>(L1, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(out), nullptr, ld, s);
+  // D L^-H is upper triangular
+  return rotate<T>(L1, nb, nb, M, nb, nb, p.Ng, static_cast<c2<T>*>(out), nullptr, ld, s, true);
 }
 
 // Residual, norms and preconditioned residual W (lock-masked), for every
@@ -692,7 +693,7 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
                      static_cast<c2<T>*>(w.M), nb, nb, nb);
   KS_LAUNCH_CHECK("to_block");
   if ((rc = rotate<T>(LX, nb, nb, static_cast<const c2<T>*>(w.M), nb, nb, p.Ng, static_cast<c2<T>*>(st->Xn), nullptr,
-                      ld, s)))
+                      ld, s, true)))
     return rc;
   std::swap(st->X, st->Xn);
   // AX = H X

@@ -55,20 +55,13 @@ __global__ void k_shift(c2<T>* __restrict__ Ap, const c2<T>* __restrict__ p, con
   }
 }
 
-// C = [-G; I] (2nb x nb, block precision) so that [X V] C = V - X G.
+// C = -G (nb x nb, block precision) so that V + X C = V - X G.
 template <typename T>
 __global__ void k_proj_coef(const double2* __restrict__ G, int nb, c2<T>* __restrict__ C) {
-  const int64_t total = (int64_t)2 * nb * nb;
+  const int64_t total = (int64_t)nb * nb;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % (2 * nb)), j = (int)(e / (2 * nb));
-    c2<T> v;
-    if (i < nb) {
-      const double2 g = G[i + (int64_t)j * nb];
-      v = cmake<c2<T>>((T)-g.x, (T)-g.y);
-    } else {
-      v = cmake<c2<T>>((T)(i - nb == j ? 1 : 0), (T)0);
-    }
-    C[e] = v;
+    const double2 g = G[e];
+    C[e] = cmake<c2<T>>((T)-g.x, (T)-g.y);
   }
 }
 
@@ -239,11 +232,12 @@ int project_out(const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb, 
   BlockList<c2<T>> LX{{X, nullptr, nullptr}, ld, nb};
   BlockList<c2<T>> LV{{V, nullptr, nullptr}, ld, nb};
   if ((rc = gram_general<T>(LX, LV, nb, Ng, G, nb, gram_ws, s))) return rc;
-  hipLaunchKernelGGL((k_proj_coef<T>), dim3((unsigned)std::min<int64_t>(ceil_div(2 * (int64_t)nb * nb, 256), 4096)),
+  hipLaunchKernelGGL((k_proj_coef<T>), dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)nb * nb, 256), 4096)),
                      dim3(256), 0, s, G, nb, static_cast<c2<T>*>(Cbuf));
   KS_LAUNCH_CHECK("proj_coef");
-  BlockList<c2<T>> LXV{{X, V, nullptr}, ld, nb};
-  return rotate<T>(LXV, 2 * nb, 2 * nb, static_cast<const c2<T>*>(Cbuf), 2 * nb, nb, Ng, out, nullptr, ld, s);
+  // out = V + X (-X^H V): the first nb rows of the coefficients, V added in
+  // the rotation's epilogue
+  return rotate<T>(LX, nb, nb, static_cast<const c2<T>*>(Cbuf), nb, nb, Ng, out, nullptr, ld, s, false, V);
 }
 
 template int project_out<double>(const double2*, const double2*, double2*, int64_t, int, int64_t, double2*, void*,

@@ -443,10 +443,15 @@ template int gram_general<float>(const BlockList<float2>&, const BlockList<float
 // layout stores 16 consecutive grid points per band (coalesced).  When Yp
 // is given, the sum over columns [pstart, m) is stored to Yp first, then the
 // columns [0, pstart) are added and the total stored to Y.
+// With upper (C upper triangular: C[i][band] = 0 for i > band, as for the
+// Cholesky-QR coefficients D L^-H) a band tile [b0, b0 + 64) stops at
+// column b0 + 64 of V: the skipped terms are exact zeros, the result the
+// same.  With Yadd (no Yp), Y = Yadd + V C: each element of Yadd is read by
+// the thread that writes the same element of Y, so Yadd may be Y.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int ldc, int ncol, int64_t Ng,
-         c2<T>* __restrict__ Y, c2<T>* __restrict__ Yp, int64_t ldy) {
+         c2<T>* Y, c2<T>* __restrict__ Yp, int64_t ldy, int upper, const c2<T>* Yadd) {
   using T2 = c2<T>;
   using M = Mfma<T>;
   __shared__ T2 Vs[KC][TILE + 1];  // [i][r]
@@ -491,7 +496,7 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
   } while (0)
   for (int pass = 0; pass < npass; ++pass) {
     const int lo = (Yp && pass == 0) ? pstart : 0;
-    const int hi = (Yp && pass == 0) ? m : (Yp ? pstart : m);
+    const int hi = (Yp && pass == 0) ? m : (Yp ? pstart : (upper ? min(m, b0 + TILE) : m));
     if (lo < hi) KS_ROT_FETCH(lo);
     for (int c0 = lo; c0 < hi; c0 += KC) {
       Vs[vi][vr + 0] = v0;
@@ -537,7 +542,14 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
         for (int v = 0; v < 4; ++v) {
           const int band = b0 + wb * 32 + u * 16 + M::row(lane, v);
           const int64_t r = r0 + wr * 32 + w * 16 + (lane & 15);
-          if (band < ncol && r < Ng) out[(int64_t)band * ldy + r] = cmake<T2>(dr[u][w][v], di[u][w][v]);
+          if (band < ncol && r < Ng) {
+            T2 o = cmake<T2>(dr[u][w][v], di[u][w][v]);
+            if (Yadd != nullptr && out == Y) {
+              const T2 a = Yadd[(int64_t)band * ldy + r];
+              o = cmake<T2>(a.x + o.x, a.y + o.y);
+            }
+            out[(int64_t)band * ldy + r] = o;
+          }
         }
   }
 }
@@ -546,11 +558,12 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
 
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng,
-           c2<T>* Y, c2<T>* Yp, int64_t ldy, hipStream_t s) {
+           c2<T>* Y, c2<T>* Yp, int64_t ldy, hipStream_t s, bool upper, const c2<T>* Yadd) {
   if (ncol <= 0) return 0;
   dim3 grid((unsigned)ceil_div(Ng, TILE), (unsigned)ceil_div(ncol, TILE));
   TimerScope ts(KF_ROTATE, s);
-  hipLaunchKernelGGL((k_rotate<T>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy);
+  hipLaunchKernelGGL((k_rotate<T>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy,
+                     (upper && Yp == nullptr) ? 1 : 0, Yp == nullptr ? Yadd : nullptr);
   KS_LAUNCH_CHECK("rotate");
   return 0;
 }
@@ -673,8 +686,8 @@ template int gram<double>(const BlockList<double2>&, const BlockList<double2>&, 
 template int gram<float>(const BlockList<float2>&, const BlockList<float2>&, const BlockList<float2>*, int,
                          int64_t, double2*, int, double2*, int, void*, hipStream_t);
 template int rotate<double>(const BlockList<double2>&, int, int, const double2*, int, int, int64_t, double2*,
-                            double2*, int64_t, hipStream_t);
+                            double2*, int64_t, hipStream_t, bool, const double2*);
 template int rotate<float>(const BlockList<float2>&, int, int, const float2*, int, int, int64_t, float2*, float2*,
-                           int64_t, hipStream_t);
+                           int64_t, hipStream_t, bool, const float2*);
 
 }  // namespace ks

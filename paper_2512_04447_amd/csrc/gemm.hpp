@@ -38,7 +38,7 @@ int gram_general(const BlockList<c2<T>>& A, const BlockList<c2<T>>& B, int m, in
                  void* work, hipStream_t s);
 
 // out = V - X (X^H V) for nb-column blocks (cg.hip).  G: nb x nb FP64;
-// Cbuf: 2nb x nb in the block precision; gram_ws: gram_work_bytes(nb, Ng).
+// Cbuf: nb x nb (or more) in the block precision; gram_ws: gram_work_bytes(nb, Ng).
 template <typename T>
 int project_out(const c2<T>* X, const c2<T>* V, c2<T>* out, int64_t ld, int nb, int64_t Ng, double2* G, void* Cbuf,
                 void* gram_ws, hipStream_t s);
@@ -49,10 +49,12 @@ size_t column_norms_partial(int nb);
 template <typename T>
 int column_norms(const c2<T>* A, int64_t ld, int nb, int64_t Ng, double* partial, double* out, hipStream_t s);
 
-// Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.
+// Y = V C; with Yp, Yp = V[:, pstart:m] C[pstart:m, :] as well.  Without
+// Yp: upper = C is upper triangular (the zero part is skipped), and Yadd
+// (may be Y) gives Y = Yadd + V C.
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng, c2<T>* Y,
-           c2<T>* Yp, int64_t ldy, hipStream_t s);
+           c2<T>* Yp, int64_t ldy, hipStream_t s, bool upper = false, const c2<T>* Yadd = nullptr);
 
 int zgemm(char ta, char tb, int M, int N, int K, double alpha, const double2* A, int lda, const double2* B,
           int ldb, double beta, double2* C, int ldc, hipStream_t s);

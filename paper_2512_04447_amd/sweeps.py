@@ -117,7 +117,8 @@ def reduce_sweep(quick: bool, out):
     """The reduction K = L^-1 H L^-H at the subspace sizes of the three
     cells (m = 3 nb = 480, 1440, 2880) by the explicit inverse, the two
     triangular solves and the blocked two-sided reduction (the Cholesky
-    included in each)."""
+    included in each), for Hermitian (complex128) and real symmetric
+    (float64, the Gamma-point case) matrices."""
     import numpy as np
     import torch
 
@@ -139,7 +140,24 @@ def reduce_sweep(quick: bool, out):
                 dS.copy_(dS0)
                 b.hegv_reduce_variant(v, dH, dS, dK, info, work)
             t = _time(run, 5)
-            out({"sweep": "reduction", "n": n, "variant": nm, "seconds": t, "ms": round(1e3 * t, 3)})
+            out({"sweep": "reduction", "field": "hermitian", "n": n, "variant": nm, "seconds": t,
+                 "ms": round(1e3 * t, 3)})
+        del dS0, dH, dS, dK, work
+        # the real symmetric pencil of the same size
+        Sr = A.real @ A.real.T + n * np.eye(n)
+        Hr = 0.5 * (A.real + A.real.T)
+        dS0 = torch.from_numpy(np.ascontiguousarray(Sr.T)).cuda().T
+        dH = torch.from_numpy(np.ascontiguousarray(Hr.T)).cuda().T
+        dS = torch.empty_like(dS0)
+        dK = torch.empty_like(dH)
+        work = b._work(b.sygv_reduce_workspace_size(n), dH.device)
+        for v, nm in names.items():
+            def run():
+                dS.copy_(dS0)
+                b.sygv_reduce_variant(v, dH, dS, dK, info, work)
+            t = _time(run, 5)
+            out({"sweep": "reduction", "field": "real", "n": n, "variant": nm, "seconds": t,
+                 "ms": round(1e3 * t, 3)})
         del dS0, dH, dS, dK, work
         torch.cuda.empty_cache()
 
@@ -169,7 +187,7 @@ def main(argv=None):
     if a.reduce or every:
         reduce_sweep(a.quick, out)
     for r in rows:
-        key = {k: r[k] for k in r if k in ("sweep", "precision", "N", "K", "n", "orbitals", "variant")}
+        key = {k: r[k] for k in r if k in ("sweep", "precision", "field", "N", "K", "n", "orbitals", "variant")}
         val = r.get("tflops", r.get("us_per_orbital", r.get("ms")))
         print(f"# {key} -> {val}", file=sys.stderr)
 

@@ -312,7 +312,7 @@ def _c2_golden():
     import os
 
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_eigenvalues.txt")
-    return np.loadtxt(path, comments="#")
+    return np.loadtxt(path, comments="#", usecols=1)
 
 
 def test_learned_preconditioner_iterations_to_1e6_against_tpa(ks):
@@ -320,13 +320,17 @@ def test_learned_preconditioner_iterations_to_1e6_against_tpa(ks):
     on 8- and 64-atom cells, every convolution on the bfloat16 matrix cores)
     are worth by the measure that counts: LOBPCG iterations from the same
     initial block of the 64-atom cell (FP64) until every tracked eigenvalue
-    is within 1e-6 Ha of the oracle's, against TPA, with the switch to TPA
-    turned off.  The network on the TPA output with the skip connection
-    (KS_PRECOND_CNN_TPA) converges, more slowly than TPA; the network on the
-    plain residual (KS_PRECOND_CNN) gives the largest first-step drop but
-    stalls.  The bounds below are the measured results (a negative result
-    for the learned preconditioner), asserted so that a regression in the
-    kernels or the weights shows."""
+    is within 1e-6 Ha of the oracle's, against TPA.
+
+    Measured (a negative result for the learned preconditioner): TPA needs
+    11 iterations.  With the switch to TPA turned off, the network on the
+    plain residual (KS_PRECOND_CNN) gives the largest first-step drop (max
+    tracked residual 5.1 against TPA's 19.8) and then stalls near 4; the
+    network on the TPA output with the skip connection (KS_PRECOND_CNN_TPA)
+    falls to about 0.2 in 60 iterations without reaching the tolerance.
+    With the driver's switch to TPA on a stall the network on r converges.
+    Asserted: TPA converges within 20 iterations, the network's first step
+    beats TPA's, the switched run converges, every run stays finite."""
     import os
 
     import torch
@@ -344,22 +348,21 @@ def test_learned_preconditioner_iterations_to_1e6_against_tpa(ks):
     x0 = dev(ki.make_x0(cfg))
     gold = _c2_golden()[: cfg.ntrack]
     out = {}
-    for name, kind, wpath, maxit in (("tpa", b.KS_PRECOND_TPA, None, 40),
-                                     ("cnn_tpa", b.KS_PRECOND_CNN_TPA, lr.WEIGHTS_TPA, 60),
-                                     ("cnn", b.KS_PRECOND_CNN, lr.WEIGHTS, 30)):
+    runs = (("tpa", b.KS_PRECOND_TPA, None, 40, False),
+            ("cnn_tpa", b.KS_PRECOND_CNN_TPA, lr.WEIGHTS_TPA, 40, False),
+            ("cnn", b.KS_PRECOND_CNN, lr.WEIGHTS, 30, False),
+            ("cnn_switch", b.KS_PRECOND_CNN, lr.WEIGHTS, 40, True))
+    for name, kind, wpath, maxit, switch in runs:
         params = None if wpath is None else torch.from_numpy(np.load(wpath)).cuda()
         r = solve.run_to_tolerance(plan, v, x0, cfg.ntrack, kind, 1e-7, maxit, ref=gold, cnn_params=params,
-                                   switch_to_tpa=False, log=lambda *a: None)
-        first = r["history"][1][1] if len(r["history"]) > 1 else float("nan")
+                                   switch_to_tpa=switch, log=lambda *a: None)
+        first = r["history"][1][1]
         out[name] = (r["reached"], r["iterations"], r["seconds"], first, r["max_res"])
         _say(name, "reached", r["reached"], "iterations", r["iterations"], "seconds", round(r["seconds"], 3),
-             "first-step max res", first, "final max res", r["max_res"])
+             "first-step max res", first, "final max res", r["max_res"], "switched at", r["switched_to_tpa_at"])
         del r
         torch.cuda.empty_cache()
     assert out["tpa"][0] and out["tpa"][1] <= 20
-    assert out["cnn_tpa"][0]
-    assert out["cnn_tpa"][1] <= 3 * out["tpa"][1]
-    # every run stays finite
+    assert out["cnn"][3] < out["tpa"][3]
+    assert out["cnn_switch"][0]
     assert all(np.isfinite(o[4]) for o in out.values())
-
-
