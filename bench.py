@@ -120,9 +120,11 @@ def family_work(cfg, es):
         "gram_flops": 8 * Ng * (nb * (nb + 1) / 2 * (2 + extra) + nb * nb + 2 * m * (m + 1) / 2),
         # the basis Gram alone: S and H over [X W P], Hermitian triangles
         "gram_basis_flops": 8 * Ng * m * (m + 1),
-        # W and P orthonormalising rotations, the projection update, and one
-        # pass over V giving X' = V C and P' = V[:, nb:] C[nb:]
-        "rotate_flops": 8 * Ng * (nb * nb * (3 + extra) + m * nb + 2 * nb * nb),
+        # the W and P (and, mixed, X) orthonormalising rotations by upper
+        # triangular coefficients (nb(nb+1)/2 multiply-adds per grid point),
+        # the projection update X (X^H W) (nb^2), and X' = V C (m nb); P' =
+        # V[:, nb:] C[nb:] is the partial sum of the same pass, no extra work
+        "rotate_flops": 8 * Ng * (nb * (nb + 1) / 2 * (2 + extra) + nb * nb + m * nb),
         # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-applies (R+W)
         "pass_a_bytes": blk * (2 + 3 + 2 * n_h),
         # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W) per H-apply
