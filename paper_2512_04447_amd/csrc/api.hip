@@ -421,7 +421,7 @@ struct PrecondWs {
 static char* precond_layout(const ks_plan& p, char* q, int nb, bool cnn, PrecondWs& w) {
   auto take = [&](size_t bytes) { char* r = q; q += al(bytes); return r; };
   const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
-  const size_t cnt = std::max<size_t>((size_t)n0, (size_t)n1 * (n2 / p.zc));
+  const size_t cnt = std::max<size_t>((size_t)std::max(n0, p.a_parts), (size_t)n1 * (n2 / p.zc));
   w.partial = reinterpret_cast<double*>(take((size_t)nb * cnt * 8));
   w.E = reinterpret_cast<double*>(take((size_t)nb * 8));
   if (cnn) {
@@ -1001,7 +1001,20 @@ static int plan_create(ks_plan** out, const ks_grid* grid, const double* kvec, c
   int dev = 0, maxlds = 0;
   KS_HIP(hipGetDevice(&dev));
   KS_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if (p->lds_plane > (size_t)maxlds || p->lds_pencil > (size_t)maxlds) {
+  p->a_parts = n0;
+  if (p->lds_plane > (size_t)maxlds) {
+    // split planes: the largest row and column groups of at most 4096
+    // points (16 per thread of a 256-thread block) that fit in the LDS
+    p->split = 1;
+    for (int r = 1; r <= n1; ++r)
+      if (n1 % r == 0 && (int64_t)r * n2 <= 4096 && (size_t)(r * n2 + n2) * es <= (size_t)maxlds) p->ry = r;
+    for (int z = 1; z <= n2; ++z)
+      if (n2 % z == 0 && (int64_t)n1 * z <= 4096 && (size_t)(n1 * z + n1) * es <= (size_t)maxlds) p->zc2 = z;
+    p->lds_rows = (size_t)(p->ry * n2 + n2) * es;
+    p->lds_cols = (size_t)(n1 * p->zc2 + n1) * es;
+    p->a_parts = p->ry > 0 ? n0 * (n1 / p->ry) : 0;
+  }
+  if ((p->split && (p->ry == 0 || p->zc2 == 0)) || p->lds_pencil > (size_t)maxlds) {
     delete p;
     return fail(KS_E_UNSUPPORTED, "plane does not fit in LDS");
   }

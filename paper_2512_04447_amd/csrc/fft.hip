@@ -562,6 +562,147 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- split planes
+// For planes that do not fit in the LDS of a CU (FP64 above 96^2 points),
+// pass A becomes k_rows (z-transforms of ry consecutive y-rows of an
+// x-plane, contiguous in memory) then k_cols (y-transforms of zc2
+// consecutive z-columns, stride n2), and pass C becomes k_cols on conjugated
+// data then k_rows with pass C's epilogue.  Tiles of at most 4096 points,
+// 256 threads, no LDS padding.
+// k_rows MODE 0: load psi.  MODE 1: load r = ax - theta x, partial[block] =
+// sum |r|^2.  MODE 2 (H): out = conj(t)/Ng + V psi.  MODE 3: out =
+// conj(t)/Ng, zero for bands with res <= lock_tol.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_rows(Fft3 f, int ry, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
+       const double* __restrict__ theta, int64_t ld, c2<T>* __restrict__ dst, int64_t ldd,
+       const c2<T>* __restrict__ tw2, const T* __restrict__ V, const c2<T>* __restrict__ psi, int64_t ldp,
+       const double* __restrict__ res, double lock_tol, double* __restrict__ partial) {
+  using T2 = c2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* s = reinterpret_cast<T2*>(smem_raw);
+  __shared__ double red[kThreads / kWave];
+  const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  const int nrc = n1 / ry;
+  int bid = blockIdx.x;
+  const int rc = bid % nrc;
+  bid /= nrc;
+  const int x = bid % n0;
+  const int band = bid / n0;
+  const int tile = ry * n2;
+  const int64_t off = (int64_t)x * n1 * n2 + (int64_t)rc * ry * n2;
+  T2* st2 = s + tile;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
+  const T2* in = src + band * ld + off;
+  constexpr int BATCH = 8;
+  double acc = 0.0;
+  if (MODE == 1) {
+    const T2* in2 = src2 + band * ld + off;
+    const T th = T(theta[band]);
+    for (int i0 = threadIdx.x; i0 < tile; i0 += kThreads * BATCH) {
+      T2 a[BATCH], b[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * kThreads, tile - 1);
+        a[u] = in[i];
+        b[u] = in2[i];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = i0 + u * kThreads;
+        const T2 r = cmake<T2>(a[u].x - th * b[u].x, a[u].y - th * b[u].y);
+        const double r2 = (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+        acc += i < tile ? r2 : 0.0;
+        s[min(i, tile - 1)] = r;
+      }
+    }
+  } else {
+    for (int i0 = threadIdx.x; i0 < tile; i0 += kThreads * BATCH) {
+      T2 a[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) a[u] = in[min(i0 + u * kThreads, tile - 1)];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) s[min(i0 + u * kThreads, tile - 1)] = a[u];
+    }
+  }
+  __syncthreads();
+  fft_batch<16, false>(s, ry, f.ax[2], 1, n2, st2);
+  T2* out = dst + band * ldd + off;
+  if (MODE <= 1) {
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) out[i] = s[i];
+    if (MODE == 1) {
+      const double t = block_sum(acc, red);
+      if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+    return;
+  }
+  const T scale = T(1.0 / ((double)n0 * (double)n1 * (double)n2));
+  if (MODE == 2) {
+    const T2* ps = psi + band * ldp + off;
+    for (int i0 = threadIdx.x; i0 < tile; i0 += kThreads * BATCH) {
+      T2 pv[BATCH];
+      T vr[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * kThreads, tile - 1);
+        pv[u] = ps[i];
+        vr[u] = V[off + i];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int i = min(i0 + u * kThreads, tile - 1);
+        const T2 t = s[i];
+        out[i] = cmake<T2>(t.x * scale + vr[u] * pv[u].x, -t.y * scale + vr[u] * pv[u].y);
+      }
+    }
+  } else {
+    const T m = (res[band] > lock_tol) ? scale : T(0);
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const T2 t = s[i];
+      out[i] = cmake<T2>(t.x * m, -t.y * m);
+    }
+  }
+}
+
+// y-transforms of zc2 consecutive z-columns of one x-plane, in place; CONJ:
+// conjugate on load (the first half of an inverse transform).
+template <typename T, bool CONJ>
+__global__ void __launch_bounds__(kThreads)
+k_cols(Fft3 f, int zc2, c2<T>* __restrict__ buf, int64_t ld, const c2<T>* __restrict__ tw1) {
+  using T2 = c2<T>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T2* s = reinterpret_cast<T2*>(smem_raw);
+  const int n0 = f.ax[0].n, n1 = f.ax[1].n, n2 = f.ax[2].n;
+  const int nzc = n2 / zc2;
+  int bid = blockIdx.x;
+  const int zt = bid % nzc;
+  bid /= nzc;
+  const int x = bid % n0;
+  const int band = bid / n0;
+  T2* base = buf + band * ld + (int64_t)x * n1 * n2 + zt * zc2;
+  const int tile = n1 * zc2;
+  T2* st1 = s + tile;
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
+  constexpr int BATCH = 8;
+  for (int i0 = threadIdx.x; i0 < tile; i0 += kThreads * BATCH) {
+    T2 a[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int i = min(i0 + u * kThreads, tile - 1);
+      const int y = i / zc2, z = i - y * zc2;
+      a[u] = base[(int64_t)y * n2 + z];
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) s[min(i0 + u * kThreads, tile - 1)] = CONJ ? cconj(a[u]) : a[u];
+  }
+  __syncthreads();
+  fft_batch<16, false>(s, zc2, f.ax[1], zc2, 1, st1);
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int y = i / zc2, z = i - y * zc2;
+    base[(int64_t)y * n2 + z] = s[i];
+  }
+}
+
 // ---------------------------------------------------------------- nonlocal
 // Deterministic (no atomics, fixed summation orders).
 
@@ -940,8 +1081,30 @@ static int fixed_n(const ks_plan& p) {
 }
 
 template <typename T>
+static int split_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2, const double* theta, int64_t ld,
+                   c2<T>* dst, int64_t ldd, int nb, double* partial, hipStream_t s) {
+  const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
+  const auto* tw1 = static_cast<const c2<T>*>(p.tw[1]);
+  const auto* tw2 = static_cast<const c2<T>*>(p.tw[2]);
+  TimerScope ts(KF_PASS_A, s);
+  const dim3 gr((unsigned)(nb * n0 * (n1 / p.ry)));
+  if (mode == 0)
+    hipLaunchKernelGGL((k_rows<T, 0>), gr, dim3(kThreads), p.lds_rows, s, p.fft, p.ry, src, src2, theta, ld, dst, ldd,
+                       tw2, nullptr, nullptr, 0, nullptr, 0.0, partial);
+  else
+    hipLaunchKernelGGL((k_rows<T, 1>), gr, dim3(kThreads), p.lds_rows, s, p.fft, p.ry, src, src2, theta, ld, dst, ldd,
+                       tw2, nullptr, nullptr, 0, nullptr, 0.0, partial);
+  KS_LAUNCH_CHECK("split pass A rows");
+  hipLaunchKernelGGL((k_cols<T, false>), dim3((unsigned)(nb * n0 * (n2 / p.zc2))), dim3(kThreads), p.lds_cols, s,
+                     p.fft, p.zc2, dst, ldd, tw1);
+  KS_LAUNCH_CHECK("split pass A columns");
+  return 0;
+}
+
+template <typename T>
 static int pass_a(const ks_plan& p, int mode, const c2<T>* src, const c2<T>* src2, const double* theta,
                   int64_t ld, c2<T>* dst, int64_t ldd, int nb, double* partial, hipStream_t s) {
+  if (p.split) return split_a<T>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
   switch (fixed_n(p)) {
     case 16: return launch_plane_a<T, 4, kThreads, 16>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
     case 48: return launch_plane_a<T, 16, kThreads, 48>(p, mode, src, src2, theta, ld, dst, ldd, nb, partial, s);
@@ -981,10 +1144,34 @@ static int launch_plane_c(const ks_plan& p, int mode, const c2<T>* src, int64_t 
   return 0;
 }
 
+// src is scratch: the split form transforms it in place first.
+template <typename T>
+static int split_c(const ks_plan& p, int mode, c2<T>* src, int64_t lds_, c2<T>* dst, int64_t ldd, int nb,
+                   const T* V, const c2<T>* psi, int64_t ldp, const double* res, double lock_tol, hipStream_t s) {
+  const int n0 = p.fft.ax[0].n, n1 = p.fft.ax[1].n, n2 = p.fft.ax[2].n;
+  const auto* tw1 = static_cast<const c2<T>*>(p.tw[1]);
+  const auto* tw2 = static_cast<const c2<T>*>(p.tw[2]);
+  TimerScope ts(KF_PASS_C, s);
+  hipLaunchKernelGGL((k_cols<T, true>), dim3((unsigned)(nb * n0 * (n2 / p.zc2))), dim3(kThreads), p.lds_cols, s,
+                     p.fft, p.zc2, src, lds_, tw1);
+  KS_LAUNCH_CHECK("split pass C columns");
+  const dim3 gr((unsigned)(nb * n0 * (n1 / p.ry)));
+  if (mode == 0)
+    hipLaunchKernelGGL((k_rows<T, 2>), gr, dim3(kThreads), p.lds_rows, s, p.fft, p.ry, src, nullptr, nullptr, lds_,
+                       dst, ldd, tw2, V, psi, ldp, res, lock_tol, nullptr);
+  else
+    hipLaunchKernelGGL((k_rows<T, 3>), gr, dim3(kThreads), p.lds_rows, s, p.fft, p.ry, src, nullptr, nullptr, lds_,
+                       dst, ldd, tw2, V, psi, ldp, res, lock_tol, nullptr);
+  KS_LAUNCH_CHECK("split pass C rows");
+  return 0;
+}
+
 template <typename T>
 static int pass_c(const ks_plan& p, int mode, const c2<T>* src, int64_t lds_, c2<T>* dst, int64_t ldd,
                   int nb, const T* V, const c2<T>* psi, int64_t ldp, const c2<T>* dc,
                   const double* res, double lock_tol, hipStream_t s) {
+  if (p.split)
+    return split_c<T>(p, mode, const_cast<c2<T>*>(src), lds_, dst, ldd, nb, V, psi, ldp, res, lock_tol, s);
   switch (fixed_n(p)) {
     case 16: return launch_plane_c<T, 4, kThreads, 16>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
     case 48: return launch_plane_c<T, 16, kThreads, 48>(p, mode, src, lds_, dst, ldd, nb, V, psi, ldp, dc, res, lock_tol, s);
@@ -1170,7 +1357,7 @@ int precond_apply(const ks_plan& p, int kind, const c2<T>* X, const c2<T>* AX, c
   }
   // residual, its norms, and the forward (y,z) transform in one pass
   if ((rc = pass_a<T>(p, 1, AX, X, theta, ld, tmp, ldt, nb, partial, s))) return rc;
-  hipLaunchKernelGGL(k_row_sum, dim3(nb), dim3(kThreads), 0, s, partial, p.fft.ax[0].n, nb, 1.0, 1, res);
+  hipLaunchKernelGGL(k_row_sum, dim3(nb), dim3(kThreads), 0, s, partial, p.a_parts, nb, 1.0, 1, res);
   KS_LAUNCH_CHECK("row_sum");
   // identity preconditioner: the (y,z) forward and inverse passes cancel
   if (kind == KS_PRECOND_TPA) {

@@ -43,6 +43,13 @@ struct ks_plan {
   int zc;          // z extent of one x-pencil tile
   size_t lds_plane;
   size_t lds_pencil;
+  // Planes that do not fit in a CU's LDS (FP64 above 96^2 points): pass A and
+  // pass C each run as two passes, z-transforms of groups of ry y-rows and
+  // y-transforms of groups of zc2 z-columns of an x-plane.
+  int split = 0;
+  int ry = 0, zc2 = 0;
+  size_t lds_rows = 0, lds_cols = 0;
+  int a_parts = 0;  // partial sums per band written by the residual form of pass A
   // projectors, organised by blocks of kScatterPts consecutive grid points
   int32_t natoms = 0;
   int32_t nproj = 0;

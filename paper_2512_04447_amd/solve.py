@@ -150,14 +150,17 @@ def run_to_tolerance(plan, v, X0, ntrack: int, precond: int, lock_tol: float, ma
 
 
 def run_mixed_refined(plan_m, v_m, plan_64, v_64, X0, ntrack: int, precond: int, lock_m: float, crit: Criterion,
-                      maxit: int, cnn_params=None, handover_res: float = 2e-4, lock_64: float = 1e-9, log=print):
+                      maxit: int, cnn_params=None, handover_res: float = 2e-4, lock_64: float = 1e-9,
+                      res_tol_64: float = 0.0, log=print):
     """Mixed-precision LOBPCG (complex64 blocks) until the max tracked
     residual is at most handover_res or stops falling, then the block is
     widened to complex128 and the FP64 plan continues (Cholesky-QR,
     Rayleigh-Ritz, TPA steps) until the criterion holds.  The FP32 residual
     floor (about 1e-4 here) bounds what the mixed steps alone can reach:
     eigenvalues within 1e-6 Ha, but subspace angles of order
-    residual / gap; the FP64 steps close the rest."""
+    residual / gap; the FP64 steps close the rest.  Without a criterion
+    (crit None) the FP64 steps run until the max tracked residual is at
+    most res_tol_64."""
     import torch
 
     lob = b.Lobpcg(plan_m, v_m, X0.to(torch.complex64))
@@ -174,11 +177,12 @@ def run_mixed_refined(plan_m, v_m, plan_64, v_64, X0, ntrack: int, precond: int,
         Xw = lob.X.to(torch.complex128)  # exact widening
         del lob
         run.lob = None
+        torch.cuda.empty_cache()  # the complex64 blocks' memory back to the device for the FP64 ones
         lob64 = b.Lobpcg(plan_64, v_64, Xw)
         del Xw
         lob64.init()
         run.lob = lob64
-        iterate(run, ntrack, b.KS_PRECOND_TPA, lock_64, maxit, t0, crit, log=log)
+        iterate(run, ntrack, b.KS_PRECOND_TPA, lock_64, maxit, t0, crit, res_tol_64, log=log)
     torch.cuda.synchronize()
     h = run.history[-1]
     return {"seconds": h[0], "iterations": run.iterations, "mixed_iterations": mixed_iters,

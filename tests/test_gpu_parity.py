@@ -36,6 +36,8 @@ CELLS = {
     # the 216-atom and 128-atom cells' grids (radices 16 x 6 and 16 x 7)
     "big96": lambda: ki.custom_config("big96", 12.0, 96, ((0.3, 0.45, 0.2),), 2, lmax=1, rc=0.62),
     "big112": lambda: ki.custom_config("big112", 14.0, 112, ((0.6, 0.35, 0.15),), 1, lmax=2, rc=0.64),
+    # FP64 planes beyond a CU's LDS: the split row / column passes
+    "big100": lambda: ki.custom_config("big100", 12.5, 100, ((0.3, 0.45, 0.2),), 2, lmax=1, rc=0.62),
 }
 
 
@@ -57,7 +59,8 @@ def to_dev(a, dtype=None):
 
 @pytest.mark.parametrize("name,nb,prec", [("C1", 16, 0), ("tiny10_sp", 5, 0), ("tiny12_spd", 7, 0), ("odd14", 3, 0),
                                           ("C2", 20, 0), ("big72", 3, 0), ("big70", 2, 0), ("big72", 3, 1),
-                                          ("big70", 2, 1), ("big96", 2, 0), ("big96", 2, 1), ("big112", 1, 1)])
+                                          ("big70", 2, 1), ("big96", 2, 0), ("big96", 2, 1), ("big112", 1, 1),
+                                          ("big112", 1, 0), ("big100", 2, 0)])
 def test_apply_h_matches_oracle(ks, name, nb, prec):
     """FP64 plans to 1e-12 and FP32 plans (prec 1) to 2e-6 of max |H psi|."""
     import torch
@@ -90,7 +93,7 @@ def test_apply_h_matches_oracle(ks, name, nb, prec):
     assert err <= (1e-12 if prec == 0 else 2e-6)
 
 
-@pytest.mark.parametrize("name,nb", [("C1", 16), ("tiny10_sp", 6), ("C2", 12), ("big72", 3)])
+@pytest.mark.parametrize("name,nb", [("C1", 16), ("tiny10_sp", 6), ("C2", 12), ("big72", 3), ("big112", 3)])
 def test_tpa_preconditioner_and_residual_match_oracle(ks, name, nb):
     import torch
 
