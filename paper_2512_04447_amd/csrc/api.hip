@@ -99,6 +99,13 @@ static int upload_vec(const std::vector<T>& h, T** out) {
   return 0;
 }
 
+// Largest work item of the tiled projection (entries of one atom in one
+// tile): items of up to 96 entries give the 16 waves of a block even shares
+// (whole (tile, atom) pairs left three of them idle and the busiest with
+// 2.3 times the mean on the 216-atom cell), at the price of more partial
+// rows to reduce.
+constexpr int kPairChunk = 96;
+
 template <typename T>
 static int upload_proj(ks_plan* p, const ks_projset* ps) {
   const int na = ps->n_atoms;
@@ -239,15 +246,22 @@ static int upload_proj(ks_plan* p, const ks_projset* ps) {
         std::vector<std::pair<uint16_t, int32_t>> pts;
         for (; j < tcount[k + 1] && atom_of_supp[slot[j]] == a; ++j) pts.push_back({local_of[slot[j]], slot[j]});
         std::sort(pts.begin(), pts.end());
-        for (const auto& pt : pts) {
-          ent_t.push_back(pt.first);
-          const int32_t s2 = pt.second - sp[a];
-          for (int jp = 0; jp < npa; ++jp) ent_beta.push_back((T)ps->beta[bp[a] + (int64_t)jp * ns + s2]);
+        // a pair is one wave's work item: an atom covering much of the tile
+        // is cut into items of at most kPairChunk entries (each with its
+        // own partial rows, reduced in order with the rest), so that the
+        // waves of a block get even shares
+        for (size_t c0 = 0; c0 < pts.size(); c0 += kPairChunk) {
+          const size_t c1 = std::min(pts.size(), c0 + (size_t)kPairChunk);
+          for (size_t e = c0; e < c1; ++e) {
+            ent_t.push_back(pts[e].first);
+            const int32_t s2 = pts[e].second - sp[a];
+            for (int jp = 0; jp < npa; ++jp) ent_beta.push_back((T)ps->beta[bp[a] + (int64_t)jp * ns + s2]);
+          }
+          pair_atom.push_back(a);
+          pair_ent_ptr.push_back((int32_t)ent_t.size());
+          pair_boff.push_back((int32_t)ent_beta.size());
+          pair_row.push_back(pair_row.back() + npa);
         }
-        pair_atom.push_back(a);
-        pair_ent_ptr.push_back((int32_t)ent_t.size());
-        pair_boff.push_back((int32_t)ent_beta.size());
-        pair_row.push_back(pair_row.back() + npa);
         i = j;
       }
       tile_pair_ptr[k + 1] = (int32_t)pair_atom.size();
@@ -744,9 +758,11 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   if ((rc = block_orthonormalise<T>(p, w, st->W, st->Xn, ld, nb, nullptr, 0.0, st->status + KS_ST_DEAD_W, s)))
     return rc;
   std::swap(st->W, st->Xn);
-  // 3. AW = H W
+  // 3. AW = H W; soft-locked bands (res <= lock_tol) have exactly zero W
+  // columns (masked in step 1, kept zero by the projection and dropped by
+  // the deflating Cholesky-QR), so their transforms are skipped
   if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->W), ld, static_cast<T2*>(st->AW), ld,
-                       nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))
+                       nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s, st->res, o->lock_tol)))
     return rc;
   // 4. P, AP masked and orthonormalised
   if (st->has_p) {
@@ -754,8 +770,9 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
                                       s)))
       return rc;
     std::swap(st->P, st->Pn);
+    // the same mask zeroed the locked P columns
     if ((rc = apply_h<T>(p, static_cast<const T*>(v), static_cast<const T2*>(st->P), ld, static_cast<T2*>(st->AP), ld,
-                         nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s)))
+                         nb, static_cast<T2*>(st->T1), static_cast<T2*>(w.dc), s, st->res, o->lock_tol)))
       return rc;
   }
   // 5. subspace matrices
@@ -960,6 +977,8 @@ static int plan_create(ks_plan** out, const ks_grid* grid, const double* kvec, c
     p->fft.kvec[a] = kvec ? kvec[a] : 0.0;
     p->Ng *= grid->n[a];
   }
+  p->fft.skip_res = nullptr;
+  p->fft.skip_tol = 0.0;
   // the projector set is checked before any device work
   if (proj && proj->n_proj > 0) {
     const char* why = nullptr;

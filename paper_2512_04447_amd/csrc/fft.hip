@@ -321,6 +321,12 @@ __device__ __forceinline__ void fft_ct(T2* s, const T2* __restrict__ tw) {
 
 __device__ inline int wrap_m(int k, int n) { return (2 * k < n) ? k : k - n; }
 
+// A soft-locked band of an H-apply on the W or P block (its column is exactly
+// zero): the passes skip its transforms and write zeros.
+__device__ inline bool band_skipped(const Fft3& f, int band) {
+  return f.skip_res != nullptr && f.skip_res[band] <= f.skip_tol;
+}
+
 // ---------------------------------------------------------------- pass A
 // MODE 0: load psi.  MODE 1: load r = ax - theta x and write per-plane
 // partial sums of |r|^2 to partial[band*n0 + x].
@@ -351,6 +357,11 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * ld + off;
   constexpr int BATCH = load_batch<T, NT>();
+  if (MODE == 0 && band_skipped(f, band)) {
+    T2* out = dst + band * ldd + off;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = cmake<T2>(T(0), T(0));
+    return;
+  }
   // twiddle tables of the two axes, staged in LDS after the plane
   T2* st1 = s + lpad_size(plane);
   T2* st2 = st1 + n1;
@@ -438,6 +449,7 @@ k_pass_b(Fft3 f, c2<T>* __restrict__ buf, int64_t ld, int zc, const c2<T>* __res
   const int y = bid % n1;
   const int band = bid / n1;
   const int z0 = zt * zc;
+  if (MODE == 0 && band_skipped(f, band)) return;  // the zero input stays zero
   T2* base = buf + band * ld + (int64_t)y * n2 + z0;
   const int64_t xs = (int64_t)n1 * n2;
   const int tile = (CN > 0 ? CN : n0) * zc;
@@ -514,6 +526,11 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * lds_ + off;
   constexpr int BATCH = load_batch<T, NT>();
+  if (MODE == 0 && band_skipped(f, band)) {
+    T2* out = dst + band * ldd + off;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = cmake<T2>(T(0), T(0));
+    return;
+  }
   T2* st1 = s + lpad_size(plane);  // twiddle tables staged in LDS after the plane
   T2* st2 = st1 + n1;
   for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
@@ -591,6 +608,11 @@ k_rows(Fft3 f, int ry, const c2<T>* __restrict__ src, const c2<T>* __restrict__ 
   const int band = bid / n0;
   const int tile = ry * n2;
   const int64_t off = (int64_t)x * n1 * n2 + (int64_t)rc * ry * n2;
+  if ((MODE == 0 || MODE == 2) && band_skipped(f, band)) {
+    T2* out = dst + band * ldd + off;
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) out[i] = cmake<T2>(T(0), T(0));
+    return;
+  }
   T2* st2 = s + tile;
   for (int i = threadIdx.x; i < n2; i += blockDim.x) st2[i] = tw2[i];
   const T2* in = src + band * ld + off;
@@ -681,6 +703,7 @@ k_cols(Fft3 f, int zc2, c2<T>* __restrict__ buf, int64_t ld, const c2<T>* __rest
   const int band = bid / n0;
   T2* base = buf + band * ld + (int64_t)x * n1 * n2 + zt * zc2;
   const int tile = n1 * zc2;
+  if (band_skipped(f, band)) return;  // zeros stay zeros (forward or inverse)
   T2* st1 = s + tile;
   for (int i = threadIdx.x; i < n1; i += blockDim.x) st1[i] = tw1[i];
   constexpr int BATCH = 8;
@@ -709,7 +732,9 @@ k_cols(Fft3 f, int zc2, c2<T>* __restrict__ buf, int64_t ld, const c2<T>* __rest
 // Projection with every orbital value read once.  Block (tile k, slice of
 // band tiles) keeps the tile's (tile, atom) pairs in LDS: each pair lists
 // the atom's support points inside the tile (tile-local point, then the np
-// values of the atom's projectors there), loaded once for all band tiles of
+// values of the atom's projectors there; an atom with many points in the
+// tile is cut into several pairs of a bounded size, so that waves get even
+// shares), loaded once for all band tiles of
 // the slice (in batches of whole pairs if they do not fit).  For each band
 // tile of NBS bands the orbital values of the tile's points are staged in
 // LDS (z-runs of the box, coalesced), the next band tile's values loaded
@@ -719,8 +744,8 @@ k_cols(Fft3 f, int zc2, c2<T>* __restrict__ buf, int64_t ld, const c2<T>* __rest
 // nine projectors per atom; a fixed order), the groups are combined by a
 // fixed shuffle tree, and the pair's partial coefficients part[row + j][band]
 // (j < np) are written.  The partials of a projector are summed over its
-// tiles by k_nl_reduce (tiles ascending): the result does not depend on
-// scheduling.
+// pairs by k_nl_reduce (tiles ascending, pieces of a pair in order): the
+// result does not depend on scheduling.
 constexpr int kProjThreads = 1024;
 template <typename T, int NBS, int MAXP, int PV>
 __global__ void __launch_bounds__(kProjThreads)
@@ -1322,13 +1347,18 @@ static int nl_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const 
 
 template <typename T>
 int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* hpsi, int64_t ldh, int nb,
-            c2<T>* tmp, c2<T>* dc, hipStream_t s) {
+            c2<T>* tmp, c2<T>* dc, hipStream_t s, const double* skip_res, double skip_tol) {
   int rc;
   const int64_t ldt = p.Ng;
+  // the FFT passes see the skip mask through a copy of the plan's transform
+  // description; the NL kernels run on every band (zero columns give zero)
+  ks_plan q = p;
+  q.fft.skip_res = skip_res;
+  q.fft.skip_tol = skip_tol;
   if (p.nproj > 0 && (rc = nl_project<T>(p, psi, ldp, nb, dc, s))) return rc;
-  if ((rc = pass_a<T>(p, 0, psi, nullptr, nullptr, ldp, tmp, ldt, nb, nullptr, s))) return rc;
-  if ((rc = pass_b<T>(p, 0, tmp, ldt, nb, nullptr, nullptr, s))) return rc;
-  if ((rc = pass_c<T>(p, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s))) return rc;
+  if ((rc = pass_a<T>(q, 0, psi, nullptr, nullptr, ldp, tmp, ldt, nb, nullptr, s))) return rc;
+  if ((rc = pass_b<T>(q, 0, tmp, ldt, nb, nullptr, nullptr, s))) return rc;
+  if ((rc = pass_c<T>(q, 0, tmp, ldt, hpsi, ldh, nb, v, psi, ldp, dc, nullptr, 0.0, s))) return rc;
   if (p.nproj > 0 && (rc = nl_scatter<T>(p, hpsi, ldh, nb, dc, s))) return rc;
   return 0;
 }
@@ -1398,9 +1428,9 @@ size_t precond_work_bytes(const ks_plan& p, int nb) {
 }
 
 template int apply_h<double>(const ks_plan&, const double*, const double2*, int64_t, double2*, int64_t, int,
-                             double2*, double2*, hipStream_t);
+                             double2*, double2*, hipStream_t, const double*, double);
 template int apply_h<float>(const ks_plan&, const float*, const float2*, int64_t, float2*, int64_t, int,
-                            float2*, float2*, hipStream_t);
+                            float2*, float2*, hipStream_t, const double*, double);
 template int kinetic_energy<double>(const ks_plan&, const double2*, int64_t, int, double2*, double*, double*,
                                     hipStream_t);
 template int kinetic_energy<float>(const ks_plan&, const float2*, int64_t, int, float2*, double*, double*,

@@ -26,6 +26,11 @@ struct Fft3 {
   AxisPlan ax[3];
   double twopi_over_L[3];
   double kvec[3];  // Bloch vector (Cartesian, 1/bohr): kinetic |G + k|^2 / 2
+  // H-applies of the LOBPCG W and P blocks: bands with skip_res[band] <=
+  // skip_tol (soft-locked, so their columns are exactly zero) skip the FFT
+  // passes and write zero output; null for every other transform
+  const double* skip_res;
+  double skip_tol;
 };
 
 }  // namespace ks
@@ -97,9 +102,12 @@ struct ks_plan {
 namespace ks {
 
 // ---- H-apply and preconditioner (fft.hip) ----
+// With skip_res, bands whose skip_res[b] <= skip_tol have exactly zero
+// columns (soft-locked W and P): their FFT passes are skipped and their
+// output is written as zero.
 template <typename T>
 int apply_h(const ks_plan& p, const T* v, const c2<T>* psi, int64_t ldp, c2<T>* hpsi, int64_t ldh,
-            int nb, c2<T>* tmp, c2<T>* dc, hipStream_t s);
+            int nb, c2<T>* tmp, c2<T>* dc, hipStream_t s, const double* skip_res = nullptr, double skip_tol = 0.0);
 
 // E[b] = <x_b|T|x_b> for nb columns of X (uses tmp as scratch and
 // `partial` of nb*n0*n1 doubles).

@@ -247,6 +247,46 @@ def test_single_lobpcg_step_matches_oracle(ks, name):
     assert _subspace_gap(Xg, ref.X) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["C1", "tiny10_sp"])
+def test_soft_locked_step_matches_oracle_and_skips_locked_columns(ks, name):
+    """A step with lock_tol between two residuals: the oracle zeroes the
+    locked bands' W and P columns; the GPU does the same and skips their FFT
+    passes in the W and P H-applies (writing zeros).  Ritz values and the
+    subspace as in the unlocked step's test, and the locked columns of W, AW,
+    P and AP exactly zero."""
+    from paper_2512_04447_amd import binding as b
+
+    cfg = CELLS[name]()
+    cell = ki.make_cell(cfg)
+    _say("soft-locked step", name)
+    oc = oh.oracle_cell(cfg, cell.D)
+    pc = olob.tpa_preconditioner(oc)
+    st = olob.initial_state(oc, ki.make_x0(cfg))
+    for _ in range(4):
+        st = olob.step(oc, st, pc)
+    _, res = olob.residual(st)
+    rs = np.sort(res)
+    lock = float(0.5 * (rs[cfg.nb // 2] + rs[cfg.nb // 2 + 1]))
+    locked = res <= lock
+    assert 0 < locked.sum() < cfg.nb
+    ref = olob.step(oc, st, pc, lock_tol=lock)
+    plan = make_plan(ks, cell, cfg.nb)
+    lob = b.Lobpcg(plan, to_dev(cell.V), to_dev(st.X))
+    _gpu_state_from_oracle(lob, st)
+    lob.step(b.KS_PRECOND_TPA, lock)
+    assert np.array_equal(lob.res_host <= lock, locked)
+    th = lob.theta.cpu().numpy()
+    assert np.abs(th - ref.theta).max() <= 1e-12 * max(1.0, np.abs(ref.theta).max())
+    Xg = lob.X.cpu().numpy()
+    assert _subspace_gap(Xg, ref.X) <= 1e-10
+    # this step's W, AW, AP (P was rotated into the next step's P, so the
+    # locked columns of the masked P are seen through AP)
+    for k in ("W", "AW", "AP"):
+        blk = lob.block(k).cpu().numpy()
+        assert np.all(blk[locked] == 0), k
+        assert np.all(np.abs(blk[~locked]).max(axis=1) > 0), k
+
+
 def test_lobpcg_c1_converges_to_oracle_eigenvalues(ks):
     from paper_2512_04447_amd import binding as b
 
