@@ -31,17 +31,22 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;  // output tile edge per workgroup
-constexpr int KC = 16;    // K chunk staged in LDS (rotation)
+constexpr int KC = 16;    // K chunk staged in LDS (small GEMMs)
 constexpr int PAD = KC + 1;
+constexpr int ROT_KC = 16;  // K chunk of the rotation
 // K chunk of the Gram: 16 (FP64) or 32 (FP32) points, so that one chunk of
 // the three operand panels stays near 52 KB of LDS either way.
 template <typename T> constexpr int gram_kc() { return sizeof(T) == 4 ? 32 : 16; }
 
 // Column c of a three-segment block list (segments of nb columns each).
+// Two compares and selects between the three base pointers: a division and
+// an indexed read of the pointer array cost a dependent load from the
+// argument segment on every call.
 template <typename T2>
 __device__ inline const T2* seg_col(const BlockList<T2>& b, int c) {
-  const int s = c / b.nb;
-  return b.p[s] + (int64_t)(c - s * b.nb) * b.ld;
+  const int s = (c >= b.nb ? 1 : 0) + (c >= 2 * b.nb ? 1 : 0);
+  const T2* base = s == 0 ? b.p[0] : (s == 1 ? b.p[1] : b.p[2]);
+  return base + (int64_t)(c - s * b.nb) * b.ld;
 }
 
 // ---------------------------------------------------------------- Gram
@@ -55,20 +60,25 @@ template <typename T2> __device__ __forceinline__ T2 keep_if(bool c, T2 v) {
 // For upper tile (ti, tj) and K split `sp`: S_tile = A_I^H B1_J and, when
 // TWO, H_tile = A_I^H B2_J.  Partials (FP64) go to part[(sp*ntu + t)*4096 +
 // i*64 + j] (row-major within the tile).
-// Loads of one K chunk into registers (EPT points of one column per
-// operand).  Plain functions rather than lambdas: arrays captured by
-// reference in a lambda were kept in private memory.
+// Loads of one K chunk into registers: point kb + lk of the EPT columns
+// qa[q], qb[q], qb2[q] of each operand.  Plain functions rather than
+// lambdas: arrays captured by reference in a lambda were kept in private
+// memory.  The loads are unconditional, from valid columns at a point
+// clamped to k1 - 1 (k1 > kb).  Nothing is zeroed here (a select on the
+// loaded value would wait for the load at once): the caller zeroes the A
+// values of a point past k1 when it stores them to LDS, and the values of
+// a clamped column only reach Gram entries that are not stored.
 template <bool TWO, int EPT, typename T2>
-__device__ __forceinline__ void gram_fetch(T2 (&ra)[EPT], T2 (&rb)[EPT], T2 (&rb2)[TWO ? EPT : 1], const T2* pa,
-                                           const T2* pb, const T2* pb2, int64_t kb, int lk, int64_t k1) {
-  const T2 z = cmake<T2>(decltype(z.x)(0), decltype(z.x)(0));
+__device__ __forceinline__ void gram_fetch(T2 (&ra)[EPT], T2 (&rb)[EPT], T2 (&rb2)[TWO ? EPT : 1],
+                                           const T2* const (&qa)[EPT], const T2* const (&qb)[EPT],
+                                           const T2* const (&qb2)[EPT], int64_t kb, int lk, int64_t k1) {
+  const int64_t k = kb + lk;
+  const int64_t e = k < k1 ? k : k1 - 1;
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int64_t k = kb + lk + q;
-    const bool ok = k < k1;
-    ra[q] = (pa && ok) ? pa[k] : z;
-    rb[q] = (pb && ok) ? pb[k] : z;
-    if constexpr (TWO) rb2[q] = (pb2 && ok) ? pb2[k] : z;
+    ra[q] = gload(qa[q] + e);
+    rb[q] = gload(qb[q] + e);
+    if constexpr (TWO) rb2[q] = gload(qb2[q] + e);
   }
 }
 
@@ -113,8 +123,7 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   constexpr int GPAD = GKC + 1;
   constexpr int WJ = gram_wj<T>();
   constexpr int WN = TILE / WJ / 16;          // 16-column MFMA tiles per wave
-  constexpr int LPC = gram_threads<T>() / TILE;  // loader threads per column
-  constexpr int EPT = GKC / LPC;            // K points per loader thread and operand
+  constexpr int EPT = TILE * GKC / gram_threads<T>();  // columns per loader thread and operand
   __shared__ T2 As[TILE][GPAD];
   __shared__ T2 Bs[TILE][GPAD];
   __shared__ T2 B2s[TWO ? TILE : 1][GPAD];
@@ -141,16 +150,25 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
     for (int b = 0; b < WN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = hr[a][b][v] = hi[a][b][v] = T(0);
-  // loader: thread -> (column, EPT consecutive k)
-  const int lc = threadIdx.x / LPC;
-  const int lk = (threadIdx.x % LPC) * EPT;
-  const int ca = ti * TILE + lc;
-  const int cb = tj * TILE + lc;
-  const T2* pa = ca < m ? seg_col(A, ca) : nullptr;
-  const T2* pb = cb < m ? seg_col(B1, cb) : nullptr;
-  const T2* pb2 = (TWO && cb < m) ? seg_col(B2, cb) : nullptr;
+  // loader: thread -> point lk of the chunk in the columns lc + CST q
+  // (q < EPT): lanes run along the points of a column, so the loads are
+  // coalesced and the LDS stores free of bank conflicts
+  constexpr int CST = gram_threads<T>() / GKC;
+  static_assert(CST * EPT == TILE, "loader columns cover the tile");
+  const int lk = threadIdx.x % GKC;
+  const int lc = threadIdx.x / GKC;
   const T2 z = cmake<T2>(T(0), T(0));
   const T2* pb0 = seg_col(A, 0);  // a valid column for loads that are discarded
+  const T2* qa[EPT];
+  const T2* qb[EPT];
+  const T2* qb2[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int ca = ti * TILE + lc + CST * q, cb = tj * TILE + lc + CST * q;
+    qa[q] = ca < m ? seg_col(A, ca) : pb0;
+    qb[q] = cb < m ? seg_col(B1, cb) : pb0;
+    qb2[q] = (TWO && cb < m) ? seg_col(B2, cb) : pb0;
+  }
   // FP32 products accumulate in FP32 over KFLUSH points, then in FP64.
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int KFLUSH = 256;
@@ -171,57 +189,33 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   constexpr int NR = PREFETCH ? EPT : 1;
   T2 ra[NR], rb[NR], rb2[TWO ? NR : 1];
   if constexpr (PREFETCH) {
-    if (k0 < k1) gram_fetch<TWO>(ra, rb, rb2, pa, pb, pb2, k0, lk, k1);
+    if (k0 < k1) gram_fetch<TWO>(ra, rb, rb2, qa, qb, qb2, k0, lk, k1);
   }
   for (int64_t kb = k0; kb < k1; kb += GKC) {
     if constexpr (PREFETCH) {
+      const bool ok = kb + lk < k1;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
-        As[lc][lk + q] = ra[q];
-        Bs[lc][lk + q] = rb[q];
-        if (TWO) B2s[lc][lk + q] = rb2[q];
+        As[lc + CST * q][lk] = keep_if(ok, ra[q]);
+        Bs[lc + CST * q][lk] = rb[q];
+        if (TWO) B2s[lc + CST * q][lk] = rb2[q];
       }
     } else {
-      // FP64: all loads of the chunk issued before the first is used.
-      // Unconditional loads from valid addresses (column 0 for a column past
-      // m, point k1 - 1 past k1) into named values, the zero selected on the
-      // value: a select between addresses, a guarded load or an array the
-      // compiler keeps in scratch each made the loads go one group at a time.
-      static_assert(EPT == 4, "FP64 chunk loads are written for 4 points per thread");
-      const T2* qa = pa ? pa : pb0;
-      const T2* qb = pb ? pb : pb0;
-      const T2* qb2 = pb2 ? pb2 : pb0;
-      const int64_t kq = kb + lk;
-      const int64_t e0 = min(kq, k1 - 1), e1 = min(kq + 1, k1 - 1), e2 = min(kq + 2, k1 - 1), e3 = min(kq + 3, k1 - 1);
-      const T2 a0 = qa[e0], a1 = qa[e1], a2 = qa[e2], a3 = qa[e3];
-      const T2 b0 = qb[e0], b1 = qb[e1], b2 = qb[e2], b3 = qb[e3];
-      T2 c0 = z, c1 = z, c2 = z, c3 = z;
-      if constexpr (TWO) {
-        c0 = qb2[e0];
-        c1 = qb2[e1];
-        c2 = qb2[e2];
-        c3 = qb2[e3];
-      }
-      const bool va = pa != nullptr, vb = pb != nullptr;
-      const bool o0 = kq < k1, o1 = kq + 1 < k1, o2 = kq + 2 < k1, o3 = kq + 3 < k1;
-      As[lc][lk + 0] = keep_if(va && o0, a0);
-      As[lc][lk + 1] = keep_if(va && o1, a1);
-      As[lc][lk + 2] = keep_if(va && o2, a2);
-      As[lc][lk + 3] = keep_if(va && o3, a3);
-      Bs[lc][lk + 0] = keep_if(vb && o0, b0);
-      Bs[lc][lk + 1] = keep_if(vb && o1, b1);
-      Bs[lc][lk + 2] = keep_if(vb && o2, b2);
-      Bs[lc][lk + 3] = keep_if(vb && o3, b3);
-      if constexpr (TWO) {
-        B2s[lc][lk + 0] = keep_if(vb && o0, c0);
-        B2s[lc][lk + 1] = keep_if(vb && o1, c1);
-        B2s[lc][lk + 2] = keep_if(vb && o2, c2);
-        B2s[lc][lk + 3] = keep_if(vb && o3, c3);
+      // FP64: all loads of the chunk issued before the first is used, then
+      // stored; the A values of a point past k1 zeroed
+      T2 la[EPT], lb[EPT], lb2[TWO ? EPT : 1];
+      gram_fetch<TWO>(la, lb, lb2, qa, qb, qb2, kb, lk, k1);
+      const bool ok = kb + lk < k1;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        As[lc + CST * q][lk] = keep_if(ok, la[q]);
+        Bs[lc + CST * q][lk] = lb[q];
+        if (TWO) B2s[lc + CST * q][lk] = lb2[q];
       }
     }
     __syncthreads();
     if constexpr (PREFETCH) {
-      if (kb + GKC < k1) gram_fetch<TWO>(ra, rb, rb2, pa, pb, pb2, kb + GKC, lk, k1);
+      if (kb + GKC < k1) gram_fetch<TWO>(ra, rb, rb2, qa, qb, qb2, kb + GKC, lk, k1);
     }
     if constexpr (F32) {
       if (kb > k0 && ((kb - k0) % KFLUSH) == 0) gram_flush<TWO>(sr, si, hr, hi, dsr, dsi, dhr, dhi);
@@ -445,22 +439,38 @@ template int gram_general<float>(const BlockList<float2>&, const BlockList<float
 // columns [0, pstart) are added and the total stored to Y.
 // With upper (C upper triangular: C[i][band] = 0 for i > band, as for the
 // Cholesky-QR coefficients D L^-H) a band tile [b0, b0 + 64) stops at
-// column b0 + 64 of V: the skipped terms are exact zeros, the result the
-// same.  With Yadd (no Yp), Y = Yadd + V C: each element of Yadd is read by
-// the thread that writes the same element of Y, so Yadd may be Y.
-template <typename T>
-__global__ void __launch_bounds__(256)
+// column b0 + 64 of V, and each 16-band MFMA sub-tile stops issuing at its
+// own last band: the skipped terms are exact zeros, the result the same.
+// With Yadd (no Yp), Y = Yadd + V C: each element of Yadd is read by the
+// thread that writes the same element of Y, so Yadd may be Y.
+//
+// A workgroup takes `rtiles` consecutive 64-point row tiles of one band
+// tile.  Its chunk loads run one chunk ahead across the tiles (and the two
+// sums of Yp), so the load latency at the start of a tile and the stores at
+// its end overlap the products of the neighbouring chunks.
+template <typename T, int RKC>
+__global__ void __launch_bounds__(256, 3)
 k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int ldc, int ncol, int64_t Ng,
-         c2<T>* Y, c2<T>* __restrict__ Yp, int64_t ldy, int upper, const c2<T>* Yadd) {
+         c2<T>* Y, c2<T>* __restrict__ Yp, int64_t ldy, int upper, const c2<T>* Yadd, int rtiles) {
   using T2 = c2<T>;
   using M = Mfma<T>;
-  __shared__ T2 Vs[KC][TILE + 1];  // [i][r]
-  __shared__ T2 Cs[TILE][PAD];     // [band][i]
-  const int64_t r0 = (int64_t)blockIdx.x * TILE;
+  constexpr int EP = RKC / 4;       // V and C values per loader thread
+  __shared__ T2 Vs[RKC][TILE + 1];  // [i][r]
+  __shared__ T2 Cs[TILE][RKC + 1];  // [band][i]
+  const int64_t ntr = (Ng + TILE - 1) / TILE;
+  const int64_t t_first = (int64_t)blockIdx.x * rtiles;
+  const int nt = (int)min((int64_t)rtiles, ntr - t_first);
   const int b0 = blockIdx.y * TILE;
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
   const int wb = wave >> 1, wr = wave & 1;  // wave's band half, row half
   const bool wact = b0 + wb * 32 < ncol;
+  // sums: 0 = [pstart, m) into Yp then 1 = [0, pstart) into Y when Yp is
+  // given; else one sum over [0, m) (or [0, b0 + 64) when upper)
+  const int npass = Yp ? 2 : 1;
+  auto lo_of = [&](int p) { return (Yp && p == 0) ? pstart : 0; };
+  auto hi_of = [&](int p) { return Yp ? (p == 0 ? m : pstart) : (upper ? min(m, b0 + TILE) : m); };
+  // last chunk start (exclusive bound) of each 16-band sub-tile u under upper
+  const int ulim0 = upper ? b0 + wb * 32 + 16 : m, ulim1 = upper ? b0 + wb * 32 + 32 : m;
   typename M::acc dr[2][2], di[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -468,102 +478,138 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) dr[a][b][v] = di[a][b][v] = T(0);
-  const T2 z = cmake<T2>(T(0), T(0));
-  // loaders
-  const int vi = threadIdx.x >> 4, vr = (threadIdx.x & 15) * 4;  // V: column vi, rows vr..vr+3
-  const int cb = threadIdx.x >> 2, ci = (threadIdx.x & 3) * 4;   // C: band cb, i ci..ci+3
-  const int npass = Yp ? 2 : 1;
-  // register stage of the next chunk (its loads overlap this chunk's MFMAs);
-  // eight named values rather than arrays, which stay in registers
-  T2 v0, v1, v2, v3, q0, q1, q2, q3;
-  const int band_l = b0 + cb;
-  const bool band_ok = band_l < ncol;
-  const int64_t rr = r0 + vr;
-#define KS_ROT_FETCH(C0)                                                                    \
-  do {                                                                                      \
-    const int c_ = (C0) + vi;                                                               \
-    const T2* col_ = (c_ < hi) ? seg_col(V, c_) : nullptr;                                  \
-    v0 = (col_ && rr + 0 < Ng) ? col_[rr + 0] : z;                                          \
-    v1 = (col_ && rr + 1 < Ng) ? col_[rr + 1] : z;                                          \
-    v2 = (col_ && rr + 2 < Ng) ? col_[rr + 2] : z;                                          \
-    v3 = (col_ && rr + 3 < Ng) ? col_[rr + 3] : z;                                          \
-    const int i_ = (C0) + ci;                                                               \
-    const T2* cc_ = C + (int64_t)band_l * ldc;                                              \
-    q0 = (band_ok && i_ + 0 < hi) ? cc_[i_ + 0] : z;                                        \
-    q1 = (band_ok && i_ + 1 < hi) ? cc_[i_ + 1] : z;                                        \
-    q2 = (band_ok && i_ + 2 < hi) ? cc_[i_ + 2] : z;                                        \
-    q3 = (band_ok && i_ + 3 < hi) ? cc_[i_ + 3] : z;                                        \
-  } while (0)
-  for (int pass = 0; pass < npass; ++pass) {
-    const int lo = (Yp && pass == 0) ? pstart : 0;
-    const int hi = (Yp && pass == 0) ? m : (Yp ? pstart : (upper ? min(m, b0 + TILE) : m));
-    if (lo < hi) KS_ROT_FETCH(lo);
-    for (int c0 = lo; c0 < hi; c0 += KC) {
-      Vs[vi][vr + 0] = v0;
-      Vs[vi][vr + 1] = v1;
-      Vs[vi][vr + 2] = v2;
-      Vs[vi][vr + 3] = v3;
-      Cs[cb][ci + 0] = q0;
-      Cs[cb][ci + 1] = q1;
-      Cs[cb][ci + 2] = q2;
-      Cs[cb][ci + 3] = q3;
-      __syncthreads();
-      if (c0 + KC < hi) KS_ROT_FETCH(c0 + KC);
-      // a wave whose 32 bands all lie past ncol issues no MFMA (padding)
-      if (wact)
+  // loaders, lanes along the contiguous index of each operand (coalesced
+  // loads, LDS stores without bank conflicts): V row vr of the columns
+  // vi + 4 e; C coefficient ci of the bands cb + (256 / RKC) e, e < EP
+  const int vr = threadIdx.x % TILE, vi = threadIdx.x / TILE;
+  const int ci = threadIdx.x % RKC, cb = threadIdx.x / RKC;
+  constexpr int CBS = 256 / RKC;  // band stride between a thread's coefficients
+  // register stage of the next chunk (its loads overlap this chunk's MFMAs)
+  T2 vv[EP], qq[EP];
+  // Unconditional global loads from indices clamped into range (column 0,
+  // row Ng - 1, band 0, coefficient hi - 1); a guarded load through a
+  // pointer selected against null became a flat load, whose wait also held
+  // up the LDS reads of the current chunk.  Only the coefficients past hi
+  // are zeroed, when they are stored to LDS (not at the load, which would
+  // wait for it there): a clamped V column then meets a zero coefficient,
+  // and clamped rows or bands only reach outputs that are not stored.
+  const T2* ccol[EP];
 #pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        T2 a[2], b[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          a[u] = Cs[wb * 32 + u * 16 + (lane & 15)][kr];  // A = C^T: [band][i]
-          b[u] = Vs[kr][wr * 32 + u * 16 + (lane & 15)];  // B = V^T: [i][r]
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int w = 0; w < 2; ++w) {
-            // c * v: re = cr vr - ci vi, im = cr vi + ci vr
-            dr[u][w] = M::run(a[u].x, b[w].x, dr[u][w]);
-            dr[u][w] = M::run(-a[u].y, b[w].y, dr[u][w]);
-            di[u][w] = M::run(a[u].x, b[w].y, di[u][w]);
-            di[u][w] = M::run(a[u].y, b[w].x, di[u][w]);
-          }
+  for (int e = 0; e < EP; ++e) {
+    const int band = b0 + cb + CBS * e;
+    ccol[e] = C + (int64_t)(band < ncol ? band : 0) * ldc;
+  }
+  const int64_t rl = Ng - 1;
+  // fetch cursor (tile ft, sum fp, chunk fc): always the chunk after the
+  // one being multiplied, in the same order as the loops below
+  int ft = 0, fp = 0, fc = lo_of(0);
+  auto settle = [&]() {
+    while (ft < nt && fc >= hi_of(fp)) {
+      if (++fp == npass) {
+        fp = 0;
+        ++ft;
       }
-      __syncthreads();
+      fc = lo_of(fp);
     }
-    T2* out = (Yp && pass == 0) ? Yp : Y;
+  };
+  auto fetch = [&]() {
+    const int hi = hi_of(fp);
+    const int64_t r = min((t_first + ft) * TILE + vr, rl);
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int e = 0; e < EP; ++e) {
+      const int c_ = fc + vi + 4 * e;
+      vv[e] = gload(seg_col(V, c_ < hi ? c_ : 0) + r);
+    }
+    const int i_ = min(fc + ci, hi - 1);
 #pragma unroll
-      for (int w = 0; w < 2; ++w)
+    for (int e = 0; e < EP; ++e) qq[e] = gload(ccol[e] + i_);
+  };
+  settle();
+  if (ft < nt) fetch();
+  for (int t = 0; t < nt; ++t) {
+    const int64_t r0 = (t_first + t) * TILE;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int lo = lo_of(pass), hi = hi_of(pass);
+      for (int c0 = lo; c0 < hi; c0 += RKC) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int band = b0 + wb * 32 + u * 16 + M::row(lane, v);
-          const int64_t r = r0 + wr * 32 + w * 16 + (lane & 15);
-          if (band < ncol && r < Ng) {
-            T2 o = cmake<T2>(dr[u][w][v], di[u][w][v]);
-            if (Yadd != nullptr && out == Y) {
-              const T2 a = Yadd[(int64_t)band * ldy + r];
-              o = cmake<T2>(a.x + o.x, a.y + o.y);
+        for (int e = 0; e < EP; ++e) {
+          Vs[vi + 4 * e][vr] = vv[e];
+          Cs[cb + CBS * e][ci] = keep_if(c0 + ci < hi, qq[e]);
+        }
+        __syncthreads();
+        fc += RKC;
+        settle();
+        if (ft < nt) fetch();
+        // a wave whose 32 bands all lie past ncol issues no MFMA (padding)
+        const bool on0 = wact && c0 < ulim0, on1 = wact && c0 < ulim1;
+#pragma unroll
+        for (int kk = 0; kk < RKC; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          T2 a[2], b[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            a[u] = Cs[wb * 32 + u * 16 + (lane & 15)][kr];  // A = C^T: [band][i]
+            b[u] = Vs[kr][wr * 32 + u * 16 + (lane & 15)];  // B = V^T: [i][r]
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (!(u == 0 ? on0 : on1)) continue;
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+              // c * v: re = cr vr - ci vi, im = cr vi + ci vr
+              dr[u][w] = M::run(a[u].x, b[w].x, dr[u][w]);
+              dr[u][w] = M::run(-a[u].y, b[w].y, dr[u][w]);
+              di[u][w] = M::run(a[u].x, b[w].y, di[u][w]);
+              di[u][w] = M::run(a[u].y, b[w].x, di[u][w]);
             }
-            out[(int64_t)band * ldy + r] = o;
           }
         }
+        __syncthreads();
+      }
+      T2* out = (Yp && pass == 0) ? Yp : Y;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int band = b0 + wb * 32 + u * 16 + M::row(lane, v);
+            const int64_t r = r0 + wr * 32 + w * 16 + (lane & 15);
+            if (band < ncol && r < Ng) {
+              T2 o = cmake<T2>(dr[u][w][v], di[u][w][v]);
+              if (Yadd != nullptr && out == Y) {
+                const T2 a = Yadd[(int64_t)band * ldy + r];
+                o = cmake<T2>(a.x + o.x, a.y + o.y);
+              }
+              out[(int64_t)band * ldy + r] = o;
+            }
+          }
+      // a new tile starts from zero; Y of a tile with Yp adds the second
+      // sum to the first (the accumulators carry over between the sums)
+      if (pass == npass - 1) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dr[a][b][v] = di[a][b][v] = T(0);
+      }
+    }
   }
 }
-
-#undef KS_ROT_FETCH
 
 template <typename T>
 int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc, int ncol, int64_t Ng,
            c2<T>* Y, c2<T>* Yp, int64_t ldy, hipStream_t s, bool upper, const c2<T>* Yadd) {
   if (ncol <= 0) return 0;
-  dim3 grid((unsigned)ceil_div(Ng, TILE), (unsigned)ceil_div(ncol, TILE));
+  // row tiles per workgroup: up to 8 while the grid keeps about eight
+  // workgroups per resident slot (three per CU on 256 CUs)
+  const int64_t ntr = ceil_div(Ng, TILE), nbt = ceil_div(ncol, TILE);
+  const int rt = (int)std::max<int64_t>(1, std::min<int64_t>(8, ntr * nbt / (8 * 768)));
+  dim3 grid((unsigned)ceil_div(ntr, rt), (unsigned)nbt);
   TimerScope ts(KF_ROTATE, s);
-  hipLaunchKernelGGL((k_rotate<T>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy,
-                     (upper && Yp == nullptr) ? 1 : 0, Yp == nullptr ? Yadd : nullptr);
+  hipLaunchKernelGGL((k_rotate<T, ROT_KC>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy,
+                     (upper && Yp == nullptr) ? 1 : 0, Yp == nullptr ? Yadd : nullptr, rt);
   KS_LAUNCH_CHECK("rotate");
   return 0;
 }

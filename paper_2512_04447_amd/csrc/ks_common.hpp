@@ -67,6 +67,26 @@ template <typename T2> __device__ __host__ inline T2 cconj(T2 a) { a.y = -a.y; r
 template <typename T2, typename S> __device__ __host__ inline T2 cscale(T2 a, S s) { a.x *= s; a.y *= s; return a; }
 template <typename T2> __device__ __host__ inline decltype(T2{}.x) cabs2(T2 a) { return a.x * a.x + a.y * a.y; }
 
+// ------------------------------------------------------------------ loads
+// Load through a global (address space 1) pointer.  Where the compiler
+// cannot prove that a generic pointer is global (pointers read from a
+// struct, or selected against null) it emits flat loads, which count on
+// the LDS wait counter as well: every LDS read after them then waits for
+// the global load to return, and a register prefetch no longer overlaps
+// the arithmetic.  The pointer must address device global memory.
+// (Loaded as a clang vector type: the HIP vector structs have no copy from
+// an address-space-qualified object.)
+__device__ __forceinline__ double2 gload(const double2* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gload(const float2* p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return make_float2(v.x, v.y);
+}
+
 // ------------------------------------------------------------------ reductions
 constexpr int kWave = 64;
 
