@@ -976,8 +976,13 @@ k_nl_scatter(c2<T>* __restrict__ hpsi, int64_t ld, int nb, int64_t Ng, const int
   constexpr int ROW = NBS + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* sdc = reinterpret_cast<T2*>(smem_raw);
-  const int64_t k = blockIdx.x;
-  const int b0 = blockIdx.y * NBS;
+  // one-dimensional grid of point blocks x band groups, ordered so that the
+  // band groups of a point block run on one XCD in a row: its ELL slots and
+  // staged rows are then read from HBM once per XCD, not once per group
+  const int ngr = (nb + NBS - 1) / NBS;
+  const int64_t g = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t k = g / ngr;
+  const int b0 = (int)(g % ngr) * NBS;
   const int nbl = min(NBS, nb - b0);
   const int l0 = blk_ptr[k];
   const int nl = blk_ptr[k + 1] - l0;
@@ -1319,7 +1324,7 @@ static int nl_project(const ks_plan& p, const c2<T>* psi, int64_t ld, int nb, c2
 template <typename T, int NBS>
 static void launch_scatter(const ks_plan& p, c2<T>* hpsi, int64_t ldh, int nb, const c2<T>* dc, hipStream_t s) {
   const size_t lds = (size_t)p.maxl * (NBS + 1) * sizeof(c2<T>);
-  dim3 grid((unsigned)p.nblk, (unsigned)ceil_div(nb, NBS));
+  dim3 grid((unsigned)((int64_t)p.nblk * ceil_div(nb, NBS)));
   hipLaunchKernelGGL((k_nl_scatter<T, NBS>), grid, dim3(kScatterPts), lds, s, hpsi, ldh, nb, p.Ng, p.ell_ptr,
                      p.ell_lp, static_cast<const T*>(p.ell_beta), p.blk_ptr, p.blk_proj, dc);
 }

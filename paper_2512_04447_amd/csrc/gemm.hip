@@ -445,9 +445,10 @@ template int gram_general<float>(const BlockList<float2>&, const BlockList<float
 // thread that writes the same element of Y, so Yadd may be Y.
 //
 // A workgroup takes `rtiles` consecutive 64-point row tiles of one band
-// tile.  Its chunk loads run one chunk ahead across the tiles (and the two
-// sums of Yp), so the load latency at the start of a tile and the stores at
-// its end overlap the products of the neighbouring chunks.
+// tile (a one-dimensional grid of ceil(row tiles / rtiles) x band tiles).
+// Its chunk loads run one chunk ahead across the tiles (and the two sums
+// of Yp), so the load latency at the start of a tile and the stores at its
+// end overlap the products of the neighbouring chunks.
 template <typename T, int RKC>
 __global__ void __launch_bounds__(256, 3)
 k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int ldc, int ncol, int64_t Ng,
@@ -458,9 +459,14 @@ k_rotate(BlockList<c2<T>> V, int m, int pstart, const c2<T>* __restrict__ C, int
   __shared__ T2 Vs[RKC][TILE + 1];  // [i][r]
   __shared__ T2 Cs[TILE][RKC + 1];  // [band][i]
   const int64_t ntr = (Ng + TILE - 1) / TILE;
-  const int64_t t_first = (int64_t)blockIdx.x * rtiles;
+  // Workgroup order: the workgroups one XCD receives in a row take the band
+  // tiles of the same row tiles, which then read the same V chunks at about
+  // the same time, once from HBM for the whole XCD.
+  const int nbt = (ncol + TILE - 1) / TILE;
+  const int64_t g = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t t_first = (g / nbt) * rtiles;
   const int nt = (int)min((int64_t)rtiles, ntr - t_first);
-  const int b0 = blockIdx.y * TILE;
+  const int b0 = (int)(g % nbt) * TILE;
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
   const int wb = wave >> 1, wr = wave & 1;  // wave's band half, row half
   const bool wact = b0 + wb * 32 < ncol;
@@ -606,7 +612,7 @@ int rotate(const BlockList<c2<T>>& V, int m, int pstart, const c2<T>* C, int ldc
   // workgroups per resident slot (three per CU on 256 CUs)
   const int64_t ntr = ceil_div(Ng, TILE), nbt = ceil_div(ncol, TILE);
   const int rt = (int)std::max<int64_t>(1, std::min<int64_t>(8, ntr * nbt / (8 * 768)));
-  dim3 grid((unsigned)ceil_div(ntr, rt), (unsigned)nbt);
+  dim3 grid((unsigned)(ceil_div(ntr, rt) * nbt));
   TimerScope ts(KF_ROTATE, s);
   hipLaunchKernelGGL((k_rotate<T, ROT_KC>), grid, dim3(256), 0, s, V, m, pstart, C, ldc, ncol, Ng, Y, Yp, ldy,
                      (upper && Yp == nullptr) ? 1 : 0, Yp == nullptr ? Yadd : nullptr, rt);

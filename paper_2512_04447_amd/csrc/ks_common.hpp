@@ -87,6 +87,17 @@ __device__ __forceinline__ float2 gload(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
+// ------------------------------------------------------------------ launch order
+// The device deals consecutive workgroups of a launch to its eight XCDs in
+// turn, each XCD with its own L2.  xcd_order renumbers workgroup g of G so
+// that the workgroups one XCD receives form one contiguous range of the
+// new index (a bijection of [0, G)): workgroups that share input then run
+// on the same XCD at about the same time and meet it in its L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t g, int64_t G) {
+  const int64_t per = G / 8, rem = G % 8, x = g % 8;
+  return x * per + (x < rem ? x : rem) + g / 8;
+}
+
 // ------------------------------------------------------------------ reductions
 constexpr int kWave = 64;
 
