@@ -338,8 +338,12 @@ __device__ inline bool band_skipped(const Fft3& f, int band) {
 // stores that consume them (a guarded use draws its load into the guarded
 // block, one load in flight again): an index past the end rewrites the last
 // element with its own value.  Four for FP64 in 1024-thread blocks (128
-// registers per thread there).
-template <typename T, int NT> constexpr int load_batch() { return (sizeof(T) == 8 && NT > 256) ? 4 : 8; }
+// registers per thread there), or with a compile-time plane size the whole
+// plane at once (nine per thread for 96^2 points: one round trip to HBM per
+// plane instead of three); two loads per value (the residual form) keep four.
+template <typename T, int NT, int CN = 0> constexpr int load_batch() {
+  return (sizeof(T) == 8 && NT > 256) ? (CN > 0 ? (CN * CN + NT - 1) / NT : 4) : 8;
+}
 
 template <typename T, int MAXE, int MODE, int NT, int CN = 0>
 __global__ void __launch_bounds__(NT)
@@ -356,7 +360,7 @@ k_pass_a(Fft3 f, const c2<T>* __restrict__ src, const c2<T>* __restrict__ src2,
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * ld + off;
-  constexpr int BATCH = load_batch<T, NT>();
+  constexpr int BATCH = MODE == 1 ? load_batch<T, NT>() : load_batch<T, NT, CN>();
   if (MODE == 0 && band_skipped(f, band)) {
     T2* out = dst + band * ldd + off;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = cmake<T2>(T(0), T(0));
@@ -525,7 +529,7 @@ k_pass_c(Fft3 f, const c2<T>* __restrict__ src, int64_t lds_, c2<T>* __restrict_
   const int x = blockIdx.x - band * n0;
   const int64_t off = (int64_t)x * plane;
   const T2* in = src + band * lds_ + off;
-  constexpr int BATCH = load_batch<T, NT>();
+  constexpr int BATCH = load_batch<T, NT, CN>();
   if (MODE == 0 && band_skipped(f, band)) {
     T2* out = dst + band * ldd + off;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) out[i] = cmake<T2>(T(0), T(0));
