@@ -53,10 +53,10 @@ WORKLOADS = {
 # was measured on is unchanged (sha256 below).
 MEASURED_TRAFFIC = {
     # 216-atom cell, FP64, the basis Gram launch (Gram dispatch + its two
-    # ordered reductions): 582.19 GB fetched + 0.93 GB written
+    # ordered reductions): 685.01 GB fetched + 0.93 GB written
     # (profiles/hbm_traffic_fp64_c3.md)
-    ("C3", "fp64", "gram_basis"): (583127497733, "paper_2512_04447_amd/csrc/gemm.hip",
-                                   "b70fe4ba3038d49933f72ce014885313a947687eb357f7ca39f3feab727131ab"),
+    ("C3", "fp64", "gram_basis"): (685945912890, "paper_2512_04447_amd/csrc/gemm.hip",
+                                   "ab4c33b81f130faf45ee4b8c6de65b945313e9c8c4a83572323c90aadf97f948"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
@@ -105,12 +105,16 @@ def measured_traffic(cfg_name, precision, family):
     return value
 
 
-def family_work(cfg, es):
+def family_work(cfg, es, locked=0.0):
     """Algorithmic flops / bytes per LOBPCG step for each kernel family; es is
-    the bytes of one complex element of the blocks (16 FP64, 8 mixed)."""
+    the bytes of one complex element of the blocks (16 FP64, 8 mixed);
+    locked: soft-locked bands per step, whose columns of the W and P
+    H-applies the FFT passes skip (pass A and pass C write their zeros, pass
+    B moves nothing)."""
     Ng, nb = cfg.Ng, cfg.nb
     m = 3 * nb
     blk = Ng * nb * es
+    lk = 2 * locked * Ng * es  # the locked columns of the two skippable H-applies
     n_h = 3  # H-applies per step: W, P and the new X
     # mixed path: re-orthonormalisation of X (one more self-Gram and rotation)
     extra = 1 if es == 8 else 0
@@ -126,11 +130,11 @@ def family_work(cfg, es):
         # V[:, nb:] C[nb:] is the partial sum of the same pass, no extra work
         "rotate_flops": 8 * Ng * (nb * (nb + 1) / 2 * (2 + extra) + nb * nb + m * nb),
         # pass A: kinetic-energy FFT of X (R+W), residual (2R+W), H-applies (R+W)
-        "pass_a_bytes": blk * (2 + 3 + 2 * n_h),
+        "pass_a_bytes": blk * (2 + 3 + 2 * n_h) - lk,
         # pass B: kinetic reduction (R), TPA (R+W), kinetic (R+W) per H-apply
-        "pass_b_bytes": blk * (1 + 2 + 2 * n_h),
+        "pass_b_bytes": blk * (1 + 2 + 2 * n_h) - 2 * lk,
         # pass C: TPA (R+W), H (tmp R + psi R + W) per H-apply
-        "pass_c_bytes": blk * (2 + 3 * n_h),
+        "pass_c_bytes": blk * (2 + 3 * n_h) - 2 * lk,
         # nonlocal projection: every orbital value read once per H-apply
         "nl_project_bytes": blk * n_h,
         # nonlocal scatter: H psi read and written once per H-apply
@@ -188,14 +192,20 @@ def throughput(b, cfg, plan, v, x0, steps, warmup, mixed):
              "nl_scatter"]
     for f in range(len(names)):
         b.kernel_timer(True, f)
+    # soft-locked bands (residual at or below the lock tolerance when the
+    # step starts) skip the FFT passes of the W and P H-applies: counted so
+    # that the pass rates below charge only the bytes the passes moved
+    nlocked = 0
     for _ in range(steps):
         lob.step(b.KS_PRECOND_TPA, lock)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        nlocked += int((lob.res_host[: cfg.nb] <= lock).sum())
     fam = {}
     for f, nm in enumerate(names):
         ms, n = b.kernel_timer_read(f)
         b.kernel_timer(False, f)
         fam[nm] = (ms / steps, n / steps)
+    fam["locked_bands"] = nlocked / steps
     del lob
     torch.cuda.empty_cache()
     return wall, fam
@@ -206,7 +216,7 @@ def rates(cfg, fam, mixed, ms_per_step):
     kernel's roofline object, run-level GFLOP/s and the step's roofline
     fraction (the sum of every family's time at its peak over the measured
     step time)."""
-    w = family_work(cfg, 8 if mixed else 16)
+    w = family_work(cfg, 8 if mixed else 16, fam.get("locked_bands", 0.0))
     mma = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
     spec = {  # family: (work key, bound, peak, unit, scale to unit)
         "gram": ("gram_flops", "mfma", mma, "TFLOP/s", 1e12),
@@ -241,7 +251,8 @@ def rates(cfg, fam, mixed, ms_per_step):
     run = {"gflops": round(flops / 1e9 / (ms_per_step / 1e3), 1),
            "flops_per_step": flops,
            "roofline_ms_per_step": round(ideal_ms, 3),
-           "roofline_frac": round(ideal_ms / ms_per_step, 4)}
+           "roofline_frac": round(ideal_ms / ms_per_step, 4),
+           "locked_bands_per_step": fam.get("locked_bands", 0.0)}
     return out, roofline, run
 
 
@@ -437,7 +448,9 @@ def main():
     wall, fam = throughput(b, cfg, plan, v, x0, args.steps, args.warmup, mixed)
     ms_step = 1e3 * wall / args.steps
     log(f"[bench] {args.steps} steps in {wall:.3f}s ({ms_step:.2f} ms/step)")
-    log("[bench] per-step ms by family: " + ", ".join(f"{k}={x[0]:.3f} ({x[1]:.0f} launches)" for k, x in fam.items()))
+    log("[bench] per-step ms by family: " + ", ".join(f"{k}={x[0]:.3f} ({x[1]:.0f} launches)" for k, x in fam.items()
+                                                      if isinstance(x, tuple))
+        + f"; soft-locked bands per step {fam.get('locked_bands', 0.0):.1f}")
     kernels, roofline, run = rates(cfg, fam, mixed, ms_step)
     del plan, v
     torch.cuda.empty_cache()
