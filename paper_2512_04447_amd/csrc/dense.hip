@@ -1287,8 +1287,18 @@ __global__ void k_clusters(const double* __restrict__ w, int nev, const double* 
 // by Gaussian elimination with partial pivoting on the tridiagonal matrix
 // (thread 0; the recurrences carry their running values in registers and
 // store the factors in LDS), re-orthogonalises against the earlier vectors
-// of the cluster (modified Gram-Schmidt, all threads) and normalises; three
-// sweeps.  Dynamic LDS: 5n doubles (the factor U0 (as its reciprocal), U1,
+// of the cluster whose eigenvalues lie within ortol = 1e-5 |T| of its own
+// (block classical Gram-Schmidt, twice) and normalises; three sweeps.  A
+// cluster is a chain of eigenvalues each within ortol of the next, and can
+// span hundreds of them where the spectrum is dense; vectors of that chain
+// whose eigenvalues differ by more than ortol come out orthogonal to about
+// eps |T| / ortol = 1e-11 without it (the same bound the cluster test
+// itself accepts between clusters), so the re-orthogonalisation is against
+// the window, not the whole chain.  An ill-conditioned pencil makes |T|,
+// and with it the window, large (hundreds of vectors): the dot products of
+// a chunk of earlier vectors are then computed together, not one block
+// reduction per vector (which cost about one second per solve for a
+// window of 480).  Dynamic LDS: 5n doubles (the factor U0 (as its reciprocal), U1,
 // U2, the multipliers and x) and n ints (pivots).
 __global__ void __launch_bounds__(256)
 k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, int n, const double* __restrict__ w,
@@ -1296,7 +1306,9 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
                     const int32_t* __restrict__ ncl, double* __restrict__ Z, int ldz) {
   __shared__ double red[4];
   __shared__ double lam_prev;
+  __shared__ double dots[64];
   extern __shared__ __align__(16) unsigned char ii_raw[];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   double* ru0 = reinterpret_cast<double*>(ii_raw);  // 1 / U0
   double* u1 = ru0 + n;
   double* u2 = u1 + n;
@@ -1310,8 +1322,21 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
   const double eps = DBL_EPSILON;
   const double pertol = 10.0 * eps * fmax(tnorm, DBL_MIN);
   const double small = eps * fmax(tnorm, DBL_MIN);
+  const double ortol = 1e-5 * tnorm;  // the cluster test's tolerance
   for (int j = j0; j < j1; ++j) {
     double lam = w[j];
+    // first earlier vector of the window: w[p] >= w[j] - ortol (w ascending;
+    // the same value in every thread)
+    int pbeg = j0;
+    {
+      int hi = j;
+      const double lo_w = lam - ortol;
+      while (pbeg < hi) {
+        const int mid = (pbeg + hi) >> 1;
+        if (w[mid] < lo_w) pbeg = mid + 1;
+        else hi = mid;
+      }
+    }
     if (threadIdx.x == 0) {
       if (j > j0 && lam - lam_prev < pertol) lam = lam_prev + pertol;
       lam_prev = lam;
@@ -1407,13 +1432,27 @@ k_inverse_iteration(const double* __restrict__ d, const double* __restrict__ e, 
       const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
       for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= sc;
       __syncthreads();
-      for (int p = j0; p < j; ++p) {
-        const double* zp = Z + (int64_t)p * ldz;
-        double dot = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) dot += zp[i] * x[i];
-        dot = block_sum(dot, red);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] -= dot * zp[i];
-        __syncthreads();
+      // block classical Gram-Schmidt, twice: per chunk of up to 64 earlier
+      // vectors all dot products at once (wave w takes every fourth vector,
+      // lanes over the rows), then one update pass over the rows
+      for (int gs = 0; gs < 2; ++gs) {
+        for (int c0 = pbeg; c0 < j; c0 += 64) {
+          const int cn = min(64, j - c0);
+          for (int q = wv; q < cn; q += 4) {
+            const double* zp = Z + (int64_t)(c0 + q) * ldz;
+            double dsum = 0.0;
+            for (int i = ln; i < n; i += 64) dsum += zp[i] * x[i];
+            dsum = wave_sum(dsum);
+            if (ln == 0) dots[q] = dsum;
+          }
+          __syncthreads();
+          for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double acc = 0.0;
+            for (int q = 0; q < cn; ++q) acc += dots[q] * Z[i + (int64_t)(c0 + q) * ldz];
+            x[i] -= acc;
+          }
+          __syncthreads();
+        }
       }
       double nn = 0.0;
       for (int i = threadIdx.x; i < n; i += blockDim.x) nn += x[i] * x[i];
