@@ -142,7 +142,11 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
   const int64_t k1 = min(K, k0 + kper);
   const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
   const int wi = wave / WJ, wj = wave % WJ;
-  const bool wact = ti * TILE + wi * 32 < m && tj * TILE + wj * WN * 16 < m;
+  // A Hermitian Gram's diagonal tile needs its upper half only: the waves
+  // of rows 32..63 and columns 0..31 (strictly below the diagonal) issue no
+  // MFMA, and the reduction takes those entries from their mirrors.
+  const bool lower_skip = !full && ti == tj && wi == 1 && wj * WN * 16 < 32;
+  const bool wact = ti * TILE + wi * 32 < m && tj * TILE + wj * WN * 16 < m && !lower_skip;
   typename M::acc sr[2][WN], si[2][WN], hr[2][WN], hi[2][WN];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -275,7 +279,8 @@ k_gram(BlockList<c2<T>> A, BlockList<c2<T>> B1, BlockList<c2<T>> B2, int m, int6
 }
 
 // Sum the K splits in order and write the Hermitian m x m result
-// (column-major, ldo).  Diagonal tiles are Hermitised, (G + G^H)/2.
+// (column-major, ldo).  Diagonal tiles are Hermitised, (G + G^H)/2, within
+// their 32 x 32 diagonal blocks.
 __global__ void __launch_bounds__(256)
 k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, int m, int full,
               double2* __restrict__ out, int ldo) {
@@ -309,7 +314,10 @@ k_gram_reduce(const double2* __restrict__ part, int nsplit, int ntile, int ntu, 
       s.x += v.x;
       s.y += v.y;
     }
-    if (ti == tj) {
+    // a diagonal tile: the two triangles averaged where both were computed
+    // (within the 32 x 32 diagonal blocks); rows 32..63 of columns 0..31
+    // were not (k_gram skips them), their mirrors stand alone
+    if (ti == tj && !(i < 32 && j >= 32)) {
       double2 s2 = make_double2(0.0, 0.0);
       for (int sp = 0; sp < nsplit; ++sp) {
         const double2 v = part[((int64_t)sp * ntu + blockIdx.x) * (TILE * TILE) + j * TILE + i];
