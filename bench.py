@@ -53,10 +53,10 @@ WORKLOADS = {
 # was measured on is unchanged (sha256 below).
 MEASURED_TRAFFIC = {
     # 216-atom cell, FP64, the basis Gram launch (Gram dispatch + its two
-    # ordered reductions): 685.01 GB fetched + 0.93 GB written
+    # ordered reductions): 688.83 GB fetched + 0.93 GB written
     # (profiles/hbm_traffic_fp64_c3.md)
-    ("C3", "fp64", "gram_basis"): (685945912890, "paper_2512_04447_amd/csrc/gemm.hip",
-                                   "ab4c33b81f130faf45ee4b8c6de65b945313e9c8c4a83572323c90aadf97f948"),
+    ("C3", "fp64", "gram_basis"): (689762714048, "paper_2512_04447_amd/csrc/gemm.hip",
+                                   "6160ed8a061410f794986762277b7ebda54e54a7be8edf6395f3920999f536a6"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
