@@ -427,6 +427,43 @@ def test_hegv_degenerate_clusters_and_ill_conditioned_overlap(ks, n, cond):
     assert bool((w == 7.0).all()) and bool((Cm == 3.0).all())
 
 
+@pytest.mark.parametrize("n,cond", [(480, 1e2), (1440, 1e6)])
+def test_hegv_chained_cluster(ks, n, cond):
+    """A dense run of distinct eigenvalues, each closer to the next than
+    the cluster tolerance (1e-5 |T|), forms one chained cluster of nev - 8
+    values: inverse iteration re-orthogonalises each vector against the
+    earlier ones within the tolerance window only.  Eigenvalues within
+    1e-11 of the closed form, C^H S C = I and the residual to 1e-10 (the
+    window's bound on the orthogonality of vectors outside it is
+    eps |T| / 1e-5 |T|, about 1e-11)."""
+    import torch
+
+    from paper_2512_04447_amd import binding as b
+
+    nev = n // 3
+    rng = np.random.default_rng(n + 3)
+    # |T| is about 3 here (the spectrum's extent): spacing 1e-6 < 3e-5
+    run = -1.0 + 1e-6 * np.arange(nev - 8)
+    lam = np.concatenate([np.linspace(-2.0, -1.5, 8), run, np.linspace(0.5, 3.0, n - nev)])
+    _say("hegv chain", n, cond, len(run))
+    Hm, S = _pencil_with_spectrum(n, lam, cond, rng)
+    exact = np.sort(lam)[:nev]
+    w = torch.zeros(nev, dtype=torch.float64, device="cuda")
+    Cm = torch.zeros((nev, n), dtype=torch.complex128, device="cuda").T
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b.hegv_reduce_solve(colmajor(Hm), colmajor(S), nev, w, Cm, info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    wg, Cg = w.cpu().numpy(), Cm.cpu().numpy()
+    err = np.abs(wg - exact).max()
+    orth = np.abs(Cg.conj().T @ S @ Cg - np.eye(nev)).max()
+    resid = np.abs(Hm @ Cg - S @ Cg * wg).max() / np.abs(Hm).max()
+    _say("  err", err, "C^H S C - I", orth, "residual", resid)
+    assert err <= max(1e-13 * cond * 3.0, 1e-11)
+    assert orth <= max(1e-13 * cond, 1e-10)
+    assert resid <= max(1e-13 * cond, 1e-10)
+
+
 def test_apply_h_with_an_atom_without_projectors(ks):
     """An atom with support points but no projectors contributes nothing and
     is not read: H-apply equals the oracle with only the other atom's
