@@ -121,7 +121,18 @@ typedef struct {
   int32_t* status;
   void* host_summary;
   int32_t iter;    /* iterations done */
-  int32_t pad_;
+  /* 1 once lobpcg_step has left the next step's P Gram in p_gram; cleared
+   * by lobpcg_init.  A caller that replaces P (or the state) between steps
+   * sets it to 0. */
+  int32_t p_gram_ok;
+  /* Optional device array of nb*nb complex128 values (16*nb*nb bytes,
+   * column-major) that carries the Gram matrix of the next step's P from
+   * one lobpcg_step to the next: the step's P = V_[W P] C_[W P], so
+   * P^H P = C_[W P]^H S_[W P] C_[W P] is formed from the step's own
+   * subspace matrices (two products of its m - nb square block) instead of
+   * a pass over P's Ng rows.  The next step uses it when p_gram_ok is set.
+   * NULL: every step forms P's Gram from P itself. */
+  void* p_gram;
 } ks_lobpcg_state;
 
 /* Status words written by every lobpcg_init / lobpcg_step (cleared at its
@@ -320,7 +331,8 @@ int lobpcg_init(const ks_plan* plan, const void* v_loc, ks_lobpcg_state* st, voi
  *      within the block, deflating);
  *   3. AW = H W;
  *   4. (from the second step) P masked by the lock test, orthonormalised as
- *      W, AP = H P;
+ *      W (its Gram from the previous step's subspace matrices when
+ *      st->p_gram is set), AP = H P;
  *   5. S = V^H V, H = V^H AV for V = [X W P] (or [X W]), Hermitised; exactly
  *      zero columns decoupled (S_kk = 1, H_kk = 2 max|H_ii| + 1);
  *   6. lowest nb eigenpairs of H C = S C Theta by the reduction of

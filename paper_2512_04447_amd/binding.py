@@ -109,7 +109,8 @@ class KsLobpcgState(C.Structure):
         ("status", C.c_void_p),
         ("host_summary", C.c_void_p),
         ("iter", C.c_int32),
-        ("pad_", C.c_int32),
+        ("p_gram_ok", C.c_int32),
+        ("p_gram", C.c_void_p),
     ]
 
 
@@ -530,6 +531,8 @@ class Lobpcg:
         self.theta = torch.zeros(nb, dtype=torch.float64, device=dev)
         self.res = torch.zeros(nb, dtype=torch.float64, device=dev)
         self.status = torch.zeros(KS_STATUS_WORDS, dtype=torch.int32, device=dev)
+        # the next step's P Gram, carried from step to step
+        self.p_gram = torch.zeros((nb, nb), dtype=torch.complex128, device=dev)
         self.work = _work(plan.workspace_size(KS_OP_LOBPCG, nb), dev)
         self._by_ptr = {_ptr(t): t for t in self.buf.values()}
         st = KsLobpcgState()
@@ -540,6 +543,7 @@ class Lobpcg:
         st.theta = _ptr(self.theta)
         st.res = _ptr(self.res)
         st.status = _ptr(self.status)
+        st.p_gram = _ptr(self.p_gram)
         self.summary = None
         if summary:
             self.summary = torch.zeros(16 * nb + 4 * KS_STATUS_WORDS, dtype=torch.uint8, pin_memory=True)

@@ -465,6 +465,8 @@ struct LobWs {
   double2* C;   // m x nb (FP64)
   void* Cb;     // m x nb block precision
   double2* G;   // nb x nb
+  double2* S22; // (m - nb)^2: the [W P] block of S, kept for the next P's Gram
+  double2* T22; // (m - nb) x nb
   double2* Y;   // nb x nb
   void* M;      // nb x nb block precision
   double* dvec; // nb
@@ -493,6 +495,8 @@ static LobWs lob_ws(const ks_plan& p, void* work, int nb) {
   w.C = reinterpret_cast<double2*>(take((size_t)m * nb * 16));
   w.Cb = take((size_t)m * nb * es);
   w.G = reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
+  w.S22 = reinterpret_cast<double2*>(take((size_t)(m - nb) * (m - nb) * 16));
+  w.T22 = reinterpret_cast<double2*>(take((size_t)(m - nb) * nb * 16));
   w.Y = reinterpret_cast<double2*>(take((size_t)nb * nb * 16));
   w.M = take((size_t)nb * nb * es);
   w.dvec = reinterpret_cast<double*>(take((size_t)nb * 8));
@@ -623,12 +627,19 @@ k_finish_status(int32_t* __restrict__ st, const double* __restrict__ theta, cons
 // out.  The Cholesky deflates: a column that depends numerically on the
 // ones before it becomes an exactly-zero column (counted in *ndead).  No
 // host synchronisation.
+// gram_in: B's Gram matrix (nb x nb, FP64) when the caller has it; else it
+// is formed from B.
 template <typename T>
 static int block_orthonormalise(const ks_plan& p, const LobWs& w, const void* B, void* out, int64_t ld, int nb,
-                                const double* res, double lock_tol, int32_t* ndead, hipStream_t s) {
+                                const double* res, double lock_tol, int32_t* ndead, hipStream_t s,
+                                const double2* gram_in = nullptr) {
   int rc;
   auto L1 = blist<T>(B, nullptr, nullptr, ld, nb);
-  if ((rc = gram<T>(L1, L1, nullptr, nb, p.Ng, w.G, nb, nullptr, 0, w.gram, s))) return rc;
+  if (gram_in != nullptr) {
+    KS_HIP(hipMemcpyAsync(w.G, gram_in, (size_t)nb * nb * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  } else if ((rc = gram<T>(L1, L1, nullptr, nb, p.Ng, w.G, nb, nullptr, 0, w.gram, s))) {
+    return rc;
+  }
   hipLaunchKernelGGL(k_colscale, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, w.G, nb, nb, res, lock_tol,
                      w.dvec);
   hipLaunchKernelGGL(k_scale_gram, dim3(grid_for((int64_t)nb * nb)), dim3(256), 0, s, w.G, nb, nb, w.dvec);
@@ -733,6 +744,7 @@ static int lob_init(const ks_plan& p, const void* v, ks_lobpcg_state* st, void* 
                        s)))
     return rc;
   st->has_p = 0;
+  st->p_gram_ok = 0;
   st->iter = 0;
   return finish_step(w, st, nullptr, nb, s);
 }
@@ -767,7 +779,7 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   // 4. P, AP masked and orthonormalised
   if (st->has_p) {
     if ((rc = block_orthonormalise<T>(p, w, st->P, st->Pn, ld, nb, st->res, o->lock_tol, st->status + KS_ST_DEAD_P,
-                                      s)))
+                                      s, st->p_gram_ok ? static_cast<const double2*>(st->p_gram) : nullptr)))
       return rc;
     std::swap(st->P, st->Pn);
     // the same mask zeroed the locked P columns
@@ -785,11 +797,28 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   }
   hipLaunchKernelGGL(k_decouple, dim3(1), dim3(256), 0, s, w.S, m, w.H, m, m);
   KS_LAUNCH_CHECK("decouple");
+  // the [W P] block of S, before the factorisation overwrites it
+  const int m2 = m - nb;
+  if (st->p_gram != nullptr)
+    KS_HIP(hipMemcpy2DAsync(w.S22, (size_t)m2 * sizeof(double2), w.S + nb + (int64_t)nb * m,
+                            (size_t)m * sizeof(double2), (size_t)m2 * sizeof(double2), (size_t)m2,
+                            hipMemcpyDeviceToDevice, s));
   // 6. reduction and eigensolve; basis vectors that depend numerically on
   // earlier ones are dropped by the deflating Cholesky
   if ((rc = hegv(m, nb, w.H, m, w.S, m, w.wnew, w.C, m, w.hegv, st->status + KS_ST_INFO,
                  st->status + KS_ST_DEAD_BASIS, s)))
     return rc;
+  // the next P = V_[W P] C_[W P] has Gram C_[W P]^H S_[W P] C_[W P] (dead
+  // basis vectors have zero coefficients, so their decoupled entries of S
+  // contribute nothing)
+  st->p_gram_ok = 0;
+  if (st->p_gram != nullptr) {
+    if ((rc = zgemm('N', 'N', m2, nb, m2, 1.0, w.S22, m2, w.C + nb, m, 0.0, w.T22, m2, s))) return rc;
+    if ((rc = zgemm('C', 'N', nb, nb, m2, 1.0, w.C + nb, m, w.T22, m2, 0.0, static_cast<double2*>(st->p_gram), nb,
+                    s)))
+      return rc;
+    st->p_gram_ok = 1;
+  }
   // 7. rotation: X <- V C and P <- V[:, nb:] C[nb:, :] in one pass over V
   hipLaunchKernelGGL((k_to_block<T>), dim3(grid_for((int64_t)m * nb)), dim3(256), 0, s, w.C, m,
                      static_cast<T2*>(w.Cb), m, m, nb);

@@ -209,6 +209,7 @@ def _gpu_state_from_oracle(lob, st):
         lob.buf["P"].copy_(to_dev(st.P))
         lob.st.P = int(lob.buf["P"].data_ptr())
         lob.st.has_p = 1
+    lob.st.p_gram_ok = 0  # P replaced: the next step forms its Gram from P
     torch.cuda.synchronize()
 
 
