@@ -119,11 +119,11 @@ def family_work(cfg, es, locked=0.0):
     # mixed path: re-orthonormalisation of X (one more self-Gram and rotation)
     extra = 1 if es == 8 else 0
     return {
-        # Hermitian triangles of the W self-Gram (S only; P's Gram comes from
-        # the previous step's subspace matrices, two small products) and of
-        # the basis Gram (S and H); the full X^H W of the projection
-        # W - X X^H W
-        "gram_flops": 8 * Ng * (nb * (nb + 1) / 2 * (1 + extra) + nb * nb + 2 * m * (m + 1) / 2),
+        # Hermitian triangles of the self-Grams (S only: W; on mixed plans
+        # also P and X, FP64 plans take P's Gram from the previous step's
+        # subspace matrices, two small products) and of the basis Gram (S
+        # and H); the full X^H W of the projection W - X X^H W
+        "gram_flops": 8 * Ng * (nb * (nb + 1) / 2 * (1 + 2 * extra) + nb * nb + 2 * m * (m + 1) / 2),
         # the basis Gram alone: S and H over [X W P], Hermitian triangles
         "gram_basis_flops": 8 * Ng * m * (m + 1),
         # the W and P (and, mixed, X) orthonormalising rotations by upper

@@ -131,7 +131,9 @@ typedef struct {
    * P^H P = C_[W P]^H S_[W P] C_[W P] is formed from the step's own
    * subspace matrices (two products of its m - nb square block) instead of
    * a pass over P's Ng rows.  The next step uses it when p_gram_ok is set.
-   * NULL: every step forms P's Gram from P itself. */
+   * FP64 plans only (a mixed plan's P, rotated in FP32, departs from that
+   * product by the FP32 rounding); NULL, or a mixed plan: every step forms
+   * P's Gram from P itself. */
   void* p_gram;
 } ks_lobpcg_state;
 

@@ -797,9 +797,14 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   }
   hipLaunchKernelGGL(k_decouple, dim3(1), dim3(256), 0, s, w.S, m, w.H, m, m);
   KS_LAUNCH_CHECK("decouple");
-  // the [W P] block of S, before the factorisation overwrites it
+  // the [W P] block of S, before the factorisation overwrites it.  FP64
+  // plans only: a mixed plan's P is rotated in FP32 (and by FP32
+  // coefficients), so its computed Gram departs from C^H S C by the FP32
+  // rounding, which the Cholesky-QR of a nearly dependent P magnifies; it
+  // forms P's Gram from P itself.
   const int m2 = m - nb;
-  if (st->p_gram != nullptr)
+  const bool carry = st->p_gram != nullptr && p.prec == KS_FP64;
+  if (carry)
     KS_HIP(hipMemcpy2DAsync(w.S22, (size_t)m2 * sizeof(double2), w.S + nb + (int64_t)nb * m,
                             (size_t)m * sizeof(double2), (size_t)m2 * sizeof(double2), (size_t)m2,
                             hipMemcpyDeviceToDevice, s));
@@ -812,7 +817,7 @@ static int lob_step(const ks_plan& p, const void* v, ks_lobpcg_state* st, const 
   // basis vectors have zero coefficients, so their decoupled entries of S
   // contribute nothing)
   st->p_gram_ok = 0;
-  if (st->p_gram != nullptr) {
+  if (carry) {
     if ((rc = zgemm('N', 'N', m2, nb, m2, 1.0, w.S22, m2, w.C + nb, m, 0.0, w.T22, m2, s))) return rc;
     if ((rc = zgemm('C', 'N', nb, nb, m2, 1.0, w.C + nb, m, w.T22, m2, 0.0, static_cast<double2*>(st->p_gram), nb,
                     s)))
