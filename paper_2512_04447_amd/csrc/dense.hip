@@ -43,6 +43,41 @@ __global__ void k_potrf_init(const double2* __restrict__ S, int lds, int n, doub
   }
 }
 
+// One doubling level of the inverse of the lower-triangular NB x NB
+// matrix L (held in l): for each pair of S x S diagonal blocks whose
+// inverses are in x, form the off-diagonal block of the inverse of the
+// 2S x 2S block, -X_C (B X_A) with B the block of L below X_A and beside X_C.
+// Every product runs over the whole block: the parts of X_A and X_C above
+// their diagonals are zero in x.  16 S threads, one output each.
+template <int S>
+__device__ __forceinline__ void inverse_level(double2 (*l)[NB + 1], double2 (*x)[NB + 1], double2 (*t)[NB + 1]) {
+  const int e = threadIdx.x;
+  const int r0 = (e / (S * S)) * 2 * S, i = (e % (S * S)) % S, j = (e % (S * S)) / S;
+  const bool act = e < 16 * S;
+  if (act) {
+    double accr = 0.0, acci = 0.0;
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      const double2 b = l[r0 + S + i][r0 + p], y = x[r0 + p][r0 + j];
+      accr += b.x * y.x - b.y * y.y;
+      acci += b.x * y.y + b.y * y.x;
+    }
+    t[r0 + S + i][r0 + j] = make_double2(accr, acci);
+  }
+  __syncthreads();
+  if (act) {
+    double accr = 0.0, acci = 0.0;
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      const double2 c = x[r0 + S + i][r0 + S + p], y = t[r0 + S + p][r0 + j];
+      accr += c.x * y.x - c.y * y.y;
+      acci += c.x * y.y + c.y * y.x;
+    }
+    x[r0 + S + i][r0 + j] = make_double2(-accr, -acci);
+  }
+  __syncthreads();
+}
+
 // Unblocked Cholesky of the diagonal block at k0 (kb <= NB columns) in LDS,
 // then the inverse of that block (for the panel and the triangular solves).
 // Step j updates the trailing block with the unscaled column j divided by
@@ -62,7 +97,10 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
         int32_t* __restrict__ info, int info_offset, double2* __restrict__ linv, int32_t* __restrict__ dead,
         int32_t* __restrict__ ndead) {
   __shared__ double2 a[NB][NB + 1];
+  __shared__ double2 xa[NB][NB + 1];  // the inverse
+  __shared__ double2 ta[NB][NB + 1];  // B A^-1 of the inverse's doubling
   __shared__ double sq[NB];
+  __shared__ double pv[NB];  // pivots
   // the block: unconditional loads (indices clamped into the block), issued
   // together with the flag and the tolerance's scale; padding zeroed
   // afterwards, four in flight per thread
@@ -87,22 +125,33 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
   __syncthreads();
   // thread t owns row i = t % NB of columns p = t / NB + 8u (u = 0..3)
   const int ri = threadIdx.x % NB, pc = threadIdx.x / NB;
+  const bool deflate = dead != nullptr;
   // dead columns of this block as a bit mask (the same value in every thread)
   unsigned deadmask = 0u;
+  // pivot of the current step and its reciprocal, one step ahead: every
+  // thread forms the next pivot from the two entries that fix it, so the
+  // division runs while the step's update and barrier are in flight
+  double d = a[0][0].x;
+  bool dj = !(d > tol);
+  double rd = dj ? 0.0 : 1.0 / d;
   for (int j = 0; j < kb; ++j) {
-    const double d = a[j][j].x;
-    const bool dj = !(d > tol);
-    if (dj && dead == nullptr) {
+    if (dj && !deflate) {
       if (threadIdx.x == 0) *info = info_offset + k0 + j + 1;
-      return;  // uniform: every thread read the same d
+      return;  // uniform: every thread holds the same pivot
     }
     deadmask |= dj ? (1u << j) : 0u;
+    if (threadIdx.x == 0) pv[j] = d;
     // a[i][p] -= a[i][j] conj(a[p][j]) / d for j < p <= i < kb: every read
     // first (in range: the padding is zero), then the guarded writes; no
     // entry written here is read in this step.  A deflated column updates
     // nothing (1/d taken as 0); its entries are replaced after the loop.
-    const double rd = dj ? 0.0 : 1.0 / d;
+    // The next pivot's entry (j+1, j+1) is read by every thread and so is
+    // not written: its update is the register pivot formed below, and no
+    // later step reads it from LDS.
+    const int jn = min(j + 1, NB - 1);
     const double2 x = a[ri][j];
+    const double dnn = a[jn][jn].x;
+    const double2 xn = a[jn][j];
     double2 y[4], z[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -112,11 +161,15 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int p = pc + 8 * u;
-      if (p > j && ri >= p && ri < kb) {
+      if (p > j && ri >= p && ri < kb && !(ri == j + 1 && p == j + 1)) {
         a[ri][p].x = z[u].x - (x.x * y[u].x + x.y * y[u].y) * rd;
         a[ri][p].y = z[u].y - (x.y * y[u].x - x.x * y[u].y) * rd;
       }
     }
+    // next pivot: the same update of the entry (j+1, j+1)
+    d = dnn - (xn.x * xn.x + xn.y * xn.y) * rd;
+    dj = !(d > tol);
+    rd = dj ? 0.0 : 1.0 / d;
     __syncthreads();
   }
   // L: column j scaled by 1/sqrt(d_j), the diagonal sqrt(d_j); a deflated
@@ -126,7 +179,7 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
       if ((deadmask >> j) & 1u) dead[k0 + j] = 1;
     if (ndead) atomicAdd(ndead, __popc(deadmask));
   }
-  if (threadIdx.x < kb) sq[threadIdx.x] = ((deadmask >> threadIdx.x) & 1u) ? 1.0 : sqrt(a[threadIdx.x][threadIdx.x].x);
+  if (threadIdx.x < kb) sq[threadIdx.x] = ((deadmask >> threadIdx.x) & 1u) ? 1.0 : sqrt(pv[threadIdx.x]);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -150,30 +203,32 @@ k_potf2(double2* __restrict__ S, int lds, int k0, int kb, const double* __restri
     const int i = e % kb, j = e / kb;
     if (i >= j) S[(k0 + i) + (int64_t)(k0 + j) * lds] = a[i][j];
   }
-  // inverse X = L^-1, column c by lane c of the first wave: forward
-  // substitution X[i][c] = (delta_ic - sum_{c<=p<i} L[i][p] X[p][c]) / L[i][i]
-  // in registers, L read from LDS (the same entry for every lane), no
-  // barriers
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
-    double2 xc[NB];
+  // inverse X = L^-1 by doubling: with the inverses of the two diagonal
+  // blocks of a lower-triangular [A 0; B C] known, the off-diagonal block of
+  // its inverse is -C^-1 (B A^-1).  Block sizes 1, 2, 4, 8, 16; the padding
+  // diagonal is taken as 1, and rows of dead columns or of the padding are
+  // zeroed at the store (a dead column of L is a unit vector, so its column
+  // of the inverse is one too and vanishes with its row).
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double accr = 0.0, acci = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int i = e % NB, j = e / NB;
+    const double di = i < kb ? 1.0 / sq[i] : 1.0;
+    xa[i][j] = make_double2(i == j ? di : 0.0, 0.0);
+  }
+  __syncthreads();
+  inverse_level<1>(a, xa, ta);
+  inverse_level<2>(a, xa, ta);
+  inverse_level<4>(a, xa, ta);
+  inverse_level<8>(a, xa, ta);
+  inverse_level<16>(a, xa, ta);
 #pragma unroll
-      for (int p = 0; p < i; ++p) {
-        const double2 l = a[i][p];
-        const double2 y = xc[p];  // zero for p < c
-        accr += l.x * y.x - l.y * y.y;
-        acci += l.x * y.y + l.y * y.x;
-      }
-      const bool live = c <= i && i < kb && c < kb && ((deadmask >> i) & 1u) == 0u;
-      const double inv = 1.0 / a[i][i].x;
-      const double dr = ((i == c ? 1.0 : 0.0) - accr) * inv, di = -acci * inv;
-      xc[i] = make_double2(live ? dr : 0.0, live ? di : 0.0);
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) linv[i + (int64_t)c * NB] = xc[i];
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int i = e % NB, c = e / NB;
+    const bool live = i < kb && ((deadmask >> i) & 1u) == 0u;
+    const double2 v = xa[i][c];
+    linv[e] = make_double2(live ? v.x : 0.0, live ? v.y : 0.0);
   }
 }
 
