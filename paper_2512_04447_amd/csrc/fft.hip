@@ -856,38 +856,71 @@ k_nl_project_tile(const c2<T>* __restrict__ psi, int64_t ld, int nb, int n1, int
         __syncthreads();
       }
       const int ea = spe[qa], va = sbo[qa];
-      for (int q = qa + wv; q < qb; q += nw) {
-        const int e0 = spe[q] - ea, e1 = spe[q + 1] - ea;
-        const int np = (sbo[q + 1] - sbo[q]) / max(e1 - e0, 1);
-        const T* bq = sb + (sbo[q] - va);
+      // a pair's bounds are the same in every lane of its wave: held in
+      // scalar registers, so that the branches on them are scalar too
+      for (int q = __builtin_amdgcn_readfirstlane(qa + wv); q < qb; q += nw) {
+        const int e0 = __builtin_amdgcn_readfirstlane(spe[q] - ea);
+        const int e1 = __builtin_amdgcn_readfirstlane(spe[q + 1] - ea);
+        const int boff = __builtin_amdgcn_readfirstlane(sbo[q] - va);
+        const int np = __builtin_amdgcn_readfirstlane((sbo[q + 1] - sbo[q]) / max(e1 - e0, 1));
+        const T* bq = sb + boff;
+        // four projectors whose values start at an even offset: read an
+        // entry's values as pairs (same sums, fewer LDS reads)
+        const bool vec4 = np == 4 && (boff & 1) == 0;
         // sums in the plan's precision within a tile (FP32 for the mixed
         // plans, whose H-apply is FP32 by design); tiles are summed in FP64
         T ar[MAXP], ai[MAXP];
 #pragma unroll
         for (int j = 0; j < MAXP; ++j) ar[j] = ai[j] = T(0);
-        // entries in flight per group (fewer with nine accumulators)
+        // entries in flight per group (fewer with nine accumulators); the
+        // loop is compiled twice, for the paired reads and the general one,
+        // and the wave takes one copy (a branch on scalars)
         constexpr int UE = MAXP > 4 ? 2 : 4;
-        for (int e = e0 + g; e < e1; e += UE * G) {
-          int tt[UE];
-          bool okk[UE];
+        auto entries = [&](auto paired) {
+          constexpr bool V = decltype(paired)::value;
+          for (int e = e0 + g; e < e1; e += UE * G) {
+            int tt[UE];
+            bool okk[UE];
 #pragma unroll
-          for (int u = 0; u < UE; ++u) {
-            okk[u] = e + u * G < e1;
-            tt[u] = st[min(e + u * G, e1 - 1)];
-          }
-          T2 w[UE];
+            for (int u = 0; u < UE; ++u) {
+              okk[u] = e + u * G < e1;
+              tt[u] = st[min(e + u * G, e1 - 1)];
+            }
+            T2 w[UE];
 #pragma unroll
-          for (int u = 0; u < UE; ++u) w[u] = sp[tt[u] * ROW + b];
+            for (int u = 0; u < UE; ++u) w[u] = sp[tt[u] * ROW + b];
 #pragma unroll
-          for (int u = 0; u < UE; ++u) {
-            const int el = min(e + u * G, e1 - 1) - e0;
+            for (int u = 0; u < UE; ++u) {
+              const int el = min(e + u * G, e1 - 1) - e0;
+              if constexpr (V) {
+                // the entry's four values as two pair loads
+                const T2* bv = reinterpret_cast<const T2*>(bq + el * 4);
+                const T2 b01 = bv[0], b23 = bv[1];
+                const T be[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
-            for (int j = 0; j < MAXP; ++j) {
-              const T be = (okk[u] && j < np) ? bq[el * np + min(j, np - 1)] : T(0);
-              ar[j] += be * w[u].x;
-              ai[j] += be * w[u].y;
+                for (int j = 0; j < 4; ++j) {
+                  const T bj = okk[u] ? be[j] : T(0);
+                  ar[j] += bj * w[u].x;
+                  ai[j] += bj * w[u].y;
+                }
+              } else {
+#pragma unroll
+                for (int j = 0; j < MAXP; ++j) {
+                  const T be = (okk[u] && j < np) ? bq[el * np + min(j, np - 1)] : T(0);
+                  ar[j] += be * w[u].x;
+                  ai[j] += be * w[u].y;
+                }
+              }
             }
           }
+        };
+        if constexpr (MAXP == 4) {
+          if (vec4)
+            entries(std::true_type{});
+          else
+            entries(std::false_type{});
+        } else {
+          entries(std::false_type{});
         }
 #pragma unroll
         for (int j = 0; j < MAXP; ++j) {
