@@ -733,6 +733,35 @@ k_cols(Fft3 f, int zc2, c2<T>* __restrict__ buf, int64_t ld, const c2<T>* __rest
 // ---------------------------------------------------------------- nonlocal
 // Deterministic (no atomics, fixed summation orders).
 
+// Sum of a value over the four 16-lane rows of a wave, in every lane:
+// (row0 + row1) + (row2 + row3) for rows 0 and 1, the same sum as
+// (row2 + row3) + (row0 + row1) for rows 2 and 3.  The gfx950 row swaps
+// move the data in registers (an xor shuffle goes through the LDS unit):
+// swapping the odd rows of a copy with the even rows of another leaves the
+// even-row value in one and the odd-row value in the other, for every lane
+// of the row pair; the half swap does the same for lanes 0-31 and 32-63.
+__device__ __forceinline__ int2 swap_rows16(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return make_int2((int)r[0], (int)r[1]);
+}
+__device__ __forceinline__ int2 swap_halves32(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return make_int2((int)r[0], (int)r[1]);
+}
+__device__ __forceinline__ double group_sum4(double v) {
+  int2 lo = swap_rows16(__double2loint(v)), hi = swap_rows16(__double2hiint(v));
+  v = __hiloint2double(hi.x, lo.x) + __hiloint2double(hi.y, lo.y);
+  lo = swap_halves32(__double2loint(v));
+  hi = swap_halves32(__double2hiint(v));
+  return __hiloint2double(hi.x, lo.x) + __hiloint2double(hi.y, lo.y);
+}
+__device__ __forceinline__ float group_sum4(float v) {
+  int2 r = swap_rows16(__float_as_int(v));
+  v = __int_as_float(r.x) + __int_as_float(r.y);
+  r = swap_halves32(__float_as_int(v));
+  return __int_as_float(r.x) + __int_as_float(r.y);
+}
+
 // Projection with every orbital value read once.  Block (tile k, slice of
 // band tiles) keeps the tile's (tile, atom) pairs in LDS: each pair lists
 // the atom's support points inside the tile (tile-local point, then the np
@@ -924,10 +953,15 @@ k_nl_project_tile(const c2<T>* __restrict__ psi, int64_t ld, int nb, int n1, int
         }
 #pragma unroll
         for (int j = 0; j < MAXP; ++j) {
+          if constexpr (NBS == 16) {
+            ar[j] = group_sum4(ar[j]);
+            ai[j] = group_sum4(ai[j]);
+          } else {
 #pragma unroll
-          for (int off = NBS; off < kWave; off <<= 1) {
-            ar[j] += __shfl_xor(ar[j], off, kWave);
-            ai[j] += __shfl_xor(ai[j], off, kWave);
+            for (int off = NBS; off < kWave; off <<= 1) {
+              ar[j] += __shfl_xor(ar[j], off, kWave);
+              ai[j] += __shfl_xor(ai[j], off, kWave);
+            }
           }
         }
         if (g == 0 && b < nbl) {
