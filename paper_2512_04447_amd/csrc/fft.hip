@@ -775,7 +775,8 @@ __device__ __forceinline__ float group_sum4(float v) {
 // NBS bands x (64 / NBS) entry groups, each group sums beta_j * psi over
 // every (64 / NBS)-th entry of the pair (four entries in flight, two with
 // nine projectors per atom; a fixed order), the groups are combined by a
-// fixed shuffle tree, and the pair's partial coefficients part[row + j][band]
+// fixed tree (row and half swaps for 16 bands, xor shuffles otherwise), and
+// the pair's partial coefficients part[row + j][band]
 // (j < np) are written.  The partials of a projector are summed over its
 // pairs by k_nl_reduce (tiles ascending, pieces of a pair in order): the
 // result does not depend on scheduling.
