@@ -934,9 +934,14 @@ k_nl_project_tile(const c2<T>* __restrict__ psi, int64_t ld, int nb, int n1, int
                   ai[j] += bj * w[u].y;
                 }
               } else {
+                // sums of j >= np are never written, so only the lane's own
+                // mask selects (a condition on the wave-uniform np becomes a
+                // branch around each load); the four-projector kernel keeps
+                // it in this rarely taken copy, where dropping it spills
 #pragma unroll
                 for (int j = 0; j < MAXP; ++j) {
-                  const T be = (okk[u] && j < np) ? bq[el * np + min(j, np - 1)] : T(0);
+                  const bool use = MAXP == 4 ? okk[u] && j < np : okk[u];
+                  const T be = use ? bq[el * np + min(j, np - 1)] : T(0);
                   ar[j] += be * w[u].x;
                   ai[j] += be * w[u].y;
                 }
